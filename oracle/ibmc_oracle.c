@@ -1,0 +1,692 @@
+/*
+ * ibmc_oracle.c -- plain, slow, obviously-correct CPU oracle.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke entry and the
+ * CPU-baseline leg of the benchmark call into this file.  The product path
+ * (the HIP library) never links it, and this file includes no header, table
+ * or helper of that library.
+ *
+ * What it computes, and where the paper defines it:
+ *   - neuron potential u = sum_j w_j * i_j + b              (Sec. II-A, Eq. (1))
+ *   - sigmoid N(u) = 1 / (1 + e^-u)                          (Sec. II-A, Eq. (2))
+ *   - the safety property "the classification of every image in the
+ *     restricted set equals the clean classification"        (Sec. III-C, Eqs. (4)-(5))
+ *     checked with an incrementally growing bound k           (Sec. II-B)
+ *   - sign / value / distance change and the SS, DS, SV, DV
+ *     neuron-pair covers with their coverage literal          (Sec. III-B, Eqs. (6)-(9))
+ *   - Euclidean distance                                     (Sec. III-C, Eq. (3))
+ *
+ * Readings where the paper is silent (the same ones the library documents):
+ *   - integer networks: int8 weights, int32 bias, hidden activation
+ *     a = min(max(floor(u / 2^s), 0), 127)  (ReLU folded into the clamp);
+ *     input activation a0 = pixel value 0..255; logits are the last
+ *     layer's potentials; the label is the lowest index of the maximum.
+ *   - the restricted set at bound k: all images that differ from the clean
+ *     one in exactly k pixels p1 < ... < pk, pixel pj set to
+ *     clamp(x[pj] + D[ij], 0, 255) for a delta index ij.  Points are counted
+ *     as enumerated (duplicates from 0 in D or from clamping included).
+ *   - rank of a point: (number of k-subsets lexicographically before S)
+ *     * |D|^k + the delta indices read as a base-|D| number, i1 most
+ *     significant.
+ *   - sign(0) = 1; value change = no sign change and
+ *     den * max(|a|,|b|) >= num * min(|a|,|b|) with max(|a|,|b|) > 0;
+ *     distance change = no sign change in the whole layer and
+ *     sum (a-b)^2 >= dist_sq_min; the SS first condition is read as a sign
+ *     change of the condition neuron (as in SV); coverage counts neurons
+ *     of the non-input layers.
+ *   - float networks: a0 = x / 256, sigmoid on hidden layers, linear logits,
+ *     evaluated in double.
+ *
+ * Arithmetic: integer potentials are accumulated in int64 and checked against
+ * the int32 range the library promises; float work is done in double.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_E_INVALID (-1)
+#define ORC_E_RANGE (-2)
+#define ORC_E_OOM (-3)
+
+/* ------------------------------------------------------------------------ */
+/* network shapes (the oracle's own flat layout)                            */
+/*   W: layers concatenated, layer l row-major [dims[l+1]][dims[l]]         */
+/*   b: layers concatenated, [dims[l+1]]                                    */
+/*   potentials: layers 1..L concatenated                                   */
+/* ------------------------------------------------------------------------ */
+
+static int64_t total_units(int L, const int32_t *dims) {
+    int64_t t = 0;
+    for (int l = 1; l <= L; ++l) t += dims[l];
+    return t;
+}
+
+static int max_width(int L, const int32_t *dims) {
+    int m = 0;
+    for (int l = 0; l <= L; ++l) if (dims[l] > m) m = dims[l];
+    return m;
+}
+
+/* Integer forward pass of one image (Eq. (1) per neuron, requantised ReLU
+ * between layers).  pot receives every layer's potentials (may be NULL).
+ * Returns ORC_E_RANGE if a potential leaves the int32 range. */
+static int q8_forward(int L, const int32_t *dims, const int8_t *W, const int32_t *b,
+                      const int32_t *shift, const uint8_t *x, int64_t *act_a, int64_t *act_b,
+                      int64_t *pot, int32_t *label, int *top_tie) {
+    int64_t *in = act_a, *out = act_b;
+    for (int i = 0; i < dims[0]; ++i) in[i] = x[i];
+    const int8_t *w = W;
+    const int32_t *bb = b;
+    int64_t po = 0;
+    for (int l = 1; l <= L; ++l) {
+        int nin = dims[l - 1], nout = dims[l];
+        for (int j = 0; j < nout; ++j) {
+            int64_t u = bb[j];
+            const int8_t *row = w + (int64_t)j * nin;
+            for (int i = 0; i < nin; ++i) u += (int64_t)row[i] * in[i];
+            if (u > INT32_MAX || u < INT32_MIN) return ORC_E_RANGE;
+            if (pot) pot[po + j] = u;
+            if (l < L) {
+                /* floor(u / 2^s), then clamp to [0, 127] */
+                int64_t d = (int64_t)1 << shift[l - 1];
+                int64_t q = u / d;
+                if (u % d != 0 && u < 0) q -= 1;   /* C division truncates toward zero */
+                if (q < 0) q = 0;
+                if (q > 127) q = 127;
+                out[j] = q;
+            } else {
+                out[j] = u;
+            }
+        }
+        po += nout;
+        w += (int64_t)nout * nin;
+        bb += nout;
+        int64_t *t = in; in = out; out = t;
+    }
+    /* label: lowest index attaining the maximum logit */
+    int nc = dims[L];
+    int best = 0;
+    for (int j = 1; j < nc; ++j) if (in[j] > in[best]) best = j;
+    if (label) *label = best;
+    if (top_tie) {
+        int cnt = 0;
+        for (int j = 0; j < nc; ++j) cnt += (in[j] == in[best]);
+        *top_tie = cnt > 1;
+    }
+    return ORC_OK;
+}
+
+int orc_q8_forward(int L, const int32_t *dims, const int8_t *W, const int32_t *b,
+                   const int32_t *shift, const uint8_t *x, int64_t *pot, int32_t *label) {
+    if (L < 1 || !dims || !W || !b || !x) return ORC_E_INVALID;
+    int mw = max_width(L, dims);
+    int64_t *a = malloc(sizeof(int64_t) * mw), *c = malloc(sizeof(int64_t) * mw);
+    if (!a || !c) { free(a); free(c); return ORC_E_OOM; }
+    int rc = q8_forward(L, dims, W, b, shift, x, a, c, pot, label, NULL);
+    free(a); free(c);
+    return rc;
+}
+
+/* Double-precision forward of the float network (Eq. (2) on hidden layers). */
+static void f64_forward(int L, const int32_t *dims, const double *W, const double *b,
+                        const uint8_t *x, double *act_a, double *act_b, double *pot,
+                        int32_t *label, double *margin, double *top) {
+    double *in = act_a, *out = act_b;
+    for (int i = 0; i < dims[0]; ++i) in[i] = (double)x[i] / 256.0;
+    const double *w = W, *bb = b;
+    int64_t po = 0;
+    for (int l = 1; l <= L; ++l) {
+        int nin = dims[l - 1], nout = dims[l];
+        for (int j = 0; j < nout; ++j) {
+            double u = bb[j];
+            const double *row = w + (int64_t)j * nin;
+            for (int i = 0; i < nin; ++i) u += row[i] * in[i];
+            if (pot) pot[po + j] = u;
+            out[j] = (l < L) ? 1.0 / (1.0 + exp(-u)) : u;
+        }
+        po += nout;
+        w += (int64_t)nout * nin;
+        bb += nout;
+        double *t = in; in = out; out = t;
+    }
+    int nc = dims[L];
+    int best = 0;
+    for (int j = 1; j < nc; ++j) if (in[j] > in[best]) best = j;
+    double second = -INFINITY;
+    for (int j = 0; j < nc; ++j) if (j != best && in[j] > second) second = in[j];
+    if (label) *label = best;
+    if (margin) *margin = (nc > 1) ? in[best] - second : INFINITY;
+    if (top) *top = in[best];
+}
+
+int orc_f64_forward(int L, const int32_t *dims, const double *W, const double *b,
+                    const uint8_t *x, double *pot, int32_t *label, double *margin) {
+    if (L < 1 || !dims || !W || !b || !x) return ORC_E_INVALID;
+    int mw = max_width(L, dims);
+    double *a = malloc(sizeof(double) * mw), *c = malloc(sizeof(double) * mw);
+    if (!a || !c) { free(a); free(c); return ORC_E_OOM; }
+    f64_forward(L, dims, W, b, x, a, c, pot, label, margin, NULL);
+    free(a); free(c);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* counting and decoding points                                              */
+/* ------------------------------------------------------------------------ */
+
+/* binomial coefficient by the multiplicative recurrence (exact while it fits) */
+static int64_t binom(int64_t n, int64_t k) {
+    if (k < 0 || n < 0 || k > n) return 0;
+    if (k > n - k) k = n - k;
+    __int128 r = 1;
+    for (int64_t i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return (int64_t)r;
+}
+
+static int64_t ipow(int64_t a, int e) {
+    int64_t r = 1;
+    for (int i = 0; i < e; ++i) r *= a;
+    return r;
+}
+
+/* Number of points at bound k: the k-subsets of the n pixels times the
+ * |D|^k delta choices. */
+int64_t orc_points(int n, int m, int k) {
+    if (k < 0 || k > n) return 0;
+    return binom(n, k) * ipow(m, k);
+}
+
+/* Decode a rank at bound k into its pixels and delta indices.  The subset
+ * part is found by walking the lexicographic order: the k-subsets whose
+ * first element is q number C(n-1-q, k-1); skip whole blocks until the rank
+ * falls inside one, then recurse on the remaining elements. */
+int orc_decode(int n, int m, int k, int64_t rank, int32_t *pix, int32_t *didx) {
+    if (k < 0 || k > n || m < 1) return ORC_E_INVALID;
+    int64_t md = ipow(m, k);
+    int64_t total = binom(n, k) * md;
+    if (rank < 0 || rank >= total) return ORC_E_INVALID;
+    int64_t srank = rank / md, drank = rank % md;
+    for (int j = k - 1; j >= 0; --j) { didx[j] = (int32_t)(drank % m); drank /= m; }
+    int q = 0;
+    for (int j = 0; j < k; ++j) {
+        for (;; ++q) {
+            int64_t block = binom(n - 1 - q, k - 1 - j);
+            if (srank < block) break;
+            srank -= block;
+        }
+        pix[j] = q++;
+    }
+    return ORC_OK;
+}
+
+/* Apply a point to a copy of the clean image. */
+static void apply_point(const uint8_t *x, int n, const int16_t *D, int k, const int32_t *pix,
+                        const int32_t *didx, uint8_t *xp) {
+    memcpy(xp, x, (size_t)n);
+    for (int j = 0; j < k; ++j) {
+        int v = (int)x[pix[j]] + (int)D[didx[j]];
+        if (v < 0) v = 0;
+        if (v > 255) v = 255;
+        xp[pix[j]] = (uint8_t)v;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* exhaustive check (Sec. II-B bound loop around the Sec. III-C property)    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t *k; int64_t *rank; int32_t *label; double *margin;
+    int64_t n, cap;
+} rec_list;
+
+static int rec_push(rec_list *r, int32_t k, int64_t rank, int32_t label, double margin) {
+    if (r->n == r->cap) {
+        int64_t nc = r->cap ? r->cap * 2 : 64;
+        int32_t *a = realloc(r->k, sizeof(int32_t) * nc);
+        if (!a) return ORC_E_OOM;
+        r->k = a;
+        int64_t *bq = realloc(r->rank, sizeof(int64_t) * nc);
+        if (!bq) return ORC_E_OOM;
+        r->rank = bq;
+        int32_t *c = realloc(r->label, sizeof(int32_t) * nc);
+        if (!c) return ORC_E_OOM;
+        r->label = c;
+        double *d = realloc(r->margin, sizeof(double) * nc);
+        if (!d) return ORC_E_OOM;
+        r->margin = d;
+        r->cap = nc;
+    }
+    r->k[r->n] = k; r->rank[r->n] = rank; r->label[r->n] = label; r->margin[r->n] = margin;
+    r->n++;
+    return ORC_OK;
+}
+
+static void rec_free(rec_list *r) { free(r->k); free(r->rank); free(r->label); free(r->margin); }
+
+/* Advance a k-subset (strictly increasing) to its lexicographic successor
+ * whose first element stays `first`; returns 0 when exhausted. */
+static int next_subset_tail(int32_t *pix, int k, int n) {
+    for (int j = k - 1; j >= 1; --j) {
+        if (pix[j] < n - (k - j)) {
+            pix[j]++;
+            for (int t = j + 1; t < k; ++t) pix[t] = pix[t - 1] + 1;
+            return 1;
+        }
+    }
+    return 0;
+}
+
+static int next_digits(int32_t *d, int k, int m) {
+    for (int j = k - 1; j >= 0; --j) {
+        if (++d[j] < m) return 1;
+        d[j] = 0;
+    }
+    return 0;
+}
+
+typedef struct {
+    int is_float;
+    int L;
+    const int32_t *dims;
+    const int8_t *Wq; const int32_t *bq; const int32_t *shift;
+    const double *Wf; const double *bf;
+    double tie_rel;   /* float only: flag when margin <= tie_rel * max(1, |top|) */
+} net_ref;
+
+/* Evaluate one image; returns label, exact-tie flag (int) or near-tie flag (float). */
+static int eval_image(const net_ref *nr, const uint8_t *xp, void *sa, void *sb,
+                      int32_t *label, int *tie, double *margin) {
+    if (!nr->is_float) {
+        *margin = 0.0;
+        return q8_forward(nr->L, nr->dims, nr->Wq, nr->bq, nr->shift, xp, sa, sb, NULL, label, tie);
+    }
+    double top;
+    f64_forward(nr->L, nr->dims, nr->Wf, nr->bf, xp, sa, sb, NULL, label, margin, &top);
+    double scale = fabs(top) > 1.0 ? fabs(top) : 1.0;
+    *tie = *margin <= nr->tie_rel * scale;
+    return ORC_OK;
+}
+
+/* Enumerate bound k with first pixel `first`.  Ranks of these points form the
+ * contiguous range starting at base_rank, visited in increasing order. */
+static int enum_first(const net_ref *nr, const uint8_t *x, const int16_t *D, int m, int k,
+                      int first, int64_t base_rank, int32_t clean, rec_list *cex, rec_list *ties,
+                      int64_t *n_ties, uint8_t *xp, void *sa, void *sb) {
+    int n = nr->dims[0];
+    int32_t pix[64], dig[64];
+    pix[0] = first;
+    for (int j = 1; j < k; ++j) pix[j] = first + j;
+    int64_t rank = base_rank;
+    do {
+        for (int j = 0; j < k; ++j) dig[j] = 0;
+        do {
+            apply_point(x, n, D, k, pix, dig, xp);
+            int32_t lab; int tie; double margin;
+            int rc = eval_image(nr, xp, sa, sb, &lab, &tie, &margin);
+            if (rc) return rc;
+            if (lab != clean) {
+                rc = rec_push(cex, k, rank, lab, margin);
+                if (rc) return rc;
+            }
+            if (tie) {
+                (*n_ties)++;
+                if (ties) { rc = rec_push(ties, k, rank, lab, margin); if (rc) return rc; }
+            }
+            rank++;
+        } while (next_digits(dig, k, m));
+    } while (k > 1 && next_subset_tail(pix, k, n));
+    return ORC_OK;
+}
+
+/* Shared driver of the integer and the float check. */
+static int check_impl(const net_ref *nr, const uint8_t *x, const int16_t *D, int m,
+                      int k_min, int k_max, int k_step, int stop_at_first, int64_t cap,
+                      int64_t *points, int64_t *cex_count, int64_t *tie_count,
+                      int32_t *clean_label, int32_t *first_unsafe_k,
+                      int32_t *out_k, int64_t *out_rank, int32_t *out_label,
+                      int64_t *n_out, int64_t tie_cap, int32_t *tie_k, int64_t *tie_rank,
+                      double *tie_margin, int64_t *n_tie_out, int nthreads) {
+    int n = nr->dims[0];
+    if (m < 1 || k_min < 0 || k_max < k_min || k_step < 1 || k_max > n || k_max > 64)
+        return ORC_E_INVALID;
+    int mw = max_width(nr->L, nr->dims);
+    size_t elt = nr->is_float ? sizeof(double) : sizeof(int64_t);
+    void *sa = malloc(elt * mw), *sb = malloc(elt * mw);
+    if (!sa || !sb) { free(sa); free(sb); return ORC_E_OOM; }
+    int32_t clean; int tie0; double mg0;
+    int rc = eval_image(nr, x, sa, sb, &clean, &tie0, &mg0);
+    free(sa); free(sb);
+    if (rc) return rc;
+    *clean_label = clean;
+    *first_unsafe_k = -1;
+    int64_t written = 0, tie_written = 0;
+    if (n_tie_out) *n_tie_out = 0;
+    int level = 0;
+    for (int k = k_min; k <= k_max; k += k_step, ++level) {
+        points[level] = orc_points(n, m, k);
+        cex_count[level] = 0;
+        tie_count[level] = 0;
+        if (k == 0) {
+            /* the empty perturbation is the clean image itself */
+            tie_count[level] = tie0;
+            continue;
+        }
+        int64_t md = ipow(m, k);
+        rec_list *lists = calloc((size_t)n, sizeof(rec_list));
+        rec_list *tlists = calloc((size_t)n, sizeof(rec_list));
+        int64_t *nties = calloc((size_t)n, sizeof(int64_t));
+        int err = 0;
+        if (!lists || !tlists || !nties) { free(lists); free(tlists); free(nties); return ORC_E_OOM; }
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
+        {
+            uint8_t *xp = malloc((size_t)n);
+            void *ta = malloc(elt * mw), *tb = malloc(elt * mw);
+#pragma omp for schedule(dynamic, 1)
+            for (int first = 0; first <= n - k; ++first) {
+                if (!xp || !ta || !tb) { err = ORC_E_OOM; continue; }
+                /* subsets starting below `first` come first in lexicographic order */
+                int64_t before = 0;
+                for (int q = 0; q < first; ++q) before += binom(n - 1 - q, k - 1);
+                int r = enum_first(nr, x, D, m, k, first, before * md, clean, &lists[first],
+                                   tie_k ? &tlists[first] : NULL, &nties[first],
+                                   xp, ta, tb);
+                if (r) err = r;
+            }
+            free(xp); free(ta); free(tb);
+        }
+        for (int first = 0; first < n && !err; ++first) {
+            rec_list *r = &lists[first];
+            for (int64_t i = 0; i < r->n; ++i) {
+                if (written < cap) {
+                    out_k[written] = r->k[i]; out_rank[written] = r->rank[i]; out_label[written] = r->label[i];
+                }
+                written++;
+            }
+            cex_count[level] += r->n;
+            tie_count[level] += nties[first];
+            rec_list *t = &tlists[first];
+            for (int64_t i = 0; i < t->n; ++i) {
+                if (tie_written < tie_cap) {
+                    tie_k[tie_written] = t->k[i]; tie_rank[tie_written] = t->rank[i];
+                    if (tie_margin) tie_margin[tie_written] = t->margin[i];
+                }
+                tie_written++;
+            }
+        }
+        for (int first = 0; first < n; ++first) { rec_free(&lists[first]); rec_free(&tlists[first]); }
+        free(lists); free(tlists); free(nties);
+        if (err) return err;
+        if (cex_count[level] > 0 && *first_unsafe_k < 0) *first_unsafe_k = k;
+        if (stop_at_first && cex_count[level] > 0) { ++level; break; }
+    }
+    *n_out = written;
+    if (n_tie_out) *n_tie_out = tie_written;
+    return level;  /* number of levels evaluated (>= 0) */
+}
+
+/* Integer check.  Arrays indexed by level have room for the number of levels
+ * k_min, k_min+k_step, ... <= k_max.  Counterexamples (k, rank, new label)
+ * come out sorted by (k, rank); at most `cap` are written, n_out receives the
+ * exact total.  Exact top-2 logit ties are counted per level.
+ * Returns the number of levels evaluated, or a negative error. */
+int orc_q8_check(int L, const int32_t *dims, const int8_t *W, const int32_t *b,
+                 const int32_t *shift, const uint8_t *x, const int16_t *D, int m,
+                 int k_min, int k_max, int k_step, int stop_at_first, int64_t cap,
+                 int64_t *points, int64_t *cex_count, int64_t *tie_count,
+                 int32_t *clean_label, int32_t *first_unsafe_k,
+                 int32_t *out_k, int64_t *out_rank, int32_t *out_label, int64_t *n_out,
+                 int nthreads) {
+    if (L < 1 || !dims || !W || !b || !x || !D) return ORC_E_INVALID;
+    net_ref nr = {0, L, dims, W, b, shift, NULL, NULL, 0.0};
+    return check_impl(&nr, x, D, m, k_min, k_max, k_step, stop_at_first, cap, points, cex_count,
+                      tie_count, clean_label, first_unsafe_k, out_k, out_rank, out_label, n_out,
+                      0, NULL, NULL, NULL, NULL, nthreads);
+}
+
+/* Float (double-evaluated) check with near-tie flags: a point is flagged when
+ * the gap between its two largest logits is <= tie_rel * max(1, |largest|). */
+int orc_f64_check(int L, const int32_t *dims, const double *W, const double *b,
+                  const uint8_t *x, const int16_t *D, int m,
+                  int k_min, int k_max, int k_step, int stop_at_first, int64_t cap,
+                  double tie_rel, int64_t *points, int64_t *cex_count, int64_t *tie_count,
+                  int32_t *clean_label, int32_t *first_unsafe_k,
+                  int32_t *out_k, int64_t *out_rank, int32_t *out_label, int64_t *n_out,
+                  int64_t tie_cap, int32_t *tie_k, int64_t *tie_rank, double *tie_margin,
+                  int64_t *n_tie_out, int nthreads) {
+    if (L < 1 || !dims || !W || !b || !x || !D) return ORC_E_INVALID;
+    net_ref nr = {1, L, dims, NULL, NULL, NULL, W, b, tie_rel};
+    return check_impl(&nr, x, D, m, k_min, k_max, k_step, stop_at_first, cap, points, cex_count,
+                      tie_count, clean_label, first_unsafe_k, out_k, out_rank, out_label, n_out,
+                      tie_cap, tie_k, tie_rank, tie_margin, n_tie_out, nthreads);
+}
+
+/* Replay / sample: decode each (k, rank), build the perturbed image and run
+ * the integer forward.  logits (nullable) receives dims[L] values per point. */
+int orc_q8_eval_points(int L, const int32_t *dims, const int8_t *W, const int32_t *b,
+                       const int32_t *shift, const uint8_t *x, const int16_t *D, int m,
+                       const int32_t *ks, const int64_t *ranks, int64_t npts,
+                       int32_t *labels, int64_t *logits, int nthreads) {
+    if (L < 1 || !dims || !W || !b || !x || !D || npts < 0) return ORC_E_INVALID;
+    int n = dims[0], mw = max_width(L, dims);
+    int64_t U = total_units(L, dims);
+    int err = 0;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
+    {
+        uint8_t *xp = malloc((size_t)n);
+        int64_t *sa = malloc(sizeof(int64_t) * mw), *sb = malloc(sizeof(int64_t) * mw);
+        int64_t *pot = malloc(sizeof(int64_t) * U);
+        int32_t pix[64], dig[64];
+#pragma omp for schedule(static)
+        for (int64_t t = 0; t < npts; ++t) {
+            if (!xp || !sa || !sb || !pot) { err = ORC_E_OOM; continue; }
+            if (ks[t] > 64 || orc_decode(n, m, ks[t], ranks[t], pix, dig)) { err = ORC_E_INVALID; continue; }
+            apply_point(x, n, D, ks[t], pix, dig, xp);
+            int r = q8_forward(L, dims, W, b, shift, xp, sa, sb, pot, &labels[t], NULL);
+            if (r) { err = r; continue; }
+            if (logits) memcpy(&logits[t * dims[L]], &pot[U - dims[L]], sizeof(int64_t) * dims[L]);
+        }
+        free(xp); free(sa); free(sb); free(pot);
+    }
+    return err;
+}
+
+int orc_f64_eval_points(int L, const int32_t *dims, const double *W, const double *b,
+                        const uint8_t *x, const int16_t *D, int m,
+                        const int32_t *ks, const int64_t *ranks, int64_t npts,
+                        int32_t *labels, double *logits, double *margins, int nthreads) {
+    if (L < 1 || !dims || !W || !b || !x || !D || npts < 0) return ORC_E_INVALID;
+    int n = dims[0], mw = max_width(L, dims);
+    int64_t U = total_units(L, dims);
+    int err = 0;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
+    {
+        uint8_t *xp = malloc((size_t)n);
+        double *sa = malloc(sizeof(double) * mw), *sb = malloc(sizeof(double) * mw);
+        double *pot = malloc(sizeof(double) * U);
+        int32_t pix[64], dig[64];
+#pragma omp for schedule(static)
+        for (int64_t t = 0; t < npts; ++t) {
+            if (!xp || !sa || !sb || !pot) { err = ORC_E_OOM; continue; }
+            if (ks[t] > 64 || orc_decode(n, m, ks[t], ranks[t], pix, dig)) { err = ORC_E_INVALID; continue; }
+            apply_point(x, n, D, ks[t], pix, dig, xp);
+            double mg;
+            f64_forward(L, dims, W, b, xp, sa, sb, pot, &labels[t], &mg, NULL);
+            if (margins) margins[t] = mg;
+            if (logits) memcpy(&logits[t * dims[L]], &pot[U - dims[L]], sizeof(double) * dims[L]);
+        }
+        free(xp); free(sa); free(sb); free(pot);
+    }
+    return err;
+}
+
+/* ------------------------------------------------------------------------ */
+/* coverage (Sec. III-B)                                                     */
+/* ------------------------------------------------------------------------ */
+
+enum { ORC_SS = 0, ORC_DS = 1, ORC_SV = 2, ORC_DV = 3 };
+
+static int64_t iabs64(int64_t v) { return v < 0 ? -v : v; }
+
+/* Literal evaluation of one criterion over every adjacent-layer neuron pair
+ * and every input pair.  widths[0..nl) are the widths of the non-input
+ * layers; pot1/pot2 hold, per input pair, all their potentials
+ * concatenated.  bits: pair (l, i, j) is bit off_l + i * widths[l+1] + j,
+ * off_l = sum over earlier blocks of widths[q] * widths[q+1]; bit t lives in
+ * word t / 64 at position t % 64.  counts = {covered pairs, total pairs,
+ * covered neurons, total neurons}. */
+int orc_coverage(int nl, const int32_t *widths, const int64_t *pot1, const int64_t *pot2,
+                 int64_t n_pairs, int criterion, int64_t dist_sq_min, int32_t rnum, int32_t rden,
+                 double P, uint64_t *bits, int64_t *counts, double *fraction, int32_t *literal) {
+    if (nl < 1 || !widths || n_pairs < 0 || criterion < 0 || criterion > 3 || rnum < 1 || rden < 1)
+        return ORC_E_INVALID;
+    int64_t U = 0, total_pairs = 0;
+    int64_t off[64], uoff[64];
+    if (nl > 63) return ORC_E_INVALID;
+    for (int l = 0; l < nl; ++l) {
+        uoff[l] = U;
+        U += widths[l];
+        off[l] = total_pairs;
+        if (l + 1 < nl) total_pairs += (int64_t)widths[l] * widths[l + 1];
+    }
+    int64_t nwords = (total_pairs + 63) / 64;
+    memset(bits, 0, sizeof(uint64_t) * (size_t)(nwords ? nwords : 1));
+    int mw = 0;
+    for (int l = 0; l < nl; ++l) if (widths[l] > mw) mw = widths[l];
+    unsigned char *sc = malloc((size_t)U), *vc = malloc((size_t)U);
+    if (!sc || !vc) { free(sc); free(vc); return ORC_E_OOM; }
+    for (int64_t t = 0; t < n_pairs; ++t) {
+        const int64_t *a = pot1 + t * U, *c = pot2 + t * U;
+        int nsc[64], dc[64];
+        for (int l = 0; l < nl; ++l) {
+            nsc[l] = 0;
+            __int128 dist = 0;
+            for (int i = 0; i < widths[l]; ++i) {
+                int64_t x1 = a[uoff[l] + i], x2 = c[uoff[l] + i];
+                int s1 = x1 >= 0, s2 = x2 >= 0;          /* sign(0) = 1 */
+                sc[uoff[l] + i] = s1 != s2;
+                nsc[l] += s1 != s2;
+                int64_t hi = iabs64(x1) > iabs64(x2) ? iabs64(x1) : iabs64(x2);
+                int64_t lo = iabs64(x1) > iabs64(x2) ? iabs64(x2) : iabs64(x1);
+                vc[uoff[l] + i] = (s1 == s2) && hi > 0 && (int64_t)rden * hi >= (int64_t)rnum * lo;
+                __int128 d = (__int128)x1 - x2;
+                dist += d * d;
+            }
+            dc[l] = nsc[l] == 0 && dist >= (__int128)dist_sq_min;
+        }
+        for (int l = 0; l + 1 < nl; ++l) {
+            for (int i = 0; i < widths[l]; ++i) {
+                for (int j = 0; j < widths[l + 1]; ++j) {
+                    int cond_sign = sc[uoff[l] + i] && nsc[l] == 1;
+                    int hit;
+                    switch (criterion) {
+                        case ORC_SS: hit = cond_sign && sc[uoff[l + 1] + j]; break;
+                        case ORC_DS: hit = dc[l] && sc[uoff[l + 1] + j]; break;
+                        case ORC_SV: hit = cond_sign && vc[uoff[l + 1] + j]; break;
+                        default:     hit = dc[l] && vc[uoff[l + 1] + j]; break;
+                    }
+                    if (hit) {
+                        int64_t bit = off[l] + (int64_t)i * widths[l + 1] + j;
+                        bits[bit / 64] |= (uint64_t)1 << (bit % 64);
+                    }
+                }
+            }
+        }
+    }
+    /* summary: a neuron is covered when it belongs to at least one covered pair */
+    unsigned char *ncov = calloc((size_t)U, 1);
+    if (!ncov) { free(sc); free(vc); return ORC_E_OOM; }
+    int64_t covered_pairs = 0;
+    for (int l = 0; l + 1 < nl; ++l)
+        for (int i = 0; i < widths[l]; ++i)
+            for (int j = 0; j < widths[l + 1]; ++j) {
+                int64_t bit = off[l] + (int64_t)i * widths[l + 1] + j;
+                if ((bits[bit / 64] >> (bit % 64)) & 1) {
+                    covered_pairs++;
+                    ncov[uoff[l] + i] = 1;
+                    ncov[uoff[l + 1] + j] = 1;
+                }
+            }
+    int64_t covered_neurons = 0;
+    for (int64_t u = 0; u < U; ++u) covered_neurons += ncov[u];
+    counts[0] = covered_pairs; counts[1] = total_pairs;
+    counts[2] = covered_neurons; counts[3] = U;
+    *fraction = U ? (double)covered_neurons / (double)U : 0.0;
+    *literal = *fraction >= P;
+    free(sc); free(vc); free(ncov);
+    return ORC_OK;
+}
+
+/* Euclidean distance of two vectors (Eq. (3)). */
+double orc_euclid(const double *p, const double *q, int64_t n) {
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += (p[i] - q[i]) * (p[i] - q[i]);
+    return sqrt(s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* proposal network: s = w2 . relu(W1 f + b1) + c, weighted logistic loss     */
+/* ------------------------------------------------------------------------ */
+
+static double softplus(double z) { return z > 0 ? z + log1p(exp(-z)) : log1p(exp(z)); }
+
+/* Mean weighted binary cross-entropy over the batch and its gradients.
+ * loss_b = -[pw * y log sigmoid(s) + (1 - y) log(1 - sigmoid(s))]
+ *        =  pw * y * softplus(-s) + (1 - y) * softplus(s).
+ * Shapes: f [B][F], W1 [H][F], b1 [H], w2 [H], c scalar.  Gradients
+ * (nullable) have the parameter shapes; scores (nullable) gets s. */
+int orc_prop_loss_grad(int B, int F, int H, const double *f, const double *y, double pw,
+                       const double *W1, const double *b1, const double *w2, double c,
+                       double *loss, double *gW1, double *gb1, double *gw2, double *gc,
+                       double *scores) {
+    if (B < 0 || F < 1 || H < 1) return ORC_E_INVALID;
+    double *h = malloc(sizeof(double) * H), *hp = malloc(sizeof(double) * H);
+    if (!h || !hp) { free(h); free(hp); return ORC_E_OOM; }
+    if (gW1) memset(gW1, 0, sizeof(double) * H * F);
+    if (gb1) memset(gb1, 0, sizeof(double) * H);
+    if (gw2) memset(gw2, 0, sizeof(double) * H);
+    double tot = 0.0, tc = 0.0;
+    for (int t = 0; t < B; ++t) {
+        const double *ft = f + (int64_t)t * F;
+        double s = c;
+        for (int j = 0; j < H; ++j) {
+            double u = b1[j];
+            for (int i = 0; i < F; ++i) u += W1[(int64_t)j * F + i] * ft[i];
+            hp[j] = u;
+            h[j] = u > 0 ? u : 0.0;
+            s += w2[j] * h[j];
+        }
+        if (scores) scores[t] = s;
+        tot += pw * y[t] * softplus(-s) + (1.0 - y[t]) * softplus(s);
+        /* chain rule: d loss_b / d s = sigmoid(s) (pw y + 1 - y) - pw y */
+        double sig = 1.0 / (1.0 + exp(-s));
+        double g = (sig * (pw * y[t] + 1.0 - y[t]) - pw * y[t]) / (double)B;
+        tc += g;
+        for (int j = 0; j < H; ++j) {
+            if (gw2) gw2[j] += g * h[j];
+            double gh = hp[j] > 0 ? g * w2[j] : 0.0;
+            if (gb1) gb1[j] += gh;
+            if (gW1) for (int i = 0; i < F; ++i) gW1[(int64_t)j * F + i] += gh * ft[i];
+        }
+    }
+    if (loss) *loss = B ? tot / B : 0.0;
+    if (gc) *gc = tc;
+    free(h); free(hp);
+    return ORC_OK;
+}
+
+/* One Adam step (Kingma & Ba) on n parameters; t is the 1-based step count. */
+void orc_adam_step(int64_t n, double *theta, const double *g, double *mom, double *vel, int t,
+                   double lr, double beta1, double beta2, double eps) {
+    double c1 = 1.0 - pow(beta1, t), c2 = 1.0 - pow(beta2, t);
+    for (int64_t i = 0; i < n; ++i) {
+        mom[i] = beta1 * mom[i] + (1.0 - beta1) * g[i];
+        vel[i] = beta2 * vel[i] + (1.0 - beta2) * g[i] * g[i];
+        theta[i] -= lr * (mom[i] / c1) / (sqrt(vel[i] / c2) + eps);
+    }
+}
