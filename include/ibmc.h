@@ -1,0 +1,369 @@
+/*
+ * ibmc.h -- C ABI of the MI355X (gfx950) library for exhaustive, incrementally
+ * bounded checking of quantized multi-layer perceptrons and for their
+ * neuron-pair coverage criteria.
+ *
+ * The method follows Sena et al., "Incremental Bounded Model Checking of
+ * Artificial Neural Networks in CUDA" (arXiv 1907.12933):
+ *   - network: neuron potential u = sum_j w_j i_j + b (Sec. II-A, Eq. (1));
+ *     the sigmoid variant applies N(u) = 1 / (1 + e^-u) (Sec. II-A, Eq. (2));
+ *   - safety property: every image of the restricted set keeps the clean
+ *     image's classification; a violation is a counterexample
+ *     (Sec. III-C, Eqs. (4)-(5));
+ *   - incremental bound: the check is repeated for k = k_min, k_min+k_step,
+ *     ... (Sec. II-B, including the increment granularity);
+ *   - coverage: SS / DS / SV / DV neuron-pair covers and the covered-neuron
+ *     literal (Sec. III-B, Eqs. (6)-(9)).
+ *
+ * The paper restricts images to a Euclidean ball around the clean image and
+ * solves for a violating one symbolically.  Here the restricted set at bound k
+ * is finite and enumerated: every image that differs from the clean image x in
+ * exactly k pixels p1 < ... < pk, pixel pj becoming clamp(x[pj] + D[ij], 0, 255)
+ * for a delta index ij into the caller's delta set D.  It holds
+ * C(n, k) * |D|^k points, counted as enumerated (a zero delta or a clamp may
+ * make two points the same image).  A point is named by (k, rank) with
+ *   rank = (number of k-subsets of [0, n) lexicographically before
+ *           {p1 < ... < pk}) * |D|^k + sum_j ij * |D|^(k-j),
+ * i.e. subsets in lexicographic order, then the delta indices as a base-|D|
+ * number with i1 most significant.
+ *
+ * Integer networks (IBMC_ACT_RELU_Q8): int8 weights, int32 biases, input
+ * activation = pixel value 0..255; hidden activation
+ * a = min(max(floor(u / 2^s), 0), 127) with a per-layer shift s (ReLU folded
+ * into the clamp); the logits are the last layer's potentials; the label is
+ * the lowest index attaining the largest logit.  Every potential must fit
+ * int32: ibmc_load_mlp rejects a network whose worst case
+ * sum_i |W[j][i]| * max_input + |b[j]| reaches 2^31 (IBMC_E_RANGE).  The
+ * integer path is exact.
+ *
+ * Float networks (IBMC_ACT_SIGMOID_F32): float32 weights and biases, input
+ * activation x / 256, sigmoid on hidden layers, linear logits, lowest-index
+ * argmax.  Evaluated in float32; points whose two largest logits are within
+ * near_tie_rel * max(1, |largest|) are reported as near ties.
+ *
+ * Conventions
+ *   - Every call returns an ibmc_status: 0 = IBMC_OK, > 0 a warning, < 0 an
+ *     error.  After an error, ibmc_last_error() returns a message for the
+ *     calling thread.  No C++ exception crosses this boundary.
+ *   - Host pointers are caller-owned and only read or written during the
+ *     call.  Calls ending in _dev take device pointers (allocated by the
+ *     caller on the context's device) for the bulk inputs; summaries and
+ *     counterexample records are always written to host memory.
+ *   - The library owns the objects behind ibmc_ctx, ibmc_mlp and
+ *     ibmc_proposer.  ibmc_load_mlp copies the weights.
+ *   - A context wraps one device and one HIP stream (the caller's or its
+ *     own).  A context is not thread-safe; use one per thread.  Calls are
+ *     synchronous with respect to the host: when a call returns, its results
+ *     are in host memory.
+ *   - Counterexamples and near ties come back sorted by (property, k, rank),
+ *     whatever order the device found them in.
+ */
+#ifndef IBMC_H
+#define IBMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ibmc_status;
+
+#define IBMC_OK 0
+#define IBMC_W_TRUNCATED 1      /* more records than capacity; totals stay exact */
+#define IBMC_E_INVALID (-1)     /* bad argument, size or null pointer */
+#define IBMC_E_RANGE (-2)       /* a potential could leave int32 */
+#define IBMC_E_HIP (-3)         /* a HIP runtime call failed */
+#define IBMC_E_OOM (-4)         /* device or host allocation failed */
+#define IBMC_E_ABORTED (-5)     /* stopped by ibmc_abort before completion */
+#define IBMC_E_UNIMPL (-6)      /* shape outside what the kernels support */
+
+#define IBMC_MAX_LEVELS 16
+#define IBMC_MAX_LAYERS 4       /* weight layers (input layer not counted) */
+#define IBMC_MAX_WIDTH 1024     /* widest layer the kernels accept */
+
+typedef struct ibmc_ctx ibmc_ctx;
+typedef struct ibmc_mlp ibmc_mlp;
+typedef struct ibmc_proposer ibmc_proposer;
+
+typedef enum { IBMC_ACT_RELU_Q8 = 0, IBMC_ACT_SIGMOID_F32 = 1 } ibmc_act;
+
+/* The four covers of Sec. III-B.  IBMC_COV_VV names the fourth (the paper's
+ * distance-value cover); it is not a separate criterion. */
+typedef enum { IBMC_COV_SS = 0, IBMC_COV_DS = 1, IBMC_COV_SV = 2, IBMC_COV_DV = 3 } ibmc_criterion;
+#define IBMC_COV_VV IBMC_COV_DV
+
+/* Network description.  dims has n_layers + 1 entries: pixels, hidden
+ * widths..., classes.  W[l] is row-major [dims[l+1]][dims[l]] (int8 for
+ * IBMC_ACT_RELU_Q8, float for IBMC_ACT_SIGMOID_F32); b[l] has dims[l+1]
+ * entries (int32 or float).  shift has n_layers - 1 entries (integer nets
+ * only; each in 0..30).  2 <= n_layers <= IBMC_MAX_LAYERS; every width is
+ * <= IBMC_MAX_WIDTH; the class count is <= 64. */
+typedef struct {
+    int32_t n_layers;
+    const int32_t *dims;
+    int32_t act;
+    const void *const *W;
+    const void *const *b;
+    const int32_t *shift;
+} ibmc_mlp_desc;
+
+/* Options of a check.  k_min >= 0; k_max <= min(n_pixels, 8); k_step >= 1;
+ * at most IBMC_MAX_LEVELS levels.  k = 0 is the clean image itself (one
+ * point, never a counterexample).  stop_at_first: stop after the first level
+ * that has a counterexample (Sec. II-B stops at the first violation).
+ * cex_capacity / near_tie_capacity: room in the caller's record buffers.
+ * near_tie_rel: float nets only; <= 0 selects 4e-5. */
+typedef struct {
+    int32_t k_min, k_max, k_step, stop_at_first;
+    int64_t cex_capacity;
+    int64_t near_tie_capacity;
+    float near_tie_rel;
+    int32_t reserved;
+} ibmc_check_opts;
+
+/* One counterexample (or near tie): decode with ibmc_decode_point.  prop is
+ * the property index in a batch (0 for single-property calls). */
+typedef struct {
+    int32_t prop;
+    int32_t k;
+    int64_t rank;
+    int32_t new_label;
+    int32_t reserved;
+} ibmc_cex;
+
+typedef struct {
+    int32_t clean_label;
+    int32_t first_unsafe_k;              /* -1: no counterexample at any checked level */
+    int32_t n_levels;                    /* levels evaluated */
+    int32_t safe_up_to_k;                /* largest checked k with no counterexample at or below it; -1 if none */
+    int32_t level_k[IBMC_MAX_LEVELS];
+    int64_t points[IBMC_MAX_LEVELS];     /* points enumerated per level */
+    int64_t cex[IBMC_MAX_LEVELS];        /* counterexamples per level (exact) */
+    int64_t ties[IBMC_MAX_LEVELS];       /* integer: exact top-2 logit ties; float: near ties */
+    int64_t points_total;
+    int64_t cex_total;
+    int64_t near_ties_total;
+    double seconds;                      /* device time of the call (HIP events) */
+    double ttfc_seconds;                 /* ordered search: time to the first counterexample; -1 if none */
+    int64_t points_before_first;         /* ordered search: points visited before the first counterexample; -1 if none */
+} ibmc_check_summary;
+
+/* One property of a batch: a network, an image of dims[0] pixels, a delta
+ * set (host memory) and its bounds. */
+typedef struct {
+    const ibmc_mlp *net;
+    const uint8_t *image;                /* host (ibmc_check_batch) or device (ibmc_check_batch_dev) */
+    const int16_t *deltas;               /* host */
+    int32_t n_deltas;
+    int32_t k_min, k_max, k_step;
+} ibmc_property;
+
+/* Coverage parameters (Sec. III-B): value change iff no sign change and
+ * ratio_den * max(|a|,|b|) >= ratio_num * min(|a|,|b|) with max > 0;
+ * distance change of a layer iff no sign change in it and
+ * sum_i (a_i - b_i)^2 >= dist_sq_min; literal iff covered neurons / neurons
+ * >= P.  Zero fields select the defaults 1, 3, 2 and 0.8. */
+typedef struct {
+    int64_t dist_sq_min;
+    int32_t ratio_num, ratio_den;
+    double P;
+} ibmc_cov_params;
+
+typedef struct {
+    int64_t covered_pairs, total_pairs, covered_neurons, total_neurons;
+    double fraction;
+    int32_t literal;
+    int32_t reserved;
+    double seconds;
+} ibmc_cov_summary;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Create a context on `device`.  hip_stream: a hipStream_t to run on, or NULL
+ * for a stream the library creates (default priority). */
+ibmc_status ibmc_ctx_create(int32_t device, void *hip_stream, ibmc_ctx **out);
+void ibmc_ctx_destroy(ibmc_ctx *ctx);
+/* Message of the last error on this thread ("" if none).  Valid until the
+ * next call on this thread. */
+const char *ibmc_last_error(void);
+/* Number of multiprocessors of the context's device (for launch sizing). */
+ibmc_status ibmc_device_info(ibmc_ctx *ctx, int32_t *n_cu, int32_t *arch_major, int32_t *arch_minor);
+
+/* ---- networks ---------------------------------------------------------- */
+
+/* Copy and validate a network; lay it out on the device for the kernels.
+ * Errors: IBMC_E_INVALID (shape), IBMC_E_RANGE (int32 headroom),
+ * IBMC_E_UNIMPL (wider than the kernels accept). */
+ibmc_status ibmc_load_mlp(ibmc_ctx *ctx, const ibmc_mlp_desc *desc, ibmc_mlp **out);
+void ibmc_free_mlp(ibmc_mlp *net);
+
+/* ---- the check (Sec. II-B bound loop around the Sec. III-C property) ---- */
+
+/* Check one image.  image: n_pixels bytes (must equal dims[0]).  delta_set:
+ * n_deltas int16 values (1..64).  cex_buf: room for opts->cex_capacity
+ * records (may be NULL when the capacity is 0); near_tie_buf likewise
+ * (float nets).  Returns IBMC_W_TRUNCATED when a buffer was too small; the
+ * summary's totals stay exact. */
+ibmc_status ibmc_check_property(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *image,
+                                int32_t n_pixels, const int16_t *delta_set, int32_t n_deltas,
+                                const ibmc_check_opts *opts, ibmc_check_summary *out,
+                                ibmc_cex *cex_buf, ibmc_cex *near_tie_buf);
+
+/* Check many properties, possibly over different networks, as one
+ * batch.  outs: one summary per property.  Records of all properties share
+ * cex_buf / near_tie_buf (capacities in opts), tagged with ibmc_cex.prop.
+ * With stop_at_first == 0 all levels of all properties run in one
+ * persistent launch per network shape, captured and replayed as one HIP
+ * graph; with stop_at_first != 0 each level is launched after the previous
+ * level's verdicts are known. */
+ibmc_status ibmc_check_batch(ibmc_ctx *ctx, const ibmc_property *props, int32_t n_props,
+                             const ibmc_check_opts *opts, ibmc_check_summary *outs,
+                             ibmc_cex *cex_buf, ibmc_cex *near_tie_buf);
+/* As ibmc_check_batch, with every props[i].image a device pointer. */
+ibmc_status ibmc_check_batch_dev(ibmc_ctx *ctx, const ibmc_property *props, int32_t n_props,
+                                 const ibmc_check_opts *opts, ibmc_check_summary *outs,
+                                 ibmc_cex *cex_buf, ibmc_cex *near_tie_buf);
+
+/* Stop a running check from another host thread: the kernels poll a flag in
+ * host-mapped memory once per work chunk and drain; the check returns
+ * IBMC_E_ABORTED with the counts reached so far. */
+ibmc_status ibmc_abort(ibmc_ctx *ctx);
+
+/* Decode (k, rank) into ascending pixels[k] and delta indices[k] (host only,
+ * no device work).  IBMC_E_INVALID if rank is outside [0, C(n,k) |D|^k). */
+ibmc_status ibmc_decode_point(int32_t n_pixels, int32_t n_deltas, int32_t k, int64_t rank,
+                              int32_t *pixels, int32_t *delta_idx);
+
+/* Replay records on the device: rebuild each perturbed image, run the full
+ * forward pass (no incremental update) and write its label.  Confirms a
+ * counterexample the way the paper confirms them by re-running the network
+ * outside the checker (Sec. IV-C). */
+ibmc_status ibmc_replay(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *image,
+                        const int16_t *delta_set, int32_t n_deltas, const ibmc_cex *recs,
+                        int64_t n, int32_t *labels_out);
+
+/* Full forward pass of n_images images (host memory, dims[0] bytes each).
+ * potentials (nullable): int32 [n_images][sum of dims[1..L]] for integer
+ * nets, float for float nets; labels (nullable): [n_images]. */
+ibmc_status ibmc_forward(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *images,
+                         int64_t n_images, void *potentials, int32_t *labels);
+
+/* ---- coverage (Sec. III-B) --------------------------------------------- */
+
+/* Coverage of one criterion over n_pairs input pairs (x1[i], x2[i]) of an
+ * integer network: potentials of every non-input layer, sign / value /
+ * distance change, then the OR over pairs of the covered neuron pairs
+ * (l, i, j) between adjacent non-input layers.  covered_bits (nullable):
+ * ceil(total_pairs / 64) words; pair (l, i, j) is bit
+ * off_l + i * h_{l+1} + j (off_l = sum of earlier h_q * h_{q+1}), bit t in
+ * word t / 64 at position t % 64. */
+ibmc_status ibmc_coverage(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *x1,
+                          const uint8_t *x2, int64_t n_pairs, int32_t criterion,
+                          const ibmc_cov_params *params, ibmc_cov_summary *out,
+                          uint64_t *covered_bits);
+/* As ibmc_coverage with x1 / x2 device pointers. */
+ibmc_status ibmc_coverage_dev(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *x1,
+                              const uint8_t *x2, int64_t n_pairs, int32_t criterion,
+                              const ibmc_cov_params *params, ibmc_cov_summary *out,
+                              uint64_t *covered_bits);
+/* All four criteria from one forward pass: outs[4] and (nullable)
+ * covered_bits[4 * words] in SS, DS, SV, DV order. */
+ibmc_status ibmc_coverage_all_dev(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *x1,
+                                  const uint8_t *x2, int64_t n_pairs,
+                                  const ibmc_cov_params *params, ibmc_cov_summary *outs,
+                                  uint64_t *covered_bits);
+/* Coverage from given potentials (host int64 [n_pairs][sum widths]) of
+ * n_layers layers of the given widths, e.g. the paper's worked tables. */
+ibmc_status ibmc_coverage_from_potentials(ibmc_ctx *ctx, int32_t n_layers, const int32_t *widths,
+                                          const int64_t *u1, const int64_t *u2, int64_t n_pairs,
+                                          int32_t criterion, const ibmc_cov_params *params,
+                                          ibmc_cov_summary *out, uint64_t *covered_bits);
+
+/* ---- learned proposal network ------------------------------------------ */
+/* A two-layer scorer s = w2 . relu(W1 f + b1) + c over 32 features of a
+ * candidate (pixel, delta), trained with a positive-weighted logistic loss
+ * and Adam by the library's own bf16 matrix-core kernels.  It only orders the
+ * search: the ordered check still enumerates every point, so its verdicts
+ * and records equal the plain check's. */
+
+#define IBMC_PROP_FEATURES 32
+#define IBMC_PROP_HIDDEN 128
+
+typedef struct {
+    int32_t epochs, batch;
+    float lr, beta1, beta2, eps;
+    float pos_weight;                     /* <= 0: n_negative / n_positive */
+    uint64_t seed;                        /* initialisation and shuffles */
+} ibmc_train_opts;
+
+/* Create a proposer with seeded random weights (fp32 master copy). */
+ibmc_status ibmc_proposer_create(ibmc_ctx *ctx, uint64_t seed, ibmc_proposer **out);
+void ibmc_proposer_free(ibmc_proposer *p);
+/* Read / write the fp32 parameters: W1 [128][32], b1 [128], w2 [128], c [1]
+ * (host arrays, each nullable on get). */
+ibmc_status ibmc_proposer_get(ibmc_proposer *p, float *W1, float *b1, float *w2, float *c);
+ibmc_status ibmc_proposer_set(ibmc_proposer *p, const float *W1, const float *b1,
+                              const float *w2, const float *c);
+/* Candidate features of an image, n_pixels * n_deltas rows of 32 floats
+ * (host), in candidate order (pixel-major, then delta index): row / (rows-1),
+ * col / (cols-1), x / 255, d / dmax, e / dmax with e = clamp(x+d) - x,
+ * L1 and L2 norms of the first-layer weight column normalised by their
+ * maxima over pixels, the L1 norm restricted to first-layer units whose
+ * clean potential is in the requantiser's linear window normalised the same
+ * way, then 1, then zeros. */
+ibmc_status ibmc_proposer_features(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *image,
+                                   int32_t rows, int32_t cols, const int16_t *delta_set,
+                                   int32_t n_deltas, float *features);
+/* One forward/backward pass on a batch (host features [B][32], labels [B]
+ * of 0/1): mean loss and gradients with the parameter shapes (host). */
+ibmc_status ibmc_proposer_grad(ibmc_ctx *ctx, ibmc_proposer *p, const float *features,
+                               const float *labels, int32_t B, float pos_weight, float *loss,
+                               float *gW1, float *gb1, float *gw2, float *gc);
+/* Train on N labelled candidates (host arrays); losses (nullable) receives
+ * the mean loss of each epoch. */
+ibmc_status ibmc_proposer_train(ibmc_ctx *ctx, ibmc_proposer *p, const float *features,
+                                const float *labels, int64_t N, const ibmc_train_opts *opts,
+                                float *losses);
+/* Scores of an image's candidates (host float [n_pixels * n_deltas]). */
+ibmc_status ibmc_proposer_score(ibmc_ctx *ctx, const ibmc_proposer *p, const ibmc_mlp *net,
+                                const uint8_t *image, int32_t rows, int32_t cols,
+                                const int16_t *delta_set, int32_t n_deltas, float *scores);
+
+/* Ordered check of levels k <= 2 (integer nets): level 1 visits candidates by
+ * decreasing score; level 2 visits "shells": candidates sorted c0, c1, ...,
+ * shell t holds the pairs (c_t, c_j), j < t, on distinct pixels, so every
+ * level-2 point is visited once.  p == NULL visits the plain order (level 1
+ * pixel-major, level 2 grouped by the first pixel and its delta).  Work is
+ * handed out in visiting order; the summary's ttfc_seconds and
+ * points_before_first report when the first counterexample was found (host
+ * clock, from the call's start, including scoring and sorting).  The full
+ * enumeration always completes unless opts->stop_at_first is set, in which
+ * case the call returns once the first counterexample is confirmed. */
+ibmc_status ibmc_check_property_ranked(ibmc_ctx *ctx, const ibmc_mlp *net,
+                                       const ibmc_proposer *p, const uint8_t *image,
+                                       int32_t n_pixels, int32_t rows, int32_t cols,
+                                       const int16_t *delta_set, int32_t n_deltas,
+                                       const ibmc_check_opts *opts, ibmc_check_summary *out,
+                                       ibmc_cex *cex_buf);
+
+/* ---- tuning ------------------------------------------------------------ */
+
+/* Time the kernel variants (points per wave, waves per workgroup, weights
+ * staged in LDS or read through L2) for a network on a synthetic image and
+ * remember the fastest for that network shape in the context.  json_out
+ * (nullable, json_cap bytes) receives the measurements as JSON. */
+ibmc_status ibmc_autotune(ibmc_ctx *ctx, const ibmc_mlp *net, int32_t k, int32_t n_deltas,
+                          char *json_out, int64_t json_cap);
+/* Force a variant by its name (as listed by the tuner's JSON); NULL resets
+ * to the built-in choice. */
+ibmc_status ibmc_set_variant(ibmc_ctx *ctx, const ibmc_mlp *net, const char *variant);
+/* Device time of the last enumeration kernel launches of this context, in
+ * seconds, and the number of launches they span (for roofline reporting). */
+ibmc_status ibmc_last_kernel_time(ibmc_ctx *ctx, double *seconds, int32_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IBMC_H */

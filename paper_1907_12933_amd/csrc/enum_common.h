@@ -1,0 +1,206 @@
+// Work decomposition shared by the integer and the float enumeration
+// kernels: a global chunk index maps to (job, segment, chunk in segment);
+// a segment fixes every perturbed element but the last; the last element
+// ranges over the segment's candidates, CH points per chunk.
+#pragma once
+
+#include "ibmc_internal.h"
+
+namespace ibmc {
+
+__device__ __forceinline__ int clamp_pixel(int v) { return min(max(v, 0), 255); }
+
+// Segment cursor: position of a wave in the global chunk order
+// (job, last-prefix pixel q, prefix subset, prefix deltas, chunk).  All its
+// fields are wave-uniform.
+struct Cursor {
+    int job, k, prop, slot, mode, m, n;
+    int q;                 // last prefix pixel (plain k >= 2), -1 for k == 1
+    int pre[kMaxK];        // prefix pixels pre[0..k-2] (pre[k-2] == q)
+    int dg[kMaxK];         // prefix delta indices dg[0..k-2]
+    int64_t shell;         // shell / list modes: shell index
+    int64_t ch, nch;       // chunk inside the segment, chunks per segment
+    int64_t seglen;        // candidates of the last element in this segment
+    int64_t chunk;         // global chunk index
+    int64_t job_end;
+};
+
+template <int CH, class PT>
+__device__ void cursor_job_start(Cursor &c, const PT &P, int job) {
+    const EnumJob &J = P.jobs[job];
+    c.job = job;
+    c.k = J.k;
+    c.prop = J.prop;
+    c.slot = J.slot;
+    c.mode = J.mode;
+    c.m = P.props[J.prop].m;
+    c.n = P.props[J.prop].n;
+    c.job_end = J.chunk_end;
+}
+
+template <int CH>
+__device__ void cursor_set_q(Cursor &c) {
+    c.seglen = (int64_t)(c.n - 1 - c.q) * c.m;
+    c.nch = (c.seglen + CH - 1) / CH;
+}
+
+// Decode global chunk `chunk` from scratch.
+template <int CH, class PT>
+__device__ void cursor_decode(Cursor &c, const PT &P, int64_t chunk) {
+    int lo = 0, hi = P.n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (P.jobs[mid].chunk_begin <= chunk) lo = mid; else hi = mid - 1;
+    }
+    cursor_job_start<CH, PT>(c, P, lo);
+    const EnumJob &J = P.jobs[lo];
+    int64_t r = chunk - J.chunk_begin;
+    c.chunk = chunk;
+    if (c.mode == SEG_LIST1) {
+        c.q = -1; c.shell = 0;
+        c.seglen = (int64_t)c.n * c.m;
+        c.nch = (c.seglen + CH - 1) / CH;
+        c.ch = r;
+        return;
+    }
+    if (c.mode == SEG_SHELL) {
+        // shell_cum[t] = chunks before shell t; shells t >= 1 have t candidates
+        int64_t N1 = (int64_t)c.n * c.m;
+        int64_t a = 1, b = N1 - 1;
+        while (a < b) {
+            const int64_t mid = (a + b + 1) >> 1;
+            if (J.shell_cum[mid] <= r) a = mid; else b = mid - 1;
+        }
+        c.shell = a;
+        c.seglen = a;
+        c.nch = (a + CH - 1) / CH;
+        c.ch = r - J.shell_cum[a];
+        return;
+    }
+    if (c.k == 1) {
+        c.q = -1;
+        c.seglen = (int64_t)c.n * c.m;
+        c.nch = (c.seglen + CH - 1) / CH;
+        c.ch = r;
+        return;
+    }
+    // plain k >= 2: largest q in [k-2, n-2] with qcum[q] <= r
+    int a = c.k - 2, b = c.n - 2;
+    while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (J.qcum[mid] <= r) a = mid; else b = mid - 1;
+    }
+    c.q = a;
+    cursor_set_q<CH>(c);
+    const int64_t rr = r - J.qcum[a];
+    const int64_t seg = rr / c.nch;
+    c.ch = rr % c.nch;
+    int64_t mk1 = 1;
+    for (int j = 0; j < c.k - 1; ++j) mk1 *= c.m;
+    const int64_t combo = seg / mk1;
+    int64_t dig = seg % mk1;
+    for (int j = kMaxK - 1; j >= 0; --j) {
+        if (j < c.k - 1) { c.dg[j] = (int)(dig % c.m); dig /= c.m; }
+    }
+    int tmp[kMaxK];
+    lex_unrank_subset(combo, c.k - 2, c.q, tmp);
+    for (int j = 0; j < kMaxK; ++j)
+        if (j < c.k - 2) c.pre[j] = tmp[j];
+    c.pre[c.k - 2] = c.q;
+}
+
+// Move to the next chunk.  Returns true when the segment (hence the base)
+// changed.
+template <int CH, class PT>
+__device__ bool cursor_next(Cursor &c, const PT &P) {
+    c.chunk++;
+    if (++c.ch < c.nch) return false;
+    c.ch = 0;
+    if (c.chunk >= c.job_end) {
+        if (c.job + 1 < P.n_jobs) cursor_decode<CH, PT>(c, P, c.chunk);
+        return true;
+    }
+    if (c.mode == SEG_SHELL) {
+        c.shell++;
+        c.seglen = c.shell;
+        c.nch = (c.seglen + CH - 1) / CH;
+        return true;
+    }
+    if (c.mode == SEG_LIST1 || c.k == 1) return true;  // single segment: end of job handled above
+    // prefix deltas, last digit fastest
+    for (int j = kMaxK - 1; j >= 0; --j) {
+        if (j < c.k - 1) {
+            if (++c.dg[j] < c.m) return true;
+            c.dg[j] = 0;
+        }
+    }
+    // next (k-2)-subset of [0, q) in lexicographic order
+    const int r = c.k - 2;
+    for (int j = kMaxK - 1; j >= 0; --j) {
+        if (j < r && c.pre[j] < c.q - (r - j)) {
+            c.pre[j]++;
+            for (int t = 0; t < kMaxK; ++t)
+                if (t > j && t < r) c.pre[t] = c.pre[t - 1] + 1;
+            return true;
+        }
+    }
+    // next q
+    c.q++;
+    for (int t = 0; t < kMaxK; ++t)
+        if (t < r) c.pre[t] = t;
+    c.pre[r] = c.q;
+    cursor_set_q<CH>(c);
+    return true;
+}
+
+// Resolve the last element of candidate position o of the current segment.
+// Returns false when o is not a valid point.
+template <class PT>
+__device__ __forceinline__ bool last_element(const Cursor &c, const PT &P, int64_t o,
+                                             int &p, int &i, int &pfirst, int &ifirst) {
+    const EnumJob &J = P.jobs[c.job];
+    if (o >= c.seglen) return false;
+    if (c.mode == SEG_PLAIN) {
+        p = c.q + 1 + (int)(o / c.m);
+        i = (int)(o % c.m);
+        return true;
+    }
+    const int cand = J.order[o];
+    p = cand / c.m;
+    i = cand % c.m;
+    if (c.mode == SEG_SHELL) {
+        const int head = J.order[c.shell];
+        pfirst = head / c.m;
+        ifirst = head % c.m;
+        return p != pfirst;
+    }
+    return true;
+}
+
+// Point rank (see the header) of a point given by its prefix and last element.
+template <class PT>
+__device__ int64_t point_rank(const Cursor &c, const PT &P, int p, int i) {
+    int pix[kMaxK], dig[kMaxK];
+    int kk = c.k;
+    if (c.mode == SEG_PLAIN) {
+        for (int j = 0; j < kMaxK; ++j)
+            if (j < kk - 1) { pix[j] = c.pre[j]; dig[j] = c.dg[j]; }
+        pix[kk - 1] = p;
+        dig[kk - 1] = i;
+    } else if (c.mode == SEG_SHELL) {
+        const int head = P.jobs[c.job].order[c.shell];
+        const int ph = head / c.m, ih = head % c.m;
+        if (ph < p) { pix[0] = ph; dig[0] = ih; pix[1] = p; dig[1] = i; }
+        else { pix[0] = p; dig[0] = i; pix[1] = ph; dig[1] = ih; }
+    } else {
+        pix[0] = p; dig[0] = i;
+    }
+    int64_t d = 0;
+    for (int j = 0; j < kMaxK; ++j)
+        if (j < kk) d = d * c.m + dig[j];
+    int64_t mk = 1;
+    for (int j = 0; j < kk; ++j) mk *= c.m;
+    return lex_rank_subset(pix, kk, c.n) * mk + d;
+}
+
+}  // namespace ibmc

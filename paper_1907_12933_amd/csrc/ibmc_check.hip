@@ -1,0 +1,481 @@
+// The check driver: the incremental bound loop of Sec. II-B around the
+// safety property of Sec. III-C, over one or many properties.  Builds the
+// work plan (jobs of (property, level) and their chunk counts), runs the
+// clean pass and the enumeration kernels, gathers counters and records.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "ibmc_host.h"
+
+namespace ibmc {
+
+std::string shape_key(const ibmc_mlp *m) {
+    std::string s = (m->act == IBMC_ACT_RELU_Q8) ? "q8" : "f32";
+    for (int d : m->dims) s += "_" + std::to_string(d);
+    return s;
+}
+
+static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+static int64_t ipow64(int64_t a, int e) {
+    int64_t r = 1;
+    for (int i = 0; i < e; ++i) r *= a;
+    return r;
+}
+
+// Chunks of a plain level; qcum receives the chunks before each last-prefix
+// pixel q (k >= 2).
+static int64_t plan_plain_level(int n, int m, int k, int CH, std::vector<int64_t> &qcum) {
+    if (k == 1) return ceil_div((int64_t)n * m, CH);
+    qcum.assign(n, 0);
+    const int64_t mk1 = ipow64(m, k - 1);
+    int64_t acc = 0;
+    for (int q = 0; q < n; ++q) {
+        qcum[q] = acc;
+        if (q >= k - 2 && q <= n - 2) acc += binom_small(q, k - 2) * mk1 * ceil_div((int64_t)(n - 1 - q) * m, CH);
+    }
+    return acc;
+}
+
+// Variant choice for an integer network: the tuned one if any, else the
+// widest point tile whose weights fit the LDS budget.
+const EnumVariant *pick_variant(ibmc_ctx *ctx, const ibmc_mlp *net) {
+    int nv = 0;
+    const EnumVariant *vs = enum_variants(&nv);
+    const int L = net->L;
+    const int kb1 = net->qd.H[1] / 64;
+    const int kb2 = (L == 3) ? net->qd.H[2] / 64 : 0;
+    std::string want = net->forced_variant;
+    if (want.empty()) {
+        auto it = ctx->tuned.find(shape_key(net));
+        if (it != ctx->tuned.end()) want = it->second;
+    }
+    if (!want.empty())
+        for (int i = 0; i < nv; ++i)
+            if (want == vs[i].name && vs[i].L == L && vs[i].kb1 == kb1 && vs[i].kb2 == kb2) return &vs[i];
+    const EnumVariant *best = nullptr;
+    for (int i = 0; i < nv; ++i) {
+        const EnumVariant &v = vs[i];
+        if (v.L != L || v.kb1 != kb1 || v.kb2 != kb2) continue;
+        if (enum_lds_bytes(v, net->qd) > 96 * 1024) continue;
+        const int score = (v.wlds ? 100 : 0) + (v.nt == 2 ? 10 : v.nt);
+        if (!best || score > (best->wlds ? 100 : 0) + (best->nt == 2 ? 10 : best->nt)) best = &v;
+    }
+    return best;
+}
+
+struct Level {
+    int prop;
+    int k;
+    int slot;
+};
+
+struct BatchState {
+    std::vector<PropDev> hprops;
+    std::vector<int> level_count;             // levels per property
+    std::vector<std::vector<int>> level_k;    // k per level per property
+    std::vector<int> slot_base;               // first slot of each property
+    int n_slots = 0;
+};
+
+static ibmc_status validate_props(const ibmc_property *props, int32_t n_props, const ibmc_check_opts *o) {
+    if (!props || n_props < 1) return fail(IBMC_E_INVALID, "no properties");
+    if (!o) return fail(IBMC_E_INVALID, "opts is null");
+    if (o->cex_capacity < 0 || o->near_tie_capacity < 0) return fail(IBMC_E_INVALID, "negative capacity");
+    for (int i = 0; i < n_props; ++i) {
+        const ibmc_property &p = props[i];
+        if (!p.net || !p.image || !p.deltas) return fail(IBMC_E_INVALID, "property %d: null net/image/deltas", i);
+        if (p.n_deltas < 1 || p.n_deltas > kMaxDeltas)
+            return fail(IBMC_E_INVALID, "property %d: n_deltas %d outside [1, %d]", i, p.n_deltas, kMaxDeltas);
+        const int n = p.net->dims[0];
+        if (p.k_min < 0 || p.k_max < p.k_min || p.k_step < 1)
+            return fail(IBMC_E_INVALID, "property %d: bad k range %d..%d step %d", i, p.k_min, p.k_max, p.k_step);
+        if (p.k_max > n || p.k_max > kMaxK)
+            return fail(IBMC_E_INVALID, "property %d: k_max %d exceeds min(n=%d, %d)", i, p.k_max, n, kMaxK);
+        int levels = 0;
+        for (int k = p.k_min; k <= p.k_max; k += p.k_step) {
+            ++levels;
+            // points of the level must fit comfortably in int64
+            __int128 pts = (__int128)binom_small(n, k);
+            for (int j = 0; j < k; ++j) pts *= p.n_deltas;
+            if (pts > ((__int128)1 << 56)) return fail(IBMC_E_UNIMPL, "property %d: level %d too large", i, k);
+        }
+        if (levels > IBMC_MAX_LEVELS) return fail(IBMC_E_INVALID, "property %d: %d levels > %d", i, levels, IBMC_MAX_LEVELS);
+        if (p.net->act == IBMC_ACT_RELU_Q8 && p.net->L > 3 && p.k_max >= 1)
+            return fail(IBMC_E_UNIMPL, "property %d: enumeration supports 2 or 3 weight layers", i);
+        if (p.net->act == IBMC_ACT_SIGMOID_F32) {
+            for (int l = 1; l <= p.net->L; ++l)
+                if (p.net->dims[l] > 512) return fail(IBMC_E_UNIMPL, "property %d: float layer wider than 512", i);
+        }
+    }
+    return IBMC_OK;
+}
+
+// Run the given levels (subset of every property's level list) as one
+// launch per network.  level_sel[prop] = level indices to run.
+static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t n_props,
+                              const ibmc_check_opts *o, BatchState &B,
+                              const std::vector<std::vector<int>> &level_sel, bool images_on_device,
+                              std::vector<unsigned long long> &slot_cex, std::vector<unsigned long long> &slot_ties,
+                              std::vector<CexRec> &recs, std::vector<CexRec> &ties, int64_t &rec_total,
+                              int64_t &tie_total, double &kernel_seconds, int &launches) {
+    hipStream_t s = ctx->stream;
+    // group properties by network
+    std::vector<const ibmc_mlp *> nets;
+    std::map<const ibmc_mlp *, std::vector<int>> by_net;
+    for (int i = 0; i < n_props; ++i) {
+        if (level_sel[i].empty()) continue;
+        if (!by_net.count(props[i].net)) nets.push_back(props[i].net);
+        by_net[props[i].net].push_back(i);
+    }
+    // counters: [0] queue, [1] rec_count, [2] first_chunk, [3] tie_count, [4] stop flag (int)
+    //           then slot_cex[n_slots], slot_ties[n_slots]
+    const int64_t n_ctr = 8 + 2 * (int64_t)B.n_slots;
+    IBMC_TRY(ctx->counters.reserve(n_ctr * 8));
+    unsigned long long *ctr = ctx->counters.as<unsigned long long>();
+    const int64_t cap = o->cex_capacity, tcap = o->near_tie_capacity;
+    IBMC_TRY(ctx->recs.reserve((size_t)std::max<int64_t>(cap, 1) * sizeof(CexRec)));
+    IBMC_TRY(ctx->ties.reserve((size_t)std::max<int64_t>(tcap, 1) * sizeof(CexRec)));
+    HIP_OK(launch_fill_u64(ctr, n_ctr, 0ull, s));
+    HIP_OK(launch_fill_u64(ctr + 2, 1, ~0ull, s));  // first_chunk starts at "none"
+    int64_t max_h1 = 64;
+    for (auto *nt : nets) max_h1 = std::max<int64_t>(max_h1, nt->act == IBMC_ACT_RELU_Q8 ? nt->qd.H[1] : nt->dims[1]);
+    IBMC_TRY(ctx->u0.reserve((size_t)n_props * max_h1 * 4));
+    std::vector<int32_t> u0_index(n_props);
+    std::iota(u0_index.begin(), u0_index.end(), 0);
+    IBMC_TRY(ctx->u0_index.upload(u0_index.data(), u0_index.size() * 4, s));
+
+    kernel_seconds = 0.0;
+    launches = 0;
+    for (const ibmc_mlp *net : nets) {
+        const std::vector<int> &ids = by_net[net];
+        const bool q8 = net->act == IBMC_ACT_RELU_Q8;
+        const EnumVariant *v = nullptr;
+        int CH = enum_f32_chunk();
+        if (q8) {
+            v = pick_variant(ctx, net);
+            if (!v) return fail(IBMC_E_UNIMPL, "no enumeration kernel for network %s", shape_key(net).c_str());
+            CH = v->chunk;
+        }
+        // jobs and their chunk plans
+        std::vector<EnumJob> jobs;
+        std::vector<int64_t> qcum_all;
+        std::vector<size_t> qcum_off;
+        int64_t total = 0;
+        for (int pid : ids) {
+            const int n = net->dims[0], m = props[pid].n_deltas;
+            for (int li : level_sel[pid]) {
+                const int k = B.level_k[pid][li];
+                if (k == 0) continue;
+                std::vector<int64_t> qc;
+                const int64_t ch = plan_plain_level(n, m, k, CH, qc);
+                EnumJob J{};
+                J.prop = pid;
+                J.k = k;
+                J.slot = B.slot_base[pid] + li;
+                J.mode = SEG_PLAIN;
+                J.chunk_begin = total;
+                J.chunk_end = total + ch;
+                qcum_off.push_back(k >= 2 ? qcum_all.size() : (size_t)-1);
+                if (k >= 2) qcum_all.insert(qcum_all.end(), qc.begin(), qc.end());
+                total += ch;
+                jobs.push_back(J);
+            }
+        }
+        // clean pass of this network's properties
+        IBMC_TRY(ctx->prop_ids.upload(ids.data(), ids.size() * 4, s));
+        PropDev *dprops = ctx->props.as<PropDev>();
+        if (q8) {
+            HIP_OK(launch_clean_q8(net->qd, dprops, ctx->prop_ids.as<int32_t>(), (int32_t)ids.size(),
+                                   ctx->u0.as<int32_t>(), max_h1, s));
+        } else {
+            HIP_OK(launch_clean_f32(net->fd, dprops, ctx->prop_ids.as<int32_t>(), (int32_t)ids.size(),
+                                    ctx->u0.as<float>(), max_h1, s));
+        }
+        if (jobs.empty() || total == 0) continue;
+        IBMC_TRY(ctx->qcum.reserve(std::max<size_t>(qcum_all.size(), 1) * 8));
+        if (!qcum_all.empty())
+            HIP_OK(hipMemcpyAsync(ctx->qcum.p, qcum_all.data(), qcum_all.size() * 8, hipMemcpyHostToDevice, s));
+        for (size_t j = 0; j < jobs.size(); ++j)
+            jobs[j].qcum = (qcum_off[j] == (size_t)-1) ? nullptr : ctx->qcum.as<int64_t>() + qcum_off[j];
+        IBMC_TRY(ctx->jobs.upload(jobs.data(), jobs.size() * sizeof(EnumJob), s));
+        HIP_OK(launch_fill_u64(ctr, 1, 0ull, s));  // queue restarts for this launch
+        HIP_OK(hipEventRecord(ctx->ek0, s));
+        if (q8) {
+            EnumParams P{};
+            P.net = net->qd;
+            P.jobs = ctx->jobs.as<EnumJob>();
+            P.n_jobs = (int32_t)jobs.size();
+            P.total_chunks = total;
+            P.batch = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, total / (ctx->n_cu * 64)));
+            P.props = dprops;
+            P.queue = ctr + 0;
+            P.rec_count = ctr + 1;
+            P.first_chunk = ctr + 2;
+            P.stop_flag = reinterpret_cast<volatile int32_t *>(ctr + 4);
+            P.abort_host = ctx->flags_dev;
+            P.hit_host = nullptr;
+            P.rec_cap = cap;
+            P.recs = ctx->recs.as<CexRec>();
+            P.slot_cex = ctr + 8;
+            P.slot_ties = ctr + 8 + B.n_slots;
+            P.stop_on_first = 0;
+            int occ = 0;
+            const int64_t lds = enum_lds_bytes(*v, net->qd);
+            HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, v->fn, 256, (size_t)lds));
+            if (occ < 1) return fail(IBMC_E_UNIMPL, "variant %s does not fit (lds %lld)", v->name, (long long)lds);
+            const int64_t grid = std::min<int64_t>((int64_t)ctx->n_cu * occ, std::max<int64_t>(1, total / P.batch));
+            HIP_OK(launch_enum_q8(*v, (int)grid, P, ctx->u0.as<int32_t>(), max_h1, ctx->u0_index.as<int32_t>(), s));
+        } else {
+            FEnumParams P{};
+            P.net = net->fd;
+            P.jobs = ctx->jobs.as<EnumJob>();
+            P.n_jobs = (int32_t)jobs.size();
+            P.total_chunks = total;
+            P.batch = (int32_t)std::max<int64_t>(1, std::min<int64_t>(16, total / (ctx->n_cu * 16)));
+            P.props = dprops;
+            P.u0f = ctx->u0.as<float>();
+            P.u0_stride = (int32_t)max_h1;
+            P.tie_rel = (o->near_tie_rel > 0) ? o->near_tie_rel : 4e-5f;
+            P.queue = ctr + 0;
+            P.rec_count = ctr + 1;
+            P.rec_cap = cap;
+            P.recs = ctx->recs.as<CexRec>();
+            P.tie_count = ctr + 3;
+            P.tie_cap = tcap;
+            P.ties = ctx->ties.as<CexRec>();
+            P.slot_cex = ctr + 8;
+            P.slot_ties = ctr + 8 + B.n_slots;
+            P.stop_flag = reinterpret_cast<volatile int32_t *>(ctr + 4);
+            P.abort_host = ctx->flags_dev;
+            const int64_t grid = std::min<int64_t>((int64_t)ctx->n_cu * 4, std::max<int64_t>(1, total / P.batch));
+            HIP_OK(launch_enum_f32((int)grid, P, ctx->u0_index.as<int32_t>(), s));
+        }
+        HIP_OK(hipEventRecord(ctx->ek1, s));
+        HIP_OK(hipEventSynchronize(ctx->ek1));
+        float ms = 0.f;
+        HIP_OK(hipEventElapsedTime(&ms, ctx->ek0, ctx->ek1));
+        kernel_seconds += ms * 1e-3;
+        launches++;
+    }
+    // gather
+    std::vector<unsigned long long> h(n_ctr);
+    HIP_OK(hipMemcpyAsync(h.data(), ctr, n_ctr * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    rec_total = (int64_t)h[1];
+    tie_total = (int64_t)h[3];
+    slot_cex.assign(h.begin() + 8, h.begin() + 8 + B.n_slots);
+    slot_ties.assign(h.begin() + 8 + B.n_slots, h.begin() + 8 + 2 * B.n_slots);
+    const int64_t nr = std::min(rec_total, cap), nt = std::min(tie_total, tcap);
+    recs.resize(nr);
+    ties.resize(nt);
+    if (nr) HIP_OK(hipMemcpyAsync(recs.data(), ctx->recs.p, nr * sizeof(CexRec), hipMemcpyDeviceToHost, s));
+    if (nt) HIP_OK(hipMemcpyAsync(ties.data(), ctx->ties.p, nt * sizeof(CexRec), hipMemcpyDeviceToHost, s));
+    // clean labels
+    HIP_OK(hipMemcpyAsync(B.hprops.data(), ctx->props.p, n_props * sizeof(PropDev), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (ctx->flags_host[0]) return fail(IBMC_E_ABORTED, "check aborted");
+    return IBMC_OK;
+}
+
+static bool rec_less(const CexRec &a, const CexRec &b) {
+    if (a.prop != b.prop) return a.prop < b.prop;
+    if (a.k != b.k) return a.k < b.k;
+    return a.rank < b.rank;
+}
+
+ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props, int32_t n_props, const ibmc_check_opts *o,
+                             ibmc_check_summary *outs, ibmc_cex *cex_buf, ibmc_cex *tie_buf, bool images_on_device) {
+    clear_error();
+    if (!ctx || !outs) return fail(IBMC_E_INVALID, "null ctx / outs");
+    IBMC_TRY(validate_props(props, n_props, o));
+    if (o->cex_capacity > 0 && !cex_buf) return fail(IBMC_E_INVALID, "cex_buf is null with capacity > 0");
+    if (o->near_tie_capacity > 0 && !tie_buf) return fail(IBMC_E_INVALID, "near_tie_buf is null with capacity > 0");
+    HIP_OK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    ctx->flags_host[0] = 0;
+    ctx->flags_host[1] = 0;
+    HIP_OK(hipEventRecord(ctx->ev0, s));
+
+    BatchState B;
+    B.hprops.resize(n_props);
+    B.level_k.resize(n_props);
+    B.slot_base.resize(n_props);
+    // images to the device
+    std::vector<size_t> img_off(n_props, 0);
+    size_t img_bytes = 0;
+    if (!images_on_device) {
+        for (int i = 0; i < n_props; ++i) {
+            img_off[i] = img_bytes;
+            img_bytes += (size_t)round_up(props[i].net->dims[0], 16);
+        }
+        IBMC_TRY(ctx->images.reserve(img_bytes));
+        std::vector<uint8_t> staging(img_bytes, 0);
+        for (int i = 0; i < n_props; ++i) memcpy(staging.data() + img_off[i], props[i].image, props[i].net->dims[0]);
+        HIP_OK(hipMemcpyAsync(ctx->images.p, staging.data(), img_bytes, hipMemcpyHostToDevice, s));
+        HIP_OK(hipStreamSynchronize(s));
+    }
+    for (int i = 0; i < n_props; ++i) {
+        PropDev &d = B.hprops[i];
+        memset(&d, 0, sizeof(d));
+        d.image = images_on_device ? props[i].image : ctx->images.as<uint8_t>() + img_off[i];
+        d.m = props[i].n_deltas;
+        d.n = props[i].net->dims[0];
+        for (int j = 0; j < d.m; ++j) d.deltas[j] = props[i].deltas[j];
+        B.slot_base[i] = B.n_slots;
+        for (int k = props[i].k_min; k <= props[i].k_max; k += props[i].k_step) B.level_k[i].push_back(k);
+        B.n_slots += (int)B.level_k[i].size();
+    }
+    IBMC_TRY(ctx->props.upload(B.hprops.data(), B.hprops.size() * sizeof(PropDev), s));
+
+    std::vector<std::vector<int>> done_levels(n_props);
+    std::vector<unsigned long long> cex_acc(B.n_slots, 0), ties_acc(B.n_slots, 0);
+    std::vector<CexRec> all_recs, all_ties;
+    int64_t rec_total = 0, tie_total = 0;
+    double ksec = 0.0;
+    int nlaunch = 0;
+    std::vector<bool> stopped(n_props, false);
+    std::vector<int> next_level(n_props, 0);
+    ibmc_status st = IBMC_OK;
+    while (true) {
+        std::vector<std::vector<int>> sel(n_props);
+        bool any = false;
+        for (int i = 0; i < n_props; ++i) {
+            if (stopped[i]) continue;
+            if (o->stop_at_first) {
+                if (next_level[i] < (int)B.level_k[i].size()) { sel[i].push_back(next_level[i]++); any = true; }
+            } else {
+                for (int li = next_level[i]; li < (int)B.level_k[i].size(); ++li) { sel[i].push_back(li); any = true; }
+                next_level[i] = (int)B.level_k[i].size();
+            }
+        }
+        if (!any) break;
+        std::vector<unsigned long long> sc, stt;
+        std::vector<CexRec> r, t;
+        int64_t rt = 0, tt = 0;
+        double ks = 0;
+        int nl = 0;
+        // capacity left for this round
+        ibmc_check_opts oo = *o;
+        oo.cex_capacity = std::max<int64_t>(0, o->cex_capacity - (int64_t)all_recs.size());
+        oo.near_tie_capacity = std::max<int64_t>(0, o->near_tie_capacity - (int64_t)all_ties.size());
+        st = run_levels(ctx, props, n_props, &oo, B, sel, images_on_device, sc, stt, r, t, rt, tt, ks, nl);
+        if (st < 0 && st != IBMC_E_ABORTED) return st;
+        ksec += ks;
+        nlaunch += nl;
+        rec_total += rt;
+        tie_total += tt;
+        all_recs.insert(all_recs.end(), r.begin(), r.end());
+        all_ties.insert(all_ties.end(), t.begin(), t.end());
+        for (int i = 0; i < n_props; ++i)
+            for (int li : sel[i]) {
+                const int slot = B.slot_base[i] + li;
+                cex_acc[slot] += sc[slot];
+                ties_acc[slot] += stt[slot];
+                done_levels[i].push_back(li);
+                if (o->stop_at_first && sc[slot] > 0) stopped[i] = true;
+            }
+        if (st == IBMC_E_ABORTED) break;
+    }
+    HIP_OK(hipEventRecord(ctx->ev1, s));
+    HIP_OK(hipEventSynchronize(ctx->ev1));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    ctx->last_kernel_seconds = ksec;
+    ctx->last_kernel_launches = nlaunch;
+
+    std::sort(all_recs.begin(), all_recs.end(), rec_less);
+    std::sort(all_ties.begin(), all_ties.end(), rec_less);
+    if (cex_buf && !all_recs.empty()) memcpy(cex_buf, all_recs.data(), all_recs.size() * sizeof(CexRec));
+    if (tie_buf && !all_ties.empty()) memcpy(tie_buf, all_ties.data(), all_ties.size() * sizeof(CexRec));
+    for (int i = 0; i < n_props; ++i) {
+        ibmc_check_summary &S = outs[i];
+        memset(&S, 0, sizeof(S));
+        S.clean_label = B.hprops[i].label0;
+        S.first_unsafe_k = -1;
+        S.safe_up_to_k = -1;
+        S.ttfc_seconds = -1.0;
+        S.points_before_first = -1;
+        S.seconds = ms * 1e-3;
+        std::vector<int> lv = done_levels[i];
+        std::sort(lv.begin(), lv.end());
+        S.n_levels = (int32_t)lv.size();
+        bool unsafe = false;
+        for (size_t t = 0; t < lv.size(); ++t) {
+            const int li = lv[t], k = B.level_k[i][li], slot = B.slot_base[i] + li;
+            const bool q8 = props[i].net->act == IBMC_ACT_RELU_Q8;
+            S.level_k[t] = k;
+            int64_t pts = binom_small(props[i].net->dims[0], k) * ipow64(props[i].n_deltas, k);
+            S.points[t] = pts;
+            S.cex[t] = (k == 0) ? 0 : (int64_t)cex_acc[slot];
+            S.ties[t] = (k == 0) ? (q8 ? B.hprops[i].tie0 : 0) : (int64_t)ties_acc[slot];
+            S.points_total += pts;
+            S.cex_total += S.cex[t];
+            if (!q8) S.near_ties_total += S.ties[t];
+            if (S.cex[t] > 0 && S.first_unsafe_k < 0) S.first_unsafe_k = k;
+            if (S.cex[t] > 0) unsafe = true;
+            if (!unsafe) S.safe_up_to_k = k;
+        }
+    }
+    if (st == IBMC_E_ABORTED) return st;
+    if (rec_total > o->cex_capacity || tie_total > o->near_tie_capacity) return IBMC_W_TRUNCATED;
+    return IBMC_OK;
+}
+
+}  // namespace ibmc
+
+using namespace ibmc;
+
+extern "C" ibmc_status ibmc_check_batch(ibmc_ctx *ctx, const ibmc_property *props, int32_t n_props,
+                                        const ibmc_check_opts *opts, ibmc_check_summary *outs, ibmc_cex *cex_buf,
+                                        ibmc_cex *near_tie_buf) {
+    return check_batch_impl(ctx, props, n_props, opts, outs, cex_buf, near_tie_buf, false);
+}
+
+extern "C" ibmc_status ibmc_check_batch_dev(ibmc_ctx *ctx, const ibmc_property *props, int32_t n_props,
+                                            const ibmc_check_opts *opts, ibmc_check_summary *outs, ibmc_cex *cex_buf,
+                                            ibmc_cex *near_tie_buf) {
+    return check_batch_impl(ctx, props, n_props, opts, outs, cex_buf, near_tie_buf, true);
+}
+
+extern "C" ibmc_status ibmc_check_property(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *image, int32_t n_pixels,
+                                           const int16_t *delta_set, int32_t n_deltas, const ibmc_check_opts *opts,
+                                           ibmc_check_summary *out, ibmc_cex *cex_buf, ibmc_cex *near_tie_buf) {
+    clear_error();
+    if (!net || !opts) return fail(IBMC_E_INVALID, "null net / opts");
+    if (n_pixels != net->dims[0]) return fail(IBMC_E_INVALID, "n_pixels %d != network input %d", n_pixels, net->dims[0]);
+    ibmc_property p{};
+    p.net = net;
+    p.image = image;
+    p.deltas = delta_set;
+    p.n_deltas = n_deltas;
+    p.k_min = opts->k_min;
+    p.k_max = opts->k_max;
+    p.k_step = opts->k_step;
+    return check_batch_impl(ctx, &p, 1, opts, out, cex_buf, near_tie_buf, false);
+}
+
+extern "C" ibmc_status ibmc_set_variant(ibmc_ctx *ctx, const ibmc_mlp *net, const char *variant) {
+    clear_error();
+    if (!ctx || !net) return fail(IBMC_E_INVALID, "null argument");
+    ibmc_mlp *m = const_cast<ibmc_mlp *>(net);
+    if (!variant) { m->forced_variant.clear(); return IBMC_OK; }
+    int nv = 0;
+    const EnumVariant *vs = enum_variants(&nv);
+    for (int i = 0; i < nv; ++i)
+        if (std::string(variant) == vs[i].name) {
+            if (vs[i].L != net->L || vs[i].kb1 != net->qd.H[1] / 64 ||
+                vs[i].kb2 != (net->L == 3 ? net->qd.H[2] / 64 : 0))
+                return fail(IBMC_E_INVALID, "variant %s does not match the network", variant);
+            m->forced_variant = variant;
+            return IBMC_OK;
+        }
+    return fail(IBMC_E_INVALID, "unknown variant %s", variant);
+}

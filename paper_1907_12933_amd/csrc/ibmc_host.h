@@ -1,0 +1,92 @@
+// Host-side structures of the library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+#include <deque>
+
+#include "ibmc_internal.h"
+#include "kernels_q8.h"
+#include "kernels_f32.h"
+#include "kernels_cov.h"
+#include "kernels_prop.h"
+
+namespace ibmc {
+
+ibmc_status fail(ibmc_status code, const char *fmt, ...);
+const char *last_error();
+void clear_error();
+
+#define HIP_OK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t _e = (expr);                                                                   \
+        if (_e != hipSuccess)                                                                     \
+            return ::ibmc::fail(IBMC_E_HIP, "%s:%d %s: %s", __FILE__, __LINE__, #expr,             \
+                                hipGetErrorString(_e));                                           \
+    } while (0)
+
+#define IBMC_TRY(expr)                                                                            \
+    do {                                                                                          \
+        ibmc_status _s = (expr);                                                                  \
+        if (_s < 0) return _s;                                                                    \
+    } while (0)
+
+// Grow-only device allocation.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    ~DevBuf();
+    void release();
+    ibmc_status reserve(size_t n);
+    ibmc_status upload(const void *src, size_t n, hipStream_t s);
+    template <class T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+}  // namespace ibmc
+
+struct ibmc_ctx {
+    int device = 0;
+    int n_cu = 0;
+    int arch_major = 0, arch_minor = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ek0 = nullptr, ek1 = nullptr;
+    int32_t *flags_host = nullptr;   // [0] abort request, [1] first hit
+    int32_t *flags_dev = nullptr;    // device view of flags_host
+    // scratch of the check driver (grow-only)
+    ibmc::DevBuf images, props, jobs, qcum, u0, u0_index, prop_ids, counters, recs, ties, order;
+    ibmc::DevBuf u0f;
+    // tuned kernel variant per network shape key
+    std::map<std::string, std::string> tuned;
+    double last_kernel_seconds = 0.0;
+    int last_kernel_launches = 0;
+    ~ibmc_ctx();
+};
+
+struct ibmc_mlp {
+    ibmc_ctx *ctx = nullptr;
+    int act = 0;
+    int L = 0;
+    std::vector<int> dims;
+    std::vector<int> shift;
+    std::vector<std::vector<int8_t>> Wq;
+    std::vector<std::vector<int32_t>> bq;
+    std::vector<std::vector<float>> Wf;
+    std::vector<std::vector<float>> bf;
+    std::deque<ibmc::DevBuf> buf;      // device copies (stable addresses)
+    ibmc::QNetDev qd;
+    ibmc::FNetDev fd;
+    std::string forced_variant;
+    ~ibmc_mlp();
+};
+
+namespace ibmc {
+std::string shape_key(const ibmc_mlp *m);
+}

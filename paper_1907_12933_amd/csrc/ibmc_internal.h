@@ -1,0 +1,195 @@
+// Internal declarations of the HIP library (host runtime + gfx950 kernels).
+//
+// Device data layout of an integer network (built once by ibmc_load_mlp):
+//
+//  * Hidden widths are padded to H_l = roundup(h_l, 64), the class count to
+//    H_L = roundup(h_L, 16); padding rows have zero weights and zero bias.
+//  * Layers l >= 2 run on v_mfma_i32_16x16x64_i8 in the orientation
+//    out[neurons x points] = W_l[neurons x K] * act[K x points]: weights are
+//    the A operand (16 rows x 64 K per instruction, 16 bytes per lane), the
+//    activations of 16 points are the B operand.  The accumulator of one
+//    16-row tile leaves lane (j + 16 g) holding rows 4g..4g+3 of point j.
+//    Packing those four requantised values into one dword gives, with no
+//    data movement, dword t = (tile % 4) of the next layer's B operand for
+//    K-block tile / 4 -- provided the next layer's K index is permuted by
+//    sigma below.  So activations stay in registers from layer to layer.
+//  * sigma(q): inside each block of 64, storage position q = 16g + 4t + i
+//    holds neuron 16t + 4g + i (the two middle base-4 digits swapped; sigma
+//    is an involution).  W1T (first layer, transposed [pixel][H1]), its bias
+//    and the clean potentials are stored in sigma order, so a lane reads the
+//    16 neurons it owns as 16 contiguous values.
+//  * A-operand tiles of W_l (l >= 2): [H_l/16][H_{l-1}/64][64 lanes][16 B];
+//    lane (r + 16 g), byte b of tile (m, kb) = W_l[16m + r][sigma(64kb + 16g + b)].
+//    One wave reads one tile as 1 KB of consecutive 16-byte chunks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ibmc.h"
+
+namespace ibmc {
+
+constexpr int kMaxLayers = IBMC_MAX_LAYERS;
+constexpr int kMaxWidth = IBMC_MAX_WIDTH;
+constexpr int kMaxClasses = 64;
+constexpr int kMaxK = 8;
+constexpr int kMaxDeltas = 64;
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+__host__ __device__ inline int sigma64(int q) {
+    const int blk = q & ~63, g = (q >> 4) & 3, t = (q >> 2) & 3, i = q & 3;
+    return blk | (t << 4) | (g << 2) | i;
+}
+
+__host__ __device__ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// Integer network as the kernels see it.
+struct QNetDev {
+    int L;                             // weight layers
+    int dims[kMaxLayers + 1];          // true widths
+    int H[kMaxLayers + 1];             // padded widths (H[0] = pixels, unpadded)
+    int shift[kMaxLayers];             // per hidden layer (index l-1)
+    const int8_t *W1T;                 // [n][H1], sigma order
+    const int32_t *b1s;                // [H1], sigma order
+    const int8_t *Wt[kMaxLayers + 1];  // l >= 2: A-operand tiles
+    const int32_t *bn[kMaxLayers + 1]; // l >= 2: bias, natural order, padded to H[l]
+    const int8_t *W1tile;              // layer-1 A-operand tiles over pixel K-blocks (coverage)
+    const int32_t *b1n;                // layer-1 bias, natural order, padded to H1
+    const int32_t *rowsum1;            // 128 * sum_i W1[j][i], natural order, padded (x - 128 trick)
+    const int8_t *Wd[kMaxLayers + 1];  // l >= 1: dense row-major [dims[l]][dims[l-1]]
+    const int32_t *bd[kMaxLayers + 1]; // l >= 1: dense bias [dims[l]]
+};
+
+// Float network (sigmoid variant).
+struct FNetDev {
+    int L;
+    int dims[kMaxLayers + 1];
+    const float *W1T;                  // [n][h1] transposed first layer
+    const float *WT[kMaxLayers + 1];   // l >= 2: transposed [dims[l-1]][dims[l]]
+    const float *Wd[kMaxLayers + 1];   // l >= 1: row-major [dims[l]][dims[l-1]]
+    const float *bd[kMaxLayers + 1];
+};
+
+// One counterexample record, identical to ibmc_cex.
+struct CexRec {
+    int32_t prop;
+    int32_t k;
+    int64_t rank;
+    int32_t label;
+    int32_t reserved;
+};
+static_assert(sizeof(CexRec) == sizeof(ibmc_cex), "record layout");
+
+// Per-property device data.
+struct PropDev {
+    const uint8_t *image;  // dims[0] bytes
+    const int32_t *u0s;    // clean first-layer potentials, sigma order (integer) / natural (float)
+    int32_t label0;        // written by the clean pass
+    int32_t m;             // |D|
+    int32_t n;             // pixels
+    int32_t tie0;          // clean image has an exact top-2 tie (written by the clean pass)
+    int16_t deltas[kMaxDeltas];
+};
+
+// Ordering of the last perturbed element inside a segment.
+enum SegMode : int32_t {
+    SEG_PLAIN = 0,   // last element ranges over (p, i) with p > previous pixel, pixel-major
+    SEG_SHELL = 1,   // level 2, shell t: partner candidates order[0..t) (distinct pixel)
+    SEG_LIST1 = 2,   // level 1: candidates order[0..n*m)
+};
+
+// One (property, level) of a launch.
+struct EnumJob {
+    int32_t prop;
+    int32_t k;
+    int32_t slot;          // counter slot of this (property, level)
+    int32_t mode;          // SegMode
+    int64_t chunk_begin;   // first global chunk of this job
+    int64_t chunk_end;
+    const int64_t *qcum;   // plain k >= 2: chunks before last-prefix pixel q, [n]
+    const int32_t *order;  // shell / list modes: candidate ids (p * m + i) by decreasing score
+    const int64_t *shell_cum; // shell mode: chunks before shell t, [n*m + 1]
+};
+
+struct EnumParams {
+    QNetDev net;
+    const EnumJob *jobs;
+    int32_t n_jobs;
+    int32_t batch;                     // chunks taken per queue fetch
+    int64_t total_chunks;
+    const PropDev *props;
+    unsigned long long *queue;         // next unassigned chunk
+    unsigned long long *rec_count;     // records appended (exact, may exceed capacity)
+    int64_t rec_cap;
+    CexRec *recs;
+    unsigned long long *slot_cex;      // per slot counterexamples
+    unsigned long long *slot_ties;     // per slot exact top-2 ties
+    unsigned long long *first_chunk;   // min chunk index holding a counterexample (ordered searches)
+    volatile int32_t *stop_flag;       // device memory: set on the first counterexample if stop_on_first
+    volatile int32_t *abort_host;      // host-mapped abort request (nullable), polled per queue fetch
+    volatile int32_t *hit_host;        // host-mapped, set on the first counterexample (nullable)
+    int32_t stop_on_first;
+    int32_t pad;
+};
+
+// Float enumeration parameters.
+struct FEnumParams {
+    FNetDev net;
+    const EnumJob *jobs;
+    int32_t n_jobs;
+    int32_t batch;
+    int64_t total_chunks;
+    const PropDev *props;
+    const float *u0f;                  // clean first-layer potentials per property [prop][h1]
+    int32_t u0_stride;
+    float tie_rel;
+    unsigned long long *queue;
+    unsigned long long *rec_count;
+    int64_t rec_cap;
+    CexRec *recs;
+    unsigned long long *tie_count;
+    int64_t tie_cap;
+    CexRec *ties;
+    unsigned long long *slot_cex;
+    unsigned long long *slot_ties;
+    volatile int32_t *stop_flag;
+    volatile int32_t *abort_host;
+};
+
+// Binomial coefficient for the small k used here (exact in int64 for n <= 1024, r <= 8).
+__host__ __device__ inline int64_t binom_small(int64_t n, int r) {
+    if (r < 0 || n < r) return 0;
+    int64_t v = 1;
+    for (int t = 1; t <= r; ++t) {
+        const int64_t x = n - r + t;  // v * x is divisible by t; split to keep intermediates small
+        v = (v / t) * x + ((v % t) * x) / t;
+    }
+    return v;
+}
+
+// Combinatorial number system: the lexicographic rank of a k-subset
+// p[0] < ... < p[k-1] of [0, n) is C(n,k) - 1 - sum_j C(n-1-p[j], k-j).
+__host__ __device__ inline int64_t lex_rank_subset(const int *p, int k, int n) {
+    int64_t s = 0;
+    for (int j = 0; j < k; ++j) s += binom_small(n - 1 - p[j], k - j);
+    return binom_small(n, k) - 1 - s;
+}
+
+// Inverse of lex_rank_subset: write R = C(n,k) - 1 - rank as
+// sum_j C(c_j, k-j) with n > c_0 > c_1 > ... >= 0 (greedy), then p_j = n-1-c_j.
+__host__ __device__ inline void lex_unrank_subset(int64_t rank, int k, int n, int *p) {
+    int64_t R = binom_small(n, k) - 1 - rank;
+    int c = n;
+    for (int j = 0; j < k; ++j) {
+        const int r = k - j;
+        int cj = c - 1;
+        while (cj >= r && binom_small(cj, r) > R) --cj;  // stops at r-1 at the latest: C(r-1, r) = 0
+        R -= binom_small(cj, r);
+        p[j] = n - 1 - cj;
+        c = cj;
+    }
+}
+
+}  // namespace ibmc

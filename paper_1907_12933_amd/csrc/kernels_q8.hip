@@ -1,0 +1,233 @@
+// Integer-network kernels for gfx950: plain dense forward (clean pass,
+// replay, forward), and the exhaustive enumeration of the bounded
+// perturbation domain with incremental first layer and int8 MFMA later layers.
+#include <vector>
+
+#include "kernels_q8.h"
+#include "enum_common.h"
+
+namespace ibmc {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int requant_relu(int u, int s) {
+    // floor(u / 2^s) (arithmetic shift), then clamp to [0, 127]
+    return min(max(u >> s, 0), 127);
+}
+
+__device__ __forceinline__ int pack4(int a0, int a1, int a2, int a3) {
+    return a0 | (a1 << 8) | (a2 << 16) | (a3 << 24);
+}
+
+
+// ---------------------------------------------------------------------------
+// plain dense forward of one image held in LDS (one workgroup of 256 threads)
+// ---------------------------------------------------------------------------
+
+// xs: n pixel values; act0/act1: scratch of kMaxWidth ints each.
+// Writes potentials (natural order, layers concatenated) if pot != nullptr,
+// layer-1 potentials in sigma order if u0s != nullptr; returns the label
+// (thread 0 holds the valid value) and the exact-tie flag.
+__device__ void dense_forward_block(const QNetDev &net, const int *xs, int *act0, int *act1,
+                                    int32_t *pot, int32_t *u0s, int *label_out, int *tie_out) {
+    const int tid = threadIdx.x;
+    const int n = net.dims[0], H1 = net.H[1];
+    // layer 1 through the transposed first layer (coalesced), sigma order
+    for (int q = tid; q < H1; q += blockDim.x) {
+        int u = net.b1s[q];
+        for (int i = 0; i < n; ++i) u += (int)net.W1T[(int64_t)i * H1 + q] * xs[i];
+        const int neuron = sigma64(q);
+        if (u0s) u0s[q] = u;
+        if (neuron < net.dims[1]) {
+            if (pot) pot[neuron] = u;
+            act0[neuron] = (net.L > 1) ? requant_relu(u, net.shift[0]) : u;
+        }
+    }
+    __syncthreads();
+    int *in = act0, *out = act1;
+    int po = net.dims[1];
+    for (int l = 2; l <= net.L; ++l) {
+        const int nin = net.dims[l - 1], nout = net.dims[l];
+        const int8_t *W = net.Wd[l];
+        for (int j = tid; j < nout; j += blockDim.x) {
+            int u = net.bd[l][j];
+            const int8_t *row = W + (int64_t)j * nin;
+            for (int i = 0; i < nin; ++i) u += (int)row[i] * in[i];
+            if (pot) pot[po + j] = u;
+            out[j] = (l < net.L) ? requant_relu(u, net.shift[l - 1]) : u;
+        }
+        po += nout;
+        __syncthreads();
+        int *t = in; in = out; out = t;
+    }
+    if (tid == 0) {
+        const int nc = net.dims[net.L];
+        int best = 0;
+        for (int j = 1; j < nc; ++j) if (in[j] > in[best]) best = j;
+        int cnt = 0;
+        for (int j = 0; j < nc; ++j) cnt += in[j] == in[best];
+        *label_out = best;
+        *tie_out = cnt > 1;
+    }
+}
+
+__global__ void __launch_bounds__(256) forward_q8_kernel(QNetDev net, const uint8_t *images,
+                                                         int64_t n_images, int32_t *labels,
+                                                         int32_t *pots, int64_t pot_stride) {
+    __shared__ int xs[kMaxWidth];
+    __shared__ int a0[kMaxWidth], a1[kMaxWidth];
+    __shared__ int lab, tie;
+    for (int64_t img = blockIdx.x; img < n_images; img += gridDim.x) {
+        const uint8_t *x = images + img * net.dims[0];
+        for (int i = threadIdx.x; i < net.dims[0]; i += blockDim.x) xs[i] = x[i];
+        __syncthreads();
+        dense_forward_block(net, xs, a0, a1, pots ? pots + img * pot_stride : nullptr, nullptr, &lab, &tie);
+        __syncthreads();
+        if (threadIdx.x == 0 && labels) labels[img] = lab;
+        __syncthreads();
+    }
+}
+
+// Clean pass of the properties listed in prop_ids: first-layer potentials in
+// sigma order (the base of every incremental update, stored at the property's
+// index) and the clean label.
+__global__ void __launch_bounds__(256) clean_q8_kernel(QNetDev net, PropDev *props,
+                                                       const int32_t *prop_ids, int32_t n_ids,
+                                                       int32_t *u0_store, int64_t u0_stride) {
+    __shared__ int xs[kMaxWidth];
+    __shared__ int a0[kMaxWidth], a1[kMaxWidth];
+    __shared__ int lab, tie;
+    for (int t = blockIdx.x; t < n_ids; t += gridDim.x) {
+        const int pid = prop_ids[t];
+        const uint8_t *x = props[pid].image;
+        for (int i = threadIdx.x; i < net.dims[0]; i += blockDim.x) xs[i] = x[i];
+        __syncthreads();
+        dense_forward_block(net, xs, a0, a1, nullptr, u0_store + (int64_t)pid * u0_stride, &lab, &tie);
+        __syncthreads();
+        if (threadIdx.x == 0) { props[pid].label0 = lab; props[pid].tie0 = tie; }
+        __syncthreads();
+    }
+}
+
+// Replay: rebuild each perturbed image from its record and run the plain
+// forward pass.
+__global__ void __launch_bounds__(256) replay_q8_kernel(QNetDev net, const uint8_t *clean,
+                                                        const int16_t *deltas, int m,
+                                                        const CexRec *recs, int64_t n_recs,
+                                                        int32_t *labels) {
+    __shared__ int xs[kMaxWidth];
+    __shared__ int a0[kMaxWidth], a1[kMaxWidth];
+    __shared__ int lab, tie;
+    __shared__ int pix[kMaxK], dig[kMaxK];
+    const int n = net.dims[0];
+    for (int64_t r = blockIdx.x; r < n_recs; r += gridDim.x) {
+        const int k = recs[r].k;
+        if (threadIdx.x == 0) {
+            int64_t mk = 1;
+            for (int j = 0; j < k; ++j) mk *= m;
+            int64_t srank = recs[r].rank / mk, drank = recs[r].rank % mk;
+            int p[kMaxK];
+            lex_unrank_subset(srank, k, n, p);
+            for (int j = k - 1; j >= 0; --j) { dig[j] = (int)(drank % m); drank /= m; }
+            for (int j = 0; j < k; ++j) pix[j] = p[j];
+        }
+        for (int i = threadIdx.x; i < n; i += blockDim.x) xs[i] = clean[i];
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int j = 0; j < k; ++j) xs[pix[j]] = clamp_pixel(xs[pix[j]] + deltas[dig[j]]);
+        __syncthreads();
+        dense_forward_block(net, xs, a0, a1, nullptr, nullptr, &lab, &tie);
+        __syncthreads();
+        if (threadIdx.x == 0) labels[r] = lab;
+        __syncthreads();
+    }
+}
+
+__global__ void fill_u64_kernel(unsigned long long *p, int64_t n, unsigned long long v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// enumeration
+// ---------------------------------------------------------------------------
+
+// ---------------------------------------------------------------------------
+// instantiation table (the instances live in enum_q8_*.hip, compiled in parallel)
+// ---------------------------------------------------------------------------
+
+const EnumVariant *enum_variants(int *count) {
+    static std::vector<EnumVariant> all;
+    if (all.empty()) {
+        int n = 0;
+        const EnumVariant *v = enum_variants_l2(&n);
+        all.insert(all.end(), v, v + n);
+        v = enum_variants_l3a(&n);
+        all.insert(all.end(), v, v + n);
+        v = enum_variants_l3b(&n);
+        all.insert(all.end(), v, v + n);
+    }
+    *count = (int)all.size();
+    return all.data();
+}
+
+// ---------------------------------------------------------------------------
+// host launch wrappers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_forward_q8(const QNetDev &net, const uint8_t *images, int64_t n_images,
+                             int32_t *labels, int32_t *pots, int64_t pot_stride, hipStream_t s) {
+    if (n_images <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>(n_images, 4096);
+    hipLaunchKernelGGL(forward_q8_kernel, dim3(grid), dim3(256), 0, s, net, images, n_images,
+                       labels, pots, pot_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_clean_q8(const QNetDev &net, PropDev *props, const int32_t *prop_ids,
+                           int32_t n_ids, int32_t *u0_store, int64_t u0_stride, hipStream_t s) {
+    if (n_ids <= 0) return hipSuccess;
+    const int grid = std::min(n_ids, 4096);
+    hipLaunchKernelGGL(clean_q8_kernel, dim3(grid), dim3(256), 0, s, net, props, prop_ids, n_ids,
+                       u0_store, u0_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_replay_q8(const QNetDev &net, const uint8_t *clean, const int16_t *deltas, int m,
+                            const CexRec *recs, int64_t n_recs, int32_t *labels, hipStream_t s) {
+    if (n_recs <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>(n_recs, 8192);
+    hipLaunchKernelGGL(replay_q8_kernel, dim3(grid), dim3(256), 0, s, net, clean, deltas, m, recs,
+                       n_recs, labels);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(grid), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+int64_t enum_lds_bytes(const EnumVariant &v, const QNetDev &net) {
+    int64_t w = 0;
+    if (v.wlds) {
+        if (v.L == 3) w += (int64_t)(net.H[2] / 16) * v.kb1 * 1024;
+        const int kbl = (v.L == 3) ? v.kb2 : v.kb1;
+        w += (int64_t)(net.H[v.L] / 16) * kbl * 1024;
+    }
+    return w + 4LL * v.kb1 * 64 * 4;
+}
+
+hipError_t launch_enum_q8(const EnumVariant &v, int grid, const EnumParams &P,
+                          const int32_t *u0_store, int64_t u0_stride, const int32_t *u0_index,
+                          hipStream_t s) {
+    const int64_t lds = enum_lds_bytes(v, P.net);
+    void *args[] = {const_cast<EnumParams *>(&P), &u0_store, &u0_stride, &u0_index};
+    return hipLaunchKernel(v.fn, dim3(grid), dim3(256), args, (size_t)lds, s);
+}
+
+}  // namespace ibmc
