@@ -113,7 +113,7 @@ typedef struct {
  * point, never a counterexample).  stop_at_first: stop after the first level
  * that has a counterexample (Sec. II-B stops at the first violation).
  * cex_capacity / near_tie_capacity: room in the caller's record buffers.
- * near_tie_rel: float nets only; <= 0 selects 4e-5. */
+ * near_tie_rel: float nets only; <= 0 selects 1e-4. */
 typedef struct {
     int32_t k_min, k_max, k_step, stop_at_first;
     int64_t cex_capacity;
@@ -329,6 +329,12 @@ ibmc_status ibmc_proposer_train(ibmc_ctx *ctx, ibmc_proposer *p, const float *fe
 ibmc_status ibmc_proposer_score(ibmc_ctx *ctx, const ibmc_proposer *p, const ibmc_mlp *net,
                                 const uint8_t *image, int32_t rows, int32_t cols,
                                 const int16_t *delta_set, int32_t n_deltas, float *scores);
+
+/* Training labels from a property's counterexample records: labels_out
+ * (host float [n_pixels * n_deltas], candidate p * n_deltas + i) is 1 for
+ * every (pixel, delta index) that occurs in some record, else 0. */
+ibmc_status ibmc_label_candidates(ibmc_ctx *ctx, int32_t n_pixels, int32_t n_deltas, const ibmc_cex *recs,
+                                  int64_t n, float *labels_out);
 
 /* Ordered check of levels k <= 2 (integer nets): level 1 visits candidates by
  * decreasing score; level 2 visits "shells": candidates sorted c0, c1, ...,

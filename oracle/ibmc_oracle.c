@@ -690,3 +690,62 @@ void orc_adam_step(int64_t n, double *theta, const double *g, double *mom, doubl
         theta[i] -= lr * (mom[i] / c1) / (sqrt(vel[i] / c2) + eps);
     }
 }
+
+/* Features of every candidate (pixel p, delta index i) of an image for the
+ * proposal network, in double: row/(rows-1), col/(cols-1), x/255, d/dmax,
+ * e/dmax with e = clamp(x+d) - x, the L1 and L2 norms of the first-layer
+ * weight column of p and its L1 norm over the first-layer units whose clean
+ * potential lies in the requantiser's unsaturated window [0, 128 * 2^s),
+ * each divided by its maximum over pixels (at least 1), then 1, then zeros
+ * up to 32 entries. */
+int orc_prop_features(int L, const int32_t *dims, const int8_t *W, const int32_t *b, const int32_t *shift,
+                      const uint8_t *x, int rows, int cols, const int16_t *D, int m, double *feat) {
+    if (L < 2 || !dims || !W || !b || !shift || !x || !D || m < 1 || rows * cols != dims[0]) return ORC_E_INVALID;
+    int n = dims[0], h1 = dims[1];
+    unsigned char *live = malloc((size_t)h1);
+    double *n1 = malloc(sizeof(double) * n), *n2 = malloc(sizeof(double) * n), *nl = malloc(sizeof(double) * n);
+    if (!live || !n1 || !n2 || !nl) { free(live); free(n1); free(n2); free(nl); return ORC_E_OOM; }
+    int64_t top = (int64_t)128 << shift[0];
+    for (int j = 0; j < h1; ++j) {
+        int64_t u = b[j];
+        for (int i = 0; i < n; ++i) u += (int64_t)W[(int64_t)j * n + i] * x[i];
+        live[j] = u >= 0 && u < top;
+    }
+    double m1 = 1.0, m2 = 1.0, ml = 1.0;
+    for (int p = 0; p < n; ++p) {
+        double s1 = 0, s2 = 0, sl = 0;
+        for (int j = 0; j < h1; ++j) {
+            double w = W[(int64_t)j * n + p];
+            s1 += fabs(w);
+            s2 += w * w;
+            if (live[j]) sl += fabs(w);
+        }
+        n1[p] = s1; n2[p] = sqrt(s2); nl[p] = sl;
+        if (s1 > m1) m1 = s1;
+        if (n2[p] > m2) m2 = n2[p];
+        if (sl > ml) ml = sl;
+    }
+    double dmax = 1.0;
+    for (int i = 0; i < m; ++i) if (fabs((double)D[i]) > dmax) dmax = fabs((double)D[i]);
+    for (int p = 0; p < n; ++p) {
+        int r = p / cols, c = p % cols;
+        for (int i = 0; i < m; ++i) {
+            double *f = feat + ((int64_t)p * m + i) * 32;
+            int v = (int)x[p] + D[i];
+            if (v < 0) v = 0;
+            if (v > 255) v = 255;
+            f[0] = rows > 1 ? (double)r / (rows - 1) : (double)r;
+            f[1] = cols > 1 ? (double)c / (cols - 1) : (double)c;
+            f[2] = x[p] / 255.0;
+            f[3] = D[i] / dmax;
+            f[4] = (v - (int)x[p]) / dmax;
+            f[5] = n1[p] / m1;
+            f[6] = n2[p] / m2;
+            f[7] = nl[p] / ml;
+            f[8] = 1.0;
+            for (int z = 9; z < 32; ++z) f[z] = 0.0;
+        }
+    }
+    free(live); free(n1); free(n2); free(nl);
+    return ORC_OK;
+}

@@ -60,6 +60,7 @@ def lib():
         L.orc_adam_step.argtypes = [C.c_int64, F64P, F64P, F64P, F64P, C.c_int, C.c_double,
                                     C.c_double, C.c_double, C.c_double]
         L.orc_adam_step.restype = None
+        L.orc_prop_features.argtypes = [C.c_int, I32P, I8P, I32P, I32P, U8P, C.c_int, C.c_int, I16P, C.c_int, F64P]
         _LIB = L
     return _LIB
 
@@ -258,3 +259,14 @@ def adam_step(theta, g, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     lib().orc_adam_step(theta.size, _p(theta, F64P), _p(g, F64P), _p(m, F64P), _p(v, F64P), int(t),
                         float(lr), float(beta1), float(beta2), float(eps))
+
+
+def prop_features(net, x, rows, cols, deltas):
+    """Candidate features [n * |D|, 32] (double) of image x for the proposal network."""
+    dims, W, b, sh = _flat_q8(net)
+    x = np.ascontiguousarray(x, np.uint8)
+    D = np.ascontiguousarray(deltas, np.int16)
+    f = np.zeros((x.size * D.size, 32), np.float64)
+    _ck(lib().orc_prop_features(len(dims) - 1, _p(dims, I32P), _p(W, I8P), _p(b, I32P), _p(sh, I32P), _p(x, U8P),
+                                int(rows), int(cols), _p(D, I16P), D.size, _p(f, F64P)))
+    return f

@@ -25,8 +25,28 @@ struct Cursor {
     int64_t job_end;
 };
 
+
+// lex_unrank_subset with a fixed trip count (kept in registers on the device).
+__device__ __forceinline__ void lex_unrank_subset_fixed(int64_t rank, int k, int n, int (&p)[kMaxK]) {
+    int64_t R = binom_small(n, k) - 1 - rank;
+    int c = n;
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j) {
+        if (j < k) {
+            const int r = k - j;
+            int cj = c - 1;
+            while (cj >= r && binom_small(cj, r) > R) --cj;
+            R -= binom_small(cj, r);
+            p[j] = n - 1 - cj;
+            c = cj;
+        } else {
+            p[j] = 0;
+        }
+    }
+}
+
 template <int CH, class PT>
-__device__ void cursor_job_start(Cursor &c, const PT &P, int job) {
+__device__ __forceinline__ void cursor_job_start(Cursor &c, const PT &P, int job) {
     const EnumJob &J = P.jobs[job];
     c.job = job;
     c.k = J.k;
@@ -39,14 +59,14 @@ __device__ void cursor_job_start(Cursor &c, const PT &P, int job) {
 }
 
 template <int CH>
-__device__ void cursor_set_q(Cursor &c) {
+__device__ __forceinline__ void cursor_set_q(Cursor &c) {
     c.seglen = (int64_t)(c.n - 1 - c.q) * c.m;
     c.nch = (c.seglen + CH - 1) / CH;
 }
 
 // Decode global chunk `chunk` from scratch.
 template <int CH, class PT>
-__device__ void cursor_decode(Cursor &c, const PT &P, int64_t chunk) {
+__device__ __forceinline__ void cursor_decode(Cursor &c, const PT &P, int64_t chunk) {
     int lo = 0, hi = P.n_jobs - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -99,20 +119,23 @@ __device__ void cursor_decode(Cursor &c, const PT &P, int64_t chunk) {
     for (int j = 0; j < c.k - 1; ++j) mk1 *= c.m;
     const int64_t combo = seg / mk1;
     int64_t dig = seg % mk1;
+#pragma unroll
     for (int j = kMaxK - 1; j >= 0; --j) {
         if (j < c.k - 1) { c.dg[j] = (int)(dig % c.m); dig /= c.m; }
     }
     int tmp[kMaxK];
-    lex_unrank_subset(combo, c.k - 2, c.q, tmp);
-    for (int j = 0; j < kMaxK; ++j)
+    lex_unrank_subset_fixed(combo, c.k - 2, c.q, tmp);
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j) {
         if (j < c.k - 2) c.pre[j] = tmp[j];
-    c.pre[c.k - 2] = c.q;
+        if (j == c.k - 2) c.pre[j] = c.q;
+    }
 }
 
 // Move to the next chunk.  Returns true when the segment (hence the base)
 // changed.
 template <int CH, class PT>
-__device__ bool cursor_next(Cursor &c, const PT &P) {
+__device__ __forceinline__ bool cursor_next(Cursor &c, const PT &P) {
     c.chunk++;
     if (++c.ch < c.nch) return false;
     c.ch = 0;
@@ -128,27 +151,41 @@ __device__ bool cursor_next(Cursor &c, const PT &P) {
     }
     if (c.mode == SEG_LIST1 || c.k == 1) return true;  // single segment: end of job handled above
     // prefix deltas, last digit fastest
-    for (int j = kMaxK - 1; j >= 0; --j) {
-        if (j < c.k - 1) {
-            if (++c.dg[j] < c.m) return true;
-            c.dg[j] = 0;
+    {
+        bool carry = true;
+#pragma unroll
+        for (int j = kMaxK - 1; j >= 0; --j) {
+            if (carry && j < c.k - 1) {
+                if (++c.dg[j] < c.m) carry = false;
+                else c.dg[j] = 0;
+            }
         }
+        if (!carry) return true;
     }
     // next (k-2)-subset of [0, q) in lexicographic order
     const int r = c.k - 2;
-    for (int j = kMaxK - 1; j >= 0; --j) {
-        if (j < r && c.pre[j] < c.q - (r - j)) {
-            c.pre[j]++;
-            for (int t = 0; t < kMaxK; ++t)
-                if (t > j && t < r) c.pre[t] = c.pre[t - 1] + 1;
+    {
+        int piv = -1;
+#pragma unroll
+        for (int j = kMaxK - 1; j >= 0; --j)
+            if (piv < 0 && j < r && c.pre[j] < c.q - (r - j)) piv = j;
+        if (piv >= 0) {
+            int run = 0;
+#pragma unroll
+            for (int t = 0; t < kMaxK; ++t) {
+                if (t == piv) { c.pre[t]++; run = c.pre[t]; }
+                else if (t > piv && t < r) { run++; c.pre[t] = run; }
+            }
             return true;
         }
     }
     // next q
     c.q++;
-    for (int t = 0; t < kMaxK; ++t)
+#pragma unroll
+    for (int t = 0; t < kMaxK; ++t) {
         if (t < r) c.pre[t] = t;
-    c.pre[r] = c.q;
+        if (t == r) c.pre[t] = c.q;
+    }
     cursor_set_q<CH>(c);
     return true;
 }
@@ -177,16 +214,42 @@ __device__ __forceinline__ bool last_element(const Cursor &c, const PT &P, int64
     return true;
 }
 
+
+// 32-bit form of last_element for the per-point hot path (segment lengths
+// are below 2^31: at most n * |D| candidates).
+template <class PT>
+__device__ __forceinline__ bool last_element32(const Cursor &c, const PT &P, int o, int &p, int &i) {
+    if (o >= (int)c.seglen) return false;
+    if (c.mode == SEG_PLAIN) {
+        const unsigned uo = (unsigned)o, um = (unsigned)c.m;
+        const unsigned qd = uo / um;
+        p = c.q + 1 + (int)qd;
+        i = (int)(uo - qd * um);
+        return true;
+    }
+    const EnumJob &J = P.jobs[c.job];
+    const int cand = J.order[o];
+    p = cand / c.m;
+    i = cand - p * c.m;
+    if (c.mode == SEG_SHELL) {
+        const int head = J.order[c.shell];
+        return p != head / c.m;
+    }
+    return true;
+}
+
 // Point rank (see the header) of a point given by its prefix and last element.
 template <class PT>
-__device__ int64_t point_rank(const Cursor &c, const PT &P, int p, int i) {
+__device__ __forceinline__ int64_t point_rank(const Cursor &c, const PT &P, int p, int i) {
     int pix[kMaxK], dig[kMaxK];
     int kk = c.k;
     if (c.mode == SEG_PLAIN) {
-        for (int j = 0; j < kMaxK; ++j)
+#pragma unroll
+        for (int j = 0; j < kMaxK; ++j) {
             if (j < kk - 1) { pix[j] = c.pre[j]; dig[j] = c.dg[j]; }
-        pix[kk - 1] = p;
-        dig[kk - 1] = i;
+            else if (j == kk - 1) { pix[j] = p; dig[j] = i; }
+            else { pix[j] = 0; dig[j] = 0; }
+        }
     } else if (c.mode == SEG_SHELL) {
         const int head = P.jobs[c.job].order[c.shell];
         const int ph = head / c.m, ih = head % c.m;
@@ -195,12 +258,15 @@ __device__ int64_t point_rank(const Cursor &c, const PT &P, int p, int i) {
     } else {
         pix[0] = p; dig[0] = i;
     }
-    int64_t d = 0;
+    int64_t d = 0, mk = 1, s = 0;
+#pragma unroll
     for (int j = 0; j < kMaxK; ++j)
-        if (j < kk) d = d * c.m + dig[j];
-    int64_t mk = 1;
-    for (int j = 0; j < kk; ++j) mk *= c.m;
-    return lex_rank_subset(pix, kk, c.n) * mk + d;
+        if (j < kk) {
+            d = d * c.m + dig[j];
+            mk *= c.m;
+            s += binom_small(c.n - 1 - pix[j], kk - j);
+        }
+    return (binom_small(c.n, kk) - 1 - s) * mk + d;
 }
 
 }  // namespace ibmc

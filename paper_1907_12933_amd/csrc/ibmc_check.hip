@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <chrono>
 #include <cstring>
 #include <map>
@@ -118,58 +119,78 @@ static ibmc_status validate_props(const ibmc_property *props, int32_t n_props, c
     return IBMC_OK;
 }
 
-// Run the given levels (subset of every property's level list) as one
-// launch per network.  level_sel[prop] = level indices to run.
+// Run the given levels (subset of every property's level list): a clean
+// pass and one persistent enumeration launch per network.  All plans are
+// uploaded first; with several networks the launches are captured as one HIP
+// graph with a parallel branch per network, so networks of uneven size share
+// the GPU.  level_sel[prop] = level indices to run.
+struct NetPlan {
+    const ibmc_mlp *net;
+    std::vector<int> ids;
+    const EnumVariant *v = nullptr;
+    int64_t total = 0;
+    size_t job_off = 0, n_jobs = 0;
+    int grid = 0;
+    int32_t packed = 0, vb_lo = 0, vb_hi = 0;
+};
+
 static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t n_props,
                               const ibmc_check_opts *o, BatchState &B,
                               const std::vector<std::vector<int>> &level_sel, bool images_on_device,
                               std::vector<unsigned long long> &slot_cex, std::vector<unsigned long long> &slot_ties,
                               std::vector<CexRec> &recs, std::vector<CexRec> &ties, int64_t &rec_total,
                               int64_t &tie_total, double &kernel_seconds, int &launches) {
+    (void)images_on_device;
     hipStream_t s = ctx->stream;
-    // group properties by network
-    std::vector<const ibmc_mlp *> nets;
-    std::map<const ibmc_mlp *, std::vector<int>> by_net;
-    for (int i = 0; i < n_props; ++i) {
-        if (level_sel[i].empty()) continue;
-        if (!by_net.count(props[i].net)) nets.push_back(props[i].net);
-        by_net[props[i].net].push_back(i);
+    std::vector<NetPlan> plans;
+    {
+        std::map<const ibmc_mlp *, size_t> where;
+        for (int i = 0; i < n_props; ++i) {
+            if (level_sel[i].empty()) continue;
+            auto it = where.find(props[i].net);
+            if (it == where.end()) {
+                where[props[i].net] = plans.size();
+                plans.emplace_back();
+                plans.back().net = props[i].net;
+                plans.back().ids.push_back(i);
+            } else {
+                plans[it->second].ids.push_back(i);
+            }
+        }
     }
-    // counters: [0] queue, [1] rec_count, [2] first_chunk, [3] tie_count, [4] stop flag (int)
-    //           then slot_cex[n_slots], slot_ties[n_slots]
-    const int64_t n_ctr = 8 + 2 * (int64_t)B.n_slots;
+    const int NN = (int)plans.size();
+    // counters: [1] rec_count, [2] first_chunk, [3] tie_count, [4] stop flag,
+    //           [8, 8+NN) per-network queues, then slot_cex[n_slots], slot_ties[n_slots]
+    const int64_t q0 = 8, sc0 = 8 + NN, st0 = sc0 + B.n_slots;
+    const int64_t n_ctr = st0 + B.n_slots;
     IBMC_TRY(ctx->counters.reserve(n_ctr * 8));
     unsigned long long *ctr = ctx->counters.as<unsigned long long>();
     const int64_t cap = o->cex_capacity, tcap = o->near_tie_capacity;
     IBMC_TRY(ctx->recs.reserve((size_t)std::max<int64_t>(cap, 1) * sizeof(CexRec)));
     IBMC_TRY(ctx->ties.reserve((size_t)std::max<int64_t>(tcap, 1) * sizeof(CexRec)));
-    HIP_OK(launch_fill_u64(ctr, n_ctr, 0ull, s));
-    HIP_OK(launch_fill_u64(ctr + 2, 1, ~0ull, s));  // first_chunk starts at "none"
     int64_t max_h1 = 64;
-    for (auto *nt : nets) max_h1 = std::max<int64_t>(max_h1, nt->act == IBMC_ACT_RELU_Q8 ? nt->qd.H[1] : nt->dims[1]);
+    for (auto &pl : plans)
+        max_h1 = std::max<int64_t>(max_h1, pl.net->act == IBMC_ACT_RELU_Q8 ? pl.net->qd.H[1] : pl.net->dims[1]);
     IBMC_TRY(ctx->u0.reserve((size_t)n_props * max_h1 * 4));
-    std::vector<int32_t> u0_index(n_props);
+    std::vector<int32_t> u0_index(n_props), all_ids;
     std::iota(u0_index.begin(), u0_index.end(), 0);
     IBMC_TRY(ctx->u0_index.upload(u0_index.data(), u0_index.size() * 4, s));
 
-    kernel_seconds = 0.0;
-    launches = 0;
-    for (const ibmc_mlp *net : nets) {
-        const std::vector<int> &ids = by_net[net];
+    // plans: variants, jobs and chunk prefix sums of every network
+    std::vector<EnumJob> jobs;
+    std::vector<int64_t> qcum_all;
+    std::vector<size_t> qcum_off;
+    for (auto &pl : plans) {
+        const ibmc_mlp *net = pl.net;
         const bool q8 = net->act == IBMC_ACT_RELU_Q8;
-        const EnumVariant *v = nullptr;
         int CH = enum_f32_chunk();
         if (q8) {
-            v = pick_variant(ctx, net);
-            if (!v) return fail(IBMC_E_UNIMPL, "no enumeration kernel for network %s", shape_key(net).c_str());
-            CH = v->chunk;
+            pl.v = pick_variant(ctx, net);
+            if (!pl.v) return fail(IBMC_E_UNIMPL, "no enumeration kernel for network %s", shape_key(net).c_str());
+            CH = pl.v->chunk;
         }
-        // jobs and their chunk plans
-        std::vector<EnumJob> jobs;
-        std::vector<int64_t> qcum_all;
-        std::vector<size_t> qcum_off;
-        int64_t total = 0;
-        for (int pid : ids) {
+        pl.job_off = jobs.size();
+        for (int pid : pl.ids) {
             const int n = net->dims[0], m = props[pid].n_deltas;
             for (int li : level_sel[pid]) {
                 const int k = B.level_k[pid][li];
@@ -181,42 +202,62 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
                 J.k = k;
                 J.slot = B.slot_base[pid] + li;
                 J.mode = SEG_PLAIN;
-                J.chunk_begin = total;
-                J.chunk_end = total + ch;
+                J.chunk_begin = pl.total;
+                J.chunk_end = pl.total + ch;
                 qcum_off.push_back(k >= 2 ? qcum_all.size() : (size_t)-1);
                 if (k >= 2) qcum_all.insert(qcum_all.end(), qc.begin(), qc.end());
-                total += ch;
+                pl.total += ch;
                 jobs.push_back(J);
             }
         }
-        // clean pass of this network's properties
-        IBMC_TRY(ctx->prop_ids.upload(ids.data(), ids.size() * 4, s));
-        PropDev *dprops = ctx->props.as<PropDev>();
+        pl.n_jobs = jobs.size() - pl.job_off;
         if (q8) {
-            HIP_OK(launch_clean_q8(net->qd, dprops, ctx->prop_ids.as<int32_t>(), (int32_t)ids.size(),
-                                   ctx->u0.as<int32_t>(), max_h1, s));
+            int maxe = 0;
+            for (int pid : pl.ids)
+                for (int j = 0; j < props[pid].n_deltas; ++j)
+                    maxe = std::max(maxe, std::min(255, std::abs((int)props[pid].deltas[j])));
+            const int64_t M2 = (int64_t)net->qd.f1 * maxe * net->qd.maxw1;
+            pl.packed = (net->qd.f1 > 0 && M2 <= 8191 && !ctx->force_int32_layer1) ? 1 : 0;
+            pl.vb_lo = (int32_t)(-16385 - M2);
+            pl.vb_hi = (int32_t)(16384 + M2);
+            int occ = 0;
+            HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, pl.v->fn, 256,
+                                                                (size_t)enum_lds_bytes(*pl.v, net->qd)));
+            if (occ < 1) return fail(IBMC_E_UNIMPL, "variant %s does not fit", pl.v->name);
+            pl.grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * occ, std::max<int64_t>(1, pl.total / 2));
         } else {
-            HIP_OK(launch_clean_f32(net->fd, dprops, ctx->prop_ids.as<int32_t>(), (int32_t)ids.size(),
-                                    ctx->u0.as<float>(), max_h1, s));
+            pl.grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * 4, std::max<int64_t>(1, pl.total));
         }
-        if (jobs.empty() || total == 0) continue;
-        IBMC_TRY(ctx->qcum.reserve(std::max<size_t>(qcum_all.size(), 1) * 8));
-        if (!qcum_all.empty())
-            HIP_OK(hipMemcpyAsync(ctx->qcum.p, qcum_all.data(), qcum_all.size() * 8, hipMemcpyHostToDevice, s));
-        for (size_t j = 0; j < jobs.size(); ++j)
-            jobs[j].qcum = (qcum_off[j] == (size_t)-1) ? nullptr : ctx->qcum.as<int64_t>() + qcum_off[j];
-        IBMC_TRY(ctx->jobs.upload(jobs.data(), jobs.size() * sizeof(EnumJob), s));
-        HIP_OK(launch_fill_u64(ctr, 1, 0ull, s));  // queue restarts for this launch
-        HIP_OK(hipEventRecord(ctx->ek0, s));
-        if (q8) {
+        all_ids.insert(all_ids.end(), pl.ids.begin(), pl.ids.end());
+    }
+    IBMC_TRY(ctx->qcum.reserve(std::max<size_t>(qcum_all.size(), 1) * 8));
+    if (!qcum_all.empty())
+        HIP_OK(hipMemcpyAsync(ctx->qcum.p, qcum_all.data(), qcum_all.size() * 8, hipMemcpyHostToDevice, s));
+    for (size_t j = 0; j < jobs.size(); ++j)
+        jobs[j].qcum = (qcum_off[j] == (size_t)-1) ? nullptr : ctx->qcum.as<int64_t>() + qcum_off[j];
+    IBMC_TRY(ctx->jobs.upload(jobs.data(), std::max<size_t>(jobs.size(), 1) * sizeof(EnumJob), s));
+    IBMC_TRY(ctx->prop_ids.upload(all_ids.data(), std::max<size_t>(all_ids.size(), 1) * 4, s));
+    HIP_OK(hipStreamSynchronize(s));  // host staging vectors may go now
+
+    PropDev *dprops = ctx->props.as<PropDev>();
+    auto launch_net = [&](const NetPlan &pl, size_t id_off, hipStream_t st) -> ibmc_status {
+        const ibmc_mlp *net = pl.net;
+        const int32_t *ids = ctx->prop_ids.as<int32_t>() + id_off;
+        if (net->act == IBMC_ACT_RELU_Q8)
+            HIP_OK(launch_clean_q8(net->qd, dprops, ids, (int32_t)pl.ids.size(), ctx->u0.as<int32_t>(), max_h1, st));
+        else
+            HIP_OK(launch_clean_f32(net->fd, dprops, ids, (int32_t)pl.ids.size(), ctx->u0.as<float>(), max_h1, st));
+        if (pl.n_jobs == 0 || pl.total == 0) return IBMC_OK;
+        const int pi = (int)(&pl - plans.data());
+        if (net->act == IBMC_ACT_RELU_Q8) {
             EnumParams P{};
             P.net = net->qd;
-            P.jobs = ctx->jobs.as<EnumJob>();
-            P.n_jobs = (int32_t)jobs.size();
-            P.total_chunks = total;
-            P.batch = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, total / (ctx->n_cu * 64)));
+            P.jobs = ctx->jobs.as<EnumJob>() + pl.job_off;
+            P.n_jobs = (int32_t)pl.n_jobs;
+            P.total_chunks = pl.total;
+            P.batch = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, pl.total / ((int64_t)pl.grid * 32)));
             P.props = dprops;
-            P.queue = ctr + 0;
+            P.queue = ctr + q0 + pi;
             P.rec_count = ctr + 1;
             P.first_chunk = ctr + 2;
             P.stop_flag = reinterpret_cast<volatile int32_t *>(ctr + 4);
@@ -224,61 +265,119 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
             P.hit_host = nullptr;
             P.rec_cap = cap;
             P.recs = ctx->recs.as<CexRec>();
-            P.slot_cex = ctr + 8;
-            P.slot_ties = ctr + 8 + B.n_slots;
+            P.slot_cex = ctr + sc0;
+            P.slot_ties = ctr + st0;
             P.stop_on_first = 0;
-            int occ = 0;
-            const int64_t lds = enum_lds_bytes(*v, net->qd);
-            HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, v->fn, 256, (size_t)lds));
-            if (occ < 1) return fail(IBMC_E_UNIMPL, "variant %s does not fit (lds %lld)", v->name, (long long)lds);
-            const int64_t grid = std::min<int64_t>((int64_t)ctx->n_cu * occ, std::max<int64_t>(1, total / P.batch));
-            HIP_OK(launch_enum_q8(*v, (int)grid, P, ctx->u0.as<int32_t>(), max_h1, ctx->u0_index.as<int32_t>(), s));
+            P.packed = pl.packed;
+            P.vb_lo = pl.vb_lo;
+            P.vb_hi = pl.vb_hi;
+            HIP_OK(launch_enum_q8(*pl.v, pl.grid, P, ctx->u0.as<int32_t>(), max_h1, ctx->u0_index.as<int32_t>(), st));
         } else {
             FEnumParams P{};
             P.net = net->fd;
-            P.jobs = ctx->jobs.as<EnumJob>();
-            P.n_jobs = (int32_t)jobs.size();
-            P.total_chunks = total;
-            P.batch = (int32_t)std::max<int64_t>(1, std::min<int64_t>(16, total / (ctx->n_cu * 16)));
+            P.jobs = ctx->jobs.as<EnumJob>() + pl.job_off;
+            P.n_jobs = (int32_t)pl.n_jobs;
+            P.total_chunks = pl.total;
+            P.batch = (int32_t)std::max<int64_t>(1, std::min<int64_t>(16, pl.total / ((int64_t)pl.grid * 8)));
             P.props = dprops;
             P.u0f = ctx->u0.as<float>();
             P.u0_stride = (int32_t)max_h1;
-            P.tie_rel = (o->near_tie_rel > 0) ? o->near_tie_rel : 4e-5f;
-            P.queue = ctr + 0;
+            P.tie_rel = (o->near_tie_rel > 0) ? o->near_tie_rel : kDefaultTieRel;
+            P.queue = ctr + q0 + pi;
             P.rec_count = ctr + 1;
             P.rec_cap = cap;
             P.recs = ctx->recs.as<CexRec>();
             P.tie_count = ctr + 3;
             P.tie_cap = tcap;
             P.ties = ctx->ties.as<CexRec>();
-            P.slot_cex = ctr + 8;
-            P.slot_ties = ctr + 8 + B.n_slots;
+            P.slot_cex = ctr + sc0;
+            P.slot_ties = ctr + st0;
             P.stop_flag = reinterpret_cast<volatile int32_t *>(ctr + 4);
             P.abort_host = ctx->flags_dev;
-            const int64_t grid = std::min<int64_t>((int64_t)ctx->n_cu * 4, std::max<int64_t>(1, total / P.batch));
-            HIP_OK(launch_enum_f32((int)grid, P, ctx->u0_index.as<int32_t>(), s));
+            HIP_OK(launch_enum_f32(pl.grid, P, ctx->u0_index.as<int32_t>(), st));
         }
-        HIP_OK(hipEventRecord(ctx->ek1, s));
-        HIP_OK(hipEventSynchronize(ctx->ek1));
-        float ms = 0.f;
-        HIP_OK(hipEventElapsedTime(&ms, ctx->ek0, ctx->ek1));
-        kernel_seconds += ms * 1e-3;
-        launches++;
+        return IBMC_OK;
+    };
+
+    kernel_seconds = 0.0;
+    launches = 0;
+    HIP_OK(hipEventRecord(ctx->ek0, s));
+    if (NN <= 1) {
+        HIP_OK(launch_fill_u64(ctr, n_ctr, 0ull, s));
+        HIP_OK(launch_fill_u64(ctr + 2, 1, ~0ull, s));
+        size_t id_off = 0;
+        for (auto &pl : plans) {
+            IBMC_TRY(launch_net(pl, id_off, s));
+            id_off += pl.ids.size();
+        }
+    } else {
+        // one graph: counters cleared by a kernel (no memset node), then a
+        // branch per network on its own stream, joined back into s
+        while ((int)ctx->side.size() < NN) {
+            hipStream_t ns;
+            HIP_OK(hipStreamCreateWithFlags(&ns, hipStreamNonBlocking));
+            ctx->side.push_back(ns);
+            hipEvent_t ev;
+            HIP_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            ctx->side_ev.push_back(ev);
+        }
+        if (!ctx->fork_ev) HIP_OK(hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+        hipStream_t cs = ctx->side[0];  // capture origin: a private stream, never the caller's
+        HIP_OK(hipStreamWaitEvent(cs, ctx->ek0, 0));
+        HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        ibmc_status cst = IBMC_OK;
+        hipError_t ce = launch_fill_u64(ctr, n_ctr, 0ull, cs);
+        if (ce == hipSuccess) ce = launch_fill_u64(ctr + 2, 1, ~0ull, cs);
+        if (ce == hipSuccess) ce = hipEventRecord(ctx->fork_ev, cs);
+        size_t id_off = 0;
+        for (int i = 0; i < NN && ce == hipSuccess && cst == IBMC_OK; ++i) {
+            hipStream_t bs = (i == 0) ? cs : ctx->side[i];
+            if (i > 0) ce = hipStreamWaitEvent(bs, ctx->fork_ev, 0);
+            if (ce == hipSuccess) cst = launch_net(plans[i], id_off, bs);
+            id_off += plans[i].ids.size();
+            if (i > 0 && ce == hipSuccess && cst == IBMC_OK) {
+                ce = hipEventRecord(ctx->side_ev[i], bs);
+                if (ce == hipSuccess) ce = hipStreamWaitEvent(cs, ctx->side_ev[i], 0);
+            }
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t ee = hipStreamEndCapture(cs, &graph);
+        if (cst != IBMC_OK) { if (graph) (void)hipGraphDestroy(graph); return cst; }
+        HIP_OK(ce);
+        HIP_OK(ee);
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIP_OK(ie);
+        const hipError_t le = hipGraphLaunch(exec, cs);
+        if (le == hipSuccess) {
+            HIP_OK(hipEventRecord(ctx->side_ev[0], cs));
+            HIP_OK(hipStreamWaitEvent(s, ctx->side_ev[0], 0));
+        }
+        HIP_OK(hipStreamSynchronize(cs));
+        (void)hipGraphExecDestroy(exec);
+        HIP_OK(le);
+        ctx->graph_launches++;
     }
+    HIP_OK(hipEventRecord(ctx->ek1, s));
+    HIP_OK(hipEventSynchronize(ctx->ek1));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, ctx->ek0, ctx->ek1));
+    kernel_seconds = ms * 1e-3;
+    launches = NN;
     // gather
     std::vector<unsigned long long> h(n_ctr);
     HIP_OK(hipMemcpyAsync(h.data(), ctr, n_ctr * 8, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     rec_total = (int64_t)h[1];
     tie_total = (int64_t)h[3];
-    slot_cex.assign(h.begin() + 8, h.begin() + 8 + B.n_slots);
-    slot_ties.assign(h.begin() + 8 + B.n_slots, h.begin() + 8 + 2 * B.n_slots);
+    slot_cex.assign(h.begin() + sc0, h.begin() + st0);
+    slot_ties.assign(h.begin() + st0, h.begin() + st0 + B.n_slots);
     const int64_t nr = std::min(rec_total, cap), nt = std::min(tie_total, tcap);
     recs.resize(nr);
     ties.resize(nt);
     if (nr) HIP_OK(hipMemcpyAsync(recs.data(), ctx->recs.p, nr * sizeof(CexRec), hipMemcpyDeviceToHost, s));
     if (nt) HIP_OK(hipMemcpyAsync(ties.data(), ctx->ties.p, nt * sizeof(CexRec), hipMemcpyDeviceToHost, s));
-    // clean labels
     HIP_OK(hipMemcpyAsync(B.hprops.data(), ctx->props.p, n_props * sizeof(PropDev), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     if (ctx->flags_host[0]) return fail(IBMC_E_ABORTED, "check aborted");
@@ -478,4 +577,320 @@ extern "C" ibmc_status ibmc_set_variant(ibmc_ctx *ctx, const ibmc_mlp *net, cons
             return IBMC_OK;
         }
     return fail(IBMC_E_INVALID, "unknown variant %s", variant);
+}
+
+// ---------------------------------------------------------------------------
+// ordered search: the same enumeration visited in plain order or in the
+// proposer's order (level 1 by score, level 2 by shells), with the time to
+// the first counterexample observed on the host
+// ---------------------------------------------------------------------------
+
+namespace ibmc {
+
+ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_proposer *p, const uint8_t *image, int rows,
+                           int cols, const int16_t *deltas, int m, const ibmc_check_opts *o, ibmc_check_summary *out,
+                           ibmc_cex *cex_buf) {
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    HIP_OK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const int n = net->dims[0];
+    const int64_t N1 = (int64_t)n * m;
+    const EnumVariant *v = pick_variant(ctx, net);
+    if (!v) return fail(IBMC_E_UNIMPL, "no enumeration kernel for network %s", shape_key(net).c_str());
+    const int CH = v->chunk;
+    ctx->flags_host[0] = 0;
+    ctx->flags_host[1] = 0;
+    HIP_OK(hipEventRecord(ctx->ev0, s));
+    // property
+    PropDev pd;
+    memset(&pd, 0, sizeof(pd));
+    IBMC_TRY(ctx->images.upload(image, n, s));
+    pd.image = ctx->images.as<uint8_t>();
+    pd.m = m;
+    pd.n = n;
+    for (int i = 0; i < m; ++i) pd.deltas[i] = deltas[i];
+    IBMC_TRY(ctx->props.upload(&pd, sizeof(pd), s));
+    const int32_t zero = 0;
+    IBMC_TRY(ctx->prop_ids.upload(&zero, 4, s));
+    IBMC_TRY(ctx->u0_index.upload(&zero, 4, s));
+    IBMC_TRY(ctx->u0.reserve((size_t)net->qd.H[1] * 4));
+    HIP_OK(launch_clean_q8(net->qd, ctx->props.as<PropDev>(), ctx->prop_ids.as<int32_t>(), 1, ctx->u0.as<int32_t>(),
+                           net->qd.H[1], s));
+    // order of the candidates
+    std::vector<int32_t> order;
+    if (p) {
+        PropCand pc;
+        pc.m = m;
+        pc.dmax = 0;
+        for (int i = 0; i < m; ++i) { pc.deltas[i] = deltas[i]; pc.dmax = std::max(pc.dmax, std::abs((int)deltas[i])); }
+        DevBuf feat, sc;
+        const PropParams PP = prop_views(p);
+        IBMC_TRY(feat.reserve((size_t)N1 * kPropF * 4));
+        IBMC_TRY(sc.reserve((size_t)N1 * 4));
+        HIP_OK(launch_prop_features(net->qd, pd.image, rows, cols, pc, feat.as<float>(), s));
+        HIP_OK(launch_prop_score(PP, feat.as<float>(), N1, sc.as<float>(), s));
+        IBMC_TRY(ctx->order.reserve((size_t)N1 * 4));
+        HIP_OK(launch_prop_sort(sc.as<float>(), (int)N1, ctx->order.as<int32_t>(), s));
+        HIP_OK(hipStreamSynchronize(s));  // feat / sc are released here
+    }
+    // jobs: one per level >= 1
+    std::vector<int> lv;
+    for (int k = o->k_min; k <= o->k_max; ++k) lv.push_back(k);
+    std::vector<EnumJob> jobs;
+    std::vector<int64_t> qc, scum;
+    int64_t total = 0;
+    for (size_t li = 0; li < lv.size(); ++li) {
+        const int k = lv[li];
+        if (k == 0) continue;
+        EnumJob J{};
+        J.prop = 0;
+        J.k = k;
+        J.slot = (int)li;
+        J.chunk_begin = total;
+        int64_t ch = 0;
+        if (!p) {
+            J.mode = SEG_PLAIN;
+            ch = plan_plain_level(n, m, k, CH, qc);
+        } else if (k == 1) {
+            J.mode = SEG_LIST1;
+            ch = ceil_div(N1, CH);
+        } else {
+            J.mode = SEG_SHELL;
+            scum.assign(N1, 0);
+            for (int64_t t = 1; t < N1; ++t) scum[t] = (t >= 2 ? scum[t - 1] + ceil_div(t - 1, CH) : 0);
+            ch = scum[N1 - 1] + ceil_div(N1 - 1, CH);
+        }
+        J.chunk_end = total + ch;
+        total += ch;
+        jobs.push_back(J);
+    }
+    const int n_slots = (int)lv.size();
+    const int64_t n_ctr = 8 + 2 * (int64_t)n_slots;
+    IBMC_TRY(ctx->counters.reserve(n_ctr * 8));
+    unsigned long long *ctr = ctx->counters.as<unsigned long long>();
+    HIP_OK(launch_fill_u64(ctr, n_ctr, 0ull, s));
+    HIP_OK(launch_fill_u64(ctr + 2, 1, ~0ull, s));
+    const int64_t cap = o->cex_capacity;
+    IBMC_TRY(ctx->recs.reserve((size_t)std::max<int64_t>(cap, 1) * sizeof(CexRec)));
+    if (!qc.empty()) IBMC_TRY(ctx->qcum.upload(qc.data(), qc.size() * 8, s));
+    DevBuf dscum;
+    if (!scum.empty()) IBMC_TRY(dscum.upload(scum.data(), scum.size() * 8, s));
+    for (auto &J : jobs) {
+        J.qcum = (J.mode == SEG_PLAIN && J.k >= 2) ? ctx->qcum.as<int64_t>() : nullptr;
+        J.order = p ? ctx->order.as<int32_t>() : nullptr;
+        J.shell_cum = (J.mode == SEG_SHELL) ? dscum.as<int64_t>() : nullptr;
+    }
+    double ttfc = -1.0;
+    int64_t rec_total = 0;
+    std::vector<unsigned long long> h(n_ctr);
+    if (!jobs.empty() && total > 0) {
+        IBMC_TRY(ctx->jobs.upload(jobs.data(), jobs.size() * sizeof(EnumJob), s));
+        EnumParams P{};
+        P.net = net->qd;
+        P.jobs = ctx->jobs.as<EnumJob>();
+        P.n_jobs = (int32_t)jobs.size();
+        P.total_chunks = total;
+        P.batch = 1;                                   // visit in order
+        P.props = ctx->props.as<PropDev>();
+        P.queue = ctr + 0;
+        P.rec_count = ctr + 1;
+        P.first_chunk = ctr + 2;
+        P.stop_flag = reinterpret_cast<volatile int32_t *>(ctr + 4);
+        P.abort_host = ctx->flags_dev;
+        P.hit_host = ctx->flags_dev + 1;
+        P.stop_on_first = o->stop_at_first ? 1 : 0;
+        P.rec_cap = cap;
+        P.recs = ctx->recs.as<CexRec>();
+        P.slot_cex = ctr + 8;
+        P.slot_ties = ctr + 8 + n_slots;
+        int maxe = 0;
+        for (int i = 0; i < m; ++i) maxe = std::max(maxe, std::min(255, std::abs((int)deltas[i])));
+        const int64_t M2 = (int64_t)net->qd.f1 * maxe * net->qd.maxw1;
+        P.packed = (net->qd.f1 > 0 && M2 <= 8191 && !ctx->force_int32_layer1) ? 1 : 0;
+        P.vb_lo = (int32_t)(-16385 - M2);
+        P.vb_hi = (int32_t)(16384 + M2);
+        int occ = 0;
+        const int64_t lds = enum_lds_bytes(*v, net->qd);
+        HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, v->fn, 256, (size_t)lds));
+        if (occ < 1) return fail(IBMC_E_UNIMPL, "variant %s does not fit", v->name);
+        const int64_t grid = std::min<int64_t>((int64_t)ctx->n_cu * occ, std::max<int64_t>(1, total));
+        HIP_OK(hipEventRecord(ctx->ek0, s));
+        HIP_OK(launch_enum_q8(*v, (int)grid, P, ctx->u0.as<int32_t>(), net->qd.H[1], ctx->u0_index.as<int32_t>(), s));
+        HIP_OK(hipEventRecord(ctx->ek1, s));
+        // watch the host-mapped first-hit flag while the kernel runs
+        while (true) {
+            if (ttfc < 0 && __atomic_load_n(&ctx->flags_host[1], __ATOMIC_ACQUIRE))
+                ttfc = std::chrono::duration<double>(clk::now() - t0).count();
+            const hipError_t q = hipEventQuery(ctx->ek1);
+            if (q == hipSuccess) break;
+            if (q != hipErrorNotReady) HIP_OK(q);
+        }
+        if (ttfc < 0 && __atomic_load_n(&ctx->flags_host[1], __ATOMIC_ACQUIRE))
+            ttfc = std::chrono::duration<double>(clk::now() - t0).count();
+        float kms = 0.f;
+        HIP_OK(hipEventElapsedTime(&kms, ctx->ek0, ctx->ek1));
+        ctx->last_kernel_seconds = kms * 1e-3;
+        ctx->last_kernel_launches = 1;
+    }
+    HIP_OK(hipMemcpyAsync(h.data(), ctr, n_ctr * 8, hipMemcpyDeviceToHost, s));
+    PropDev back;
+    HIP_OK(hipMemcpyAsync(&back, ctx->props.p, sizeof(back), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    rec_total = (int64_t)h[1];
+    const int64_t nr = std::min(rec_total, cap);
+    std::vector<CexRec> recs(nr);
+    if (nr) HIP_OK(hipMemcpy(recs.data(), ctx->recs.p, nr * sizeof(CexRec), hipMemcpyDeviceToHost));
+    if (p) {
+        order.resize(N1);
+        HIP_OK(hipMemcpy(order.data(), ctx->order.p, N1 * 4, hipMemcpyDeviceToHost));
+    }
+    HIP_OK(hipEventRecord(ctx->ev1, s));
+    HIP_OK(hipEventSynchronize(ctx->ev1));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    std::sort(recs.begin(), recs.end(), rec_less);
+    if (cex_buf && nr) memcpy(cex_buf, recs.data(), nr * sizeof(CexRec));
+
+    // position of every record in the visiting order (hardware independent)
+    int64_t first_pos = -1;
+    {
+        const bool has1 = std::find(lv.begin(), lv.end(), 1) != lv.end();
+        const int64_t off2 = has1 ? N1 : 0;
+        std::vector<int64_t> pos_of(N1, 0), shell_valid_before, same_pix_before;
+        std::vector<std::vector<int32_t>> pix_positions;
+        if (p) {
+            for (int64_t t = 0; t < N1; ++t) pos_of[order[t]] = t;
+            // valid (distinct-pixel) points in shells before t, and per pixel the sorted positions
+            pix_positions.assign(n, {});
+            shell_valid_before.assign(N1 + 1, 0);
+            for (int64_t t = 0; t < N1; ++t) {
+                const int px = order[t] / m;
+                const int64_t same = (int64_t)pix_positions[px].size();
+                shell_valid_before[t + 1] = shell_valid_before[t] + (t - same);
+                pix_positions[px].push_back((int32_t)t);
+            }
+        }
+        std::vector<int64_t> rowstart(n + 1, 0);   // plain level 2: points before first pixel q
+        for (int q = 0; q < n; ++q) rowstart[q + 1] = rowstart[q] + (int64_t)(n - 1 - q) * m * m;
+        for (const CexRec &r : recs) {
+            int64_t pos = -1;
+            int px[2] = {0, 0}, dg[2] = {0, 0};
+            int64_t mk = (r.k == 1) ? m : (int64_t)m * m;
+            int tmp[kMaxK];
+            lex_unrank_subset(r.rank / mk, r.k, n, tmp);
+            int64_t d = r.rank % mk;
+            for (int j = r.k - 1; j >= 0; --j) { dg[j] = (int)(d % m); d /= m; }
+            for (int j = 0; j < r.k; ++j) px[j] = tmp[j];
+            if (r.k == 1) {
+                const int cand = px[0] * m + dg[0];
+                pos = p ? pos_of[cand] : cand;
+            } else if (!p) {
+                pos = off2 + rowstart[px[0]] + (int64_t)dg[0] * (n - 1 - px[0]) * m + (int64_t)(px[1] - px[0] - 1) * m + dg[1];
+            } else {
+                const int64_t a = pos_of[px[0] * m + dg[0]], b = pos_of[px[1] * m + dg[1]];
+                const int64_t t = std::max(a, b), jp = std::min(a, b);
+                const int hp = order[t] / m;
+                const auto &lst = pix_positions[hp];
+                const int64_t same_before_j = std::lower_bound(lst.begin(), lst.end(), (int32_t)jp) - lst.begin();
+                pos = off2 + shell_valid_before[t] + (jp - same_before_j);
+            }
+            if (first_pos < 0 || pos < first_pos) first_pos = pos;
+        }
+    }
+    ibmc_check_summary &S = *out;
+    memset(&S, 0, sizeof(S));
+    S.clean_label = back.label0;
+    S.first_unsafe_k = -1;
+    S.safe_up_to_k = -1;
+    S.n_levels = (int32_t)lv.size();
+    bool unsafe = false;
+    for (size_t li = 0; li < lv.size(); ++li) {
+        const int k = lv[li];
+        S.level_k[li] = k;
+        S.points[li] = binom_small(n, k) * ipow64(m, k);
+        S.cex[li] = k == 0 ? 0 : (int64_t)h[8 + li];
+        S.ties[li] = k == 0 ? back.tie0 : (int64_t)h[8 + n_slots + li];
+        S.points_total += S.points[li];
+        S.cex_total += S.cex[li];
+        if (S.cex[li] > 0 && S.first_unsafe_k < 0) S.first_unsafe_k = k;
+        if (S.cex[li] > 0) unsafe = true;
+        if (!unsafe) S.safe_up_to_k = k;
+    }
+    S.seconds = ms * 1e-3;
+    S.ttfc_seconds = ttfc;
+    S.points_before_first = first_pos;
+    if (rec_total > cap) return IBMC_W_TRUNCATED;
+    return IBMC_OK;
+}
+
+}  // namespace ibmc
+
+// ---------------------------------------------------------------------------
+// autotuner: time every compiled instance that fits the network's shape on a
+// synthetic property (seeded image, deltas +-8, +-16, ...) at level k, keep
+// the fastest for this shape in the context
+// ---------------------------------------------------------------------------
+
+extern "C" ibmc_status ibmc_autotune(ibmc_ctx *ctx, const ibmc_mlp *net, int32_t k, int32_t n_deltas, char *json_out,
+                                     int64_t json_cap) {
+    clear_error();
+    if (!ctx || !net) return fail(IBMC_E_INVALID, "null argument");
+    if (net->act != IBMC_ACT_RELU_Q8) return fail(IBMC_E_UNIMPL, "tuning covers integer networks");
+    if (k < 1 || k > 3 || n_deltas < 1 || n_deltas > kMaxDeltas) return fail(IBMC_E_INVALID, "k %d / n_deltas %d", k, n_deltas);
+    const int n = net->dims[0];
+    std::vector<uint8_t> img(n);
+    uint64_t st = 0x7475ull;
+    for (int i = 0; i < n; ++i) {
+        st = st * 6364136223846793005ull + 1442695040888963407ull;
+        img[i] = (uint8_t)(st >> 56);
+    }
+    std::vector<int16_t> D(n_deltas);
+    for (int i = 0; i < n_deltas; ++i) D[i] = (int16_t)((i % 2 ? 1 : -1) * 8 * (1 + i / 2));
+    int nv = 0;
+    const EnumVariant *vs = enum_variants(&nv);
+    const int kb1 = net->qd.H[1] / 64, kb2 = (net->L == 3) ? net->qd.H[2] / 64 : 0;
+    ibmc_mlp *m = const_cast<ibmc_mlp *>(net);
+    const std::string saved = m->forced_variant;
+    std::string json = "{\"shape\": \"" + shape_key(net) + "\", \"k\": " + std::to_string(k) + ", \"variants\": [";
+    double best_t = 1e30;
+    std::string best;
+    bool first = true;
+    ibmc_check_opts o{};
+    o.k_min = k;
+    o.k_max = k;
+    o.k_step = 1;
+    o.cex_capacity = 0;
+    for (int i = 0; i < nv; ++i) {
+        const EnumVariant &v = vs[i];
+        if (v.L != net->L || v.kb1 != kb1 || v.kb2 != kb2) continue;
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, v.fn, 256, (size_t)enum_lds_bytes(v, net->qd)) !=
+                hipSuccess || occ < 1)
+            continue;
+        m->forced_variant = v.name;
+        ibmc_check_summary S;
+        double tmin = 1e30;
+        for (int rep = 0; rep < 3; ++rep) {
+            ibmc_status rc = ibmc_check_property(ctx, net, img.data(), n, D.data(), n_deltas, &o, &S, nullptr, nullptr);
+            if (rc < 0 && rc != IBMC_W_TRUNCATED) { m->forced_variant = saved; return rc; }
+            tmin = std::min(tmin, ctx->last_kernel_seconds);
+        }
+        const double pps = tmin > 0 ? (double)S.points_total / tmin : 0.0;
+        if (!first) json += ", ";
+        first = false;
+        json += "{\"name\": \"" + std::string(v.name) + "\", \"kernel_s\": " + std::to_string(tmin) +
+                ", \"points_per_s\": " + std::to_string(pps) + ", \"occupancy\": " + std::to_string(occ) + "}";
+        if (tmin < best_t) { best_t = tmin; best = v.name; }
+    }
+    m->forced_variant = saved;
+    if (best.empty()) return fail(IBMC_E_UNIMPL, "no kernel instance for %s", shape_key(net).c_str());
+    ctx->tuned[shape_key(net)] = best;
+    json += "], \"best\": \"" + best + "\"}";
+    if (json_out && json_cap > 0) {
+        const size_t nbytes = std::min<size_t>(json.size(), (size_t)json_cap - 1);
+        memcpy(json_out, json.data(), nbytes);
+        json_out[nbytes] = 0;
+    }
+    return IBMC_OK;
 }

@@ -63,8 +63,14 @@ struct ibmc_ctx {
     // scratch of the check driver (grow-only)
     ibmc::DevBuf images, props, jobs, qcum, u0, u0_index, prop_ids, counters, recs, ties, order;
     ibmc::DevBuf u0f;
+    ibmc::DevBuf cov_img, cov_pots, cov_bits, cov_sums, cov_out;
     // tuned kernel variant per network shape key
     std::map<std::string, std::string> tuned;
+    std::vector<hipStream_t> side;     // branch streams of captured batch graphs (default priority)
+    std::vector<hipEvent_t> side_ev;
+    hipEvent_t fork_ev = nullptr;
+    int64_t graph_launches = 0;
+    bool force_int32_layer1 = false;   // testing aid: take the general first-layer path
     double last_kernel_seconds = 0.0;
     int last_kernel_launches = 0;
     ~ibmc_ctx();
@@ -82,6 +88,7 @@ struct ibmc_mlp {
     std::vector<std::vector<float>> bf;
     std::deque<ibmc::DevBuf> buf;      // device copies (stable addresses)
     ibmc::QNetDev qd;
+    ibmc::FwdExtra fx;
     ibmc::FNetDev fd;
     std::string forced_variant;
     ~ibmc_mlp();
@@ -89,4 +96,5 @@ struct ibmc_mlp {
 
 namespace ibmc {
 std::string shape_key(const ibmc_mlp *m);
+PropParams prop_views(const ibmc_proposer *p);
 }

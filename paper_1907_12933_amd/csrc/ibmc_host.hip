@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -93,6 +94,9 @@ extern "C" ibmc_status ibmc_ctx_create(int32_t device, void *hip_stream, ibmc_ct
     c->n_cu = prop.multiProcessorCount;
     c->arch_major = prop.major;
     c->arch_minor = prop.minor;
+    // testing aid: IBMC_FIRST_LAYER=int32 forces the general (int32) first-layer path
+    const char *fl = getenv("IBMC_FIRST_LAYER");
+    c->force_int32_layer1 = fl && std::string(fl) == "int32";
     if (hip_stream) {
         c->stream = reinterpret_cast<hipStream_t>(hip_stream);
         c->own_stream = false;
@@ -124,6 +128,9 @@ ibmc_ctx::~ibmc_ctx() {
     if (ek0) (void)hipEventDestroy(ek0);
     if (ek1) (void)hipEventDestroy(ek1);
     if (flags_host) (void)hipHostFree(flags_host);
+    for (hipStream_t st : side) (void)hipStreamDestroy(st);
+    for (hipEvent_t ev : side_ev) (void)hipEventDestroy(ev);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
 }
 
 extern "C" void ibmc_ctx_destroy(ibmc_ctx *ctx) { delete ctx; }
@@ -196,6 +203,16 @@ static ibmc_status build_q8(ibmc_ctx *ctx, ibmc_mlp *m) {
     }
     IBMC_TRY(m->buf.emplace_back().upload(w1t.data(), w1t.size(), s));
     q.W1T = (const int8_t *)m->buf.back().p;
+    // scaled int16 copy for the packed first-layer path: f1 = 2^(8 - shift)
+    q.f1 = (L > 1 && m->shift[0] <= 8) ? (1 << (8 - m->shift[0])) : 0;
+    q.maxw1 = 0;
+    for (int8_t w : m->Wq[0]) q.maxw1 = std::max(q.maxw1, std::abs((int)w));
+    {
+        std::vector<int16_t> w16(w1t.size());
+        for (size_t t = 0; t < w1t.size(); ++t) w16[t] = (int16_t)(w1t[t] * std::max(q.f1, 1));
+        IBMC_TRY(m->buf.emplace_back().upload(w16.data(), w16.size() * 2, s));
+        q.W1T16 = (const int16_t *)m->buf.back().p;
+    }
     IBMC_TRY(m->buf.emplace_back().upload(b1s.data(), b1s.size() * 4, s));
     q.b1s = (const int32_t *)m->buf.back().p;
     IBMC_TRY(m->buf.emplace_back().upload(b1n.data(), b1n.size() * 4, s));
@@ -235,10 +252,61 @@ static ibmc_status build_q8(ibmc_ctx *ctx, ibmc_mlp *m) {
                     }
         IBMC_TRY(m->buf.emplace_back().upload(t.data(), t.size(), s));
         q.Wt[l] = (const int8_t *)m->buf.back().p;
-        std::vector<int32_t> bb(Hout, 0);
-        for (int j = 0; j < nout; ++j) bb[j] = m->bq[l - 1][j];
+        std::vector<int32_t> bb(Hout, 0), bo(Hout, 0);
+        for (int j = 0; j < nout; ++j) {
+            bb[j] = m->bq[l - 1][j];
+            // inputs arrive as a - 64: add back 64 * rowsum; hidden outputs are
+            // requantised from u - 64 * 2^s
+            int64_t rs = 0;
+            for (int i = 0; i < nin; ++i) rs += m->Wq[l - 1][(size_t)j * nin + i];
+            int64_t v = (int64_t)m->bq[l - 1][j] + 64 * rs;
+            if (l < L) v -= (int64_t)64 << m->shift[l - 1];
+            bo[j] = (int32_t)v;
+        }
         IBMC_TRY(m->buf.emplace_back().upload(bb.data(), bb.size() * 4, s));
         q.bn[l] = (const int32_t *)m->buf.back().p;
+        IBMC_TRY(m->buf.emplace_back().upload(bo.data(), bo.size() * 4, s));
+        q.bo[l] = (const int32_t *)m->buf.back().p;
+    }
+    // batched forward: natural-K tiles of layers >= 2 and accumulator inits
+    {
+        FwdExtra &fx = m->fx;
+        memset(&fx, 0, sizeof(fx));
+        fx.K0 = round_up(n, 64);
+        for (int l = 2; l <= L; ++l) {
+            const int Hin = q.H[l - 1], Hout = q.H[l], nin = m->dims[l - 1], nout = m->dims[l];
+            const int KB = Hin / 64, MT = Hout / 16;
+            std::vector<int8_t> t((size_t)MT * KB * 1024, 0);
+            for (int mt = 0; mt < MT; ++mt)
+                for (int kb = 0; kb < KB; ++kb)
+                    for (int lane = 0; lane < 64; ++lane)
+                        for (int b = 0; b < 16; ++b) {
+                            const int row = mt * 16 + (lane & 15);
+                            const int col = kb * 64 + (lane >> 4) * 16 + b;
+                            if (row < nout && col < nin)
+                                t[(((size_t)mt * KB + kb) * 64 + lane) * 16 + b] = m->Wq[l - 1][(size_t)row * nin + col];
+                        }
+            IBMC_TRY(m->buf.emplace_back().upload(t.data(), t.size(), s));
+            fx.Wn[l] = (const int8_t *)m->buf.back().p;
+        }
+        for (int l = 1; l <= L; ++l) {
+            const int nin = m->dims[l - 1], nout = m->dims[l];
+            std::vector<int32_t> init(q.H[l], 0);
+            const bool hidden = l < L;
+            for (int j = 0; j < q.H[l]; ++j) {
+                int64_t v = 0;
+                if (j < nout) {
+                    int64_t rs = 0;
+                    for (int i = 0; i < nin; ++i) rs += m->Wq[l - 1][(size_t)j * nin + i];
+                    // layer 1 reads x - 128, later layers a - 64
+                    v = (int64_t)m->bq[l - 1][j] + (l == 1 ? 128 : 64) * rs;
+                }
+                if (hidden) v -= (int64_t)64 << m->shift[l - 1];
+                init[j] = (int32_t)v;
+            }
+            IBMC_TRY(m->buf.emplace_back().upload(init.data(), init.size() * 4, s));
+            fx.init[l] = (const int32_t *)m->buf.back().p;
+        }
     }
     // dense row-major copies
     for (int l = 1; l <= L; ++l) {
@@ -385,8 +453,8 @@ extern "C" ibmc_status ibmc_forward(ibmc_ctx *ctx, const ibmc_mlp *net, const ui
     IBMC_TRY(dlab.reserve((size_t)n_images * 4));
     if (potentials) IBMC_TRY(dpot.reserve((size_t)n_images * U * 4));
     if (net->act == IBMC_ACT_RELU_Q8) {
-        HIP_OK(launch_forward_q8(net->qd, (const uint8_t *)dimg.p, n_images, (int32_t *)dlab.p,
-                                 potentials ? (int32_t *)dpot.p : nullptr, U, s));
+        HIP_OK(launch_fwd_pots_q8(net->qd, net->fx, (const uint8_t *)dimg.p, n_images,
+                                  potentials ? (int32_t *)dpot.p : nullptr, U, (int32_t *)dlab.p, s));
     } else {
         HIP_OK(launch_forward_f32(net->fd, (const uint8_t *)dimg.p, n_images, (int32_t *)dlab.p,
                                   potentials ? (float *)dpot.p : nullptr, U, s));

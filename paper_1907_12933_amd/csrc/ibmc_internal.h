@@ -52,6 +52,11 @@ struct QNetDev {
     int H[kMaxLayers + 1];             // padded widths (H[0] = pixels, unpadded)
     int shift[kMaxLayers];             // per hidden layer (index l-1)
     const int8_t *W1T;                 // [n][H1], sigma order
+    const int16_t *W1T16;              // [n][H1], sigma order, f1 * W1 (packed first-layer path)
+    int f1;                            // 2^(8 - shift[0]) if shift[0] <= 8, else 0
+    int maxw1;                         // max |W1|
+    const int32_t *bo[kMaxLayers + 1]; // l >= 2: bias with the a - 64 input offset (and the
+                                       // hidden requantiser offset) folded in, natural order
     const int32_t *b1s;                // [H1], sigma order
     const int8_t *Wt[kMaxLayers + 1];  // l >= 2: A-operand tiles
     const int32_t *bn[kMaxLayers + 1]; // l >= 2: bias, natural order, padded to H[l]
@@ -131,7 +136,8 @@ struct EnumParams {
     volatile int32_t *abort_host;      // host-mapped abort request (nullable), polled per queue fetch
     volatile int32_t *hit_host;        // host-mapped, set on the first counterexample (nullable)
     int32_t stop_on_first;
-    int32_t pad;
+    int32_t packed;                    // packed int16 first layer (bound checked by the host)
+    int32_t vb_lo, vb_hi;              // pre-clamp of the scaled base for the packed path
 };
 
 // Float enumeration parameters.

@@ -5,6 +5,9 @@
 
 namespace ibmc {
 
+// default near-tie threshold of the float path, relative to max(1, |largest logit|)
+constexpr float kDefaultTieRel = 1e-4f;
+
 hipError_t launch_forward_f32(const FNetDev &net, const uint8_t *images, int64_t n_images,
                               int32_t *labels, float *pots, int64_t pot_stride, hipStream_t s);
 hipError_t launch_replay_f32(const FNetDev &net, const uint8_t *clean, const int16_t *deltas, int m,

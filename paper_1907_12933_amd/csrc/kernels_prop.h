@@ -4,4 +4,41 @@
 #include "ibmc_internal.h"
 
 namespace ibmc {
+
+constexpr int kPropF = 32;
+constexpr int kPropH = 128;
+constexpr int kPropParams = kPropH * kPropF + kPropH + kPropH + 1;   // W1, b1, w2, c (flat, in this order)
+
+// Views into the flat fp32 parameter vector.
+struct PropParams {
+    const float *W1;   // [128][32]
+    const float *b1;   // [128]
+    const float *w2;   // [128]
+    const float *c;    // [1]
+};
+
+struct PropGrads {
+    float *gW1, *gb1, *gw2, *gc;
+    float *loss;
+};
+
+// Candidate set of one image: the delta set and its largest magnitude.
+struct PropCand {
+    int m;
+    int dmax;
+    int16_t deltas[kMaxDeltas];
+};
+
+hipError_t launch_prop_features(const QNetDev &net, const uint8_t *image, int rows, int cols, const PropCand &pc,
+                                float *feat, hipStream_t s);
+hipError_t launch_prop_score(const PropParams &P, const float *feat, int64_t N, float *scores, hipStream_t s);
+hipError_t launch_prop_train(const PropParams &P, const float *feat, const float *labels, const int32_t *index,
+                             int64_t begin, int64_t count, float inv_b, float pw, const PropGrads &G, int n_cu,
+                             hipStream_t s);
+hipError_t launch_prop_adam(float *theta, float *grad, float *mom, float *vel, int n, float lr, float b1, float b2,
+                            float eps, float c1, float c2, hipStream_t s);
+int prop_sort_max();
+hipError_t launch_prop_sort(const float *scores, int N, int32_t *order, hipStream_t s);
+hipError_t launch_label_candidates(int n, int m, const CexRec *recs, int64_t nrec, float *labels, hipStream_t s);
+
 }  // namespace ibmc

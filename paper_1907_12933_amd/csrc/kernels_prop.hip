@@ -1,0 +1,397 @@
+// Learned proposal network: candidate features, bf16 MFMA forward (scoring),
+// fused forward/backward with the weight gradient on bf16 MFMA, Adam, a
+// single-workgroup bitonic sort of the scores, and candidate labels from
+// counterexample records.
+//
+// Network: s = w2 . relu(W1 f + b1) + c with f in R^32, hidden 128.
+// v_mfma_f32_16x16x32_bf16, orientation out[hidden x samples] = W1 x F^T:
+// A = 16 hidden rows x 32 features (8 bf16 per lane), B = 32 features x 16
+// samples; the accumulator leaves lane (j + 16 g) with hidden 4g..4g+3 of
+// sample j.
+#include "kernels_prop.h"
+
+namespace ibmc {
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }  // round to nearest even
+
+// ---------------------------------------------------------------------------
+// features (one workgroup per image)
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) prop_features_kernel(QNetDev net, const uint8_t *image, int rows, int cols,
+                                                            PropCand pc, float *feat) {
+    __shared__ int xs[kMaxWidth];
+    __shared__ unsigned char live[kMaxWidth];
+    __shared__ float n1[kMaxWidth], n2[kMaxWidth], nl[kMaxWidth];
+    __shared__ float red[3][256];
+    const int tid = threadIdx.x;
+    const int n = net.dims[0], H1 = net.H[1];
+    for (int i = tid; i < n; i += blockDim.x) xs[i] = image[i];
+    __syncthreads();
+    // clean first-layer potentials (sigma order) and the requantiser's linear window
+    const int top = 128 << net.shift[0];
+    for (int q = tid; q < H1; q += blockDim.x) {
+        int u = net.b1s[q];
+        for (int i = 0; i < n; ++i) u += (int)net.W1T[(int64_t)i * H1 + q] * xs[i];
+        live[q] = (sigma64(q) < net.dims[1]) && u >= 0 && u < top;
+    }
+    __syncthreads();
+    float m1 = 0.f, m2 = 0.f, ml = 0.f;
+    for (int p = tid; p < n; p += blockDim.x) {
+        int s1 = 0, sl = 0;
+        long long s2 = 0;
+        const int8_t *col = net.W1T + (int64_t)p * H1;
+        for (int q = 0; q < H1; ++q) {
+            const int w = col[q];
+            const int aw = w < 0 ? -w : w;
+            s1 += aw;
+            s2 += (long long)w * w;
+            if (live[q]) sl += aw;
+        }
+        n1[p] = (float)s1;
+        n2[p] = sqrtf((float)s2);
+        nl[p] = (float)sl;
+        m1 = fmaxf(m1, n1[p]);
+        m2 = fmaxf(m2, n2[p]);
+        ml = fmaxf(ml, nl[p]);
+    }
+    red[0][tid] = m1; red[1][tid] = m2; red[2][tid] = ml;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (tid < st)
+            for (int z = 0; z < 3; ++z) red[z][tid] = fmaxf(red[z][tid], red[z][tid + st]);
+        __syncthreads();
+    }
+    const float M1 = fmaxf(red[0][0], 1.f), M2 = fmaxf(red[1][0], 1.f), ML = fmaxf(red[2][0], 1.f);
+    const float rden = rows > 1 ? (float)(rows - 1) : 1.f, cden = cols > 1 ? (float)(cols - 1) : 1.f;
+    const int m = pc.m;
+    const float dmax = fmaxf((float)pc.dmax, 1.f);
+    for (int t = tid; t < n * m; t += blockDim.x) {
+        const int p = t / m, i = t - p * m;
+        const int r = p / cols, c = p - r * cols;
+        const int x = xs[p];
+        const int d = pc.deltas[i];
+        const int e = min(max(x + d, 0), 255) - x;
+        float *f = feat + (int64_t)t * 32;
+        f[0] = (float)r / rden;
+        f[1] = (float)c / cden;
+        f[2] = (float)x / 255.f;
+        f[3] = (float)d / dmax;
+        f[4] = (float)e / dmax;
+        f[5] = n1[p] / M1;
+        f[6] = n2[p] / M2;
+        f[7] = nl[p] / ML;
+        f[8] = 1.f;
+        for (int z = 9; z < 32; ++z) f[z] = 0.f;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// forward scores
+// ---------------------------------------------------------------------------
+
+// Stage the bf16 copy of W1 in LDS as A operands: [8 tiles][64 lanes][8 bf16].
+__device__ __forceinline__ void stage_w1(const PropParams &P, v8bf *wt) {
+    for (int t = threadIdx.x; t < 8 * 64; t += blockDim.x) {
+        const int mt = t / 64, ln = t % 64, r = ln & 15, g = ln >> 4;
+        v8bf v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = to_bf16(P.W1[(mt * 16 + r) * 32 + g * 8 + e]);
+        wt[t] = v;
+    }
+}
+
+__device__ __forceinline__ v8bf load_feat_bf16(const float *f) {
+    const float4 a = *reinterpret_cast<const float4 *>(f), b = *reinterpret_cast<const float4 *>(f + 4);
+    v8bf v;
+    v[0] = to_bf16(a.x); v[1] = to_bf16(a.y); v[2] = to_bf16(a.z); v[3] = to_bf16(a.w);
+    v[4] = to_bf16(b.x); v[5] = to_bf16(b.y); v[6] = to_bf16(b.z); v[7] = to_bf16(b.w);
+    return v;
+}
+
+__global__ void __launch_bounds__(256) prop_score_kernel(PropParams P, const float *feat, int64_t N, float *scores) {
+    __shared__ v8bf wt[8 * 64];
+    stage_w1(P, wt);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    const int64_t waves = (int64_t)gridDim.x * 4;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile * 16 < N; tile += waves) {
+        const int64_t s = tile * 16 + j;
+        v8bf B;
+        if (s < N) B = load_feat_bf16(feat + s * 32 + g * 8);
+        else for (int e = 0; e < 8; ++e) B[e] = to_bf16(0.f);
+        float part = 0.f;
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            v4f acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wt[mt * 64 + lane], B, acc, 0, 0, 0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int h = mt * 16 + g * 4 + t;
+                part += P.w2[h] * fmaxf(acc[t] + P.b1[h], 0.f);
+            }
+        }
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (g == 0 && s < N) scores[s] = part + P.c[0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fused forward / backward of one minibatch
+// ---------------------------------------------------------------------------
+
+// Each wave takes 32 samples (two 16-sample N-tiles) per iteration.  LDS per
+// wave: gh^T as bf16 [128 hidden][32 samples] and the samples' features as
+// bf16 [32][32]; then dW1 += GH^T F on MFMA (K = samples).
+__global__ void __launch_bounds__(256) prop_train_kernel(PropParams P, const float *feat, const float *labels,
+                                                         const int32_t *index, int64_t begin, int64_t count,
+                                                         float inv_b, float pw, PropGrads G) {
+    __shared__ v8bf wt[8 * 64];
+    __shared__ __bf16 ghT[4][128][40];          // [wave][hidden][sample] (+8 pad)
+    __shared__ __bf16 fs[4][32][40];            // [wave][sample][feature] (+8 pad)
+    __shared__ float hval[4][128][33];          // relu(h) for dw2
+    __shared__ float gsv[4][32];
+    stage_w1(P, wt);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    v4f dW[8][2];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 2; ++b) dW[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    float gb1_part[2] = {0.f, 0.f}, gw2_part[2] = {0.f, 0.f};  // hidden lane and lane + 64
+    float gc_part = 0.f, loss_part = 0.f;
+    const int64_t waves = (int64_t)gridDim.x * 4;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile * 32 < count; tile += waves) {
+        // forward of 2 x 16 samples
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            const int64_t r = tile * 32 + nt * 16 + j;
+            const bool ok = r < count;
+            const int64_t s = ok ? (index ? index[begin + r] : begin + r) : 0;
+            v8bf B;
+            if (ok) B = load_feat_bf16(feat + s * 32 + g * 8);
+            else for (int e = 0; e < 8; ++e) B[e] = to_bf16(0.f);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) fs[wave][nt * 16 + j][g * 8 + e] = B[e];
+            float part = 0.f;
+            float hp[8][4];
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt) {
+                v4f acc = {0.f, 0.f, 0.f, 0.f};
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wt[mt * 64 + lane], B, acc, 0, 0, 0);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int h = mt * 16 + g * 4 + t;
+                    hp[mt][t] = acc[t] + P.b1[h];
+                    const float hr = fmaxf(hp[mt][t], 0.f);
+                    hval[wave][h][nt * 16 + j] = hr;
+                    part += P.w2[h] * hr;
+                }
+            }
+            part += __shfl_xor(part, 16);
+            part += __shfl_xor(part, 32);
+            const float sc = part + P.c[0];
+            const float y = ok ? labels[s] : 0.f;
+            // loss = pw y softplus(-s) + (1 - y) softplus(s); d loss / d s = sig (pw y + 1 - y) - pw y
+            const float sig = 1.f / (1.f + expf(-sc));
+            const float sp_pos = sc > 0.f ? sc + log1pf(expf(-sc)) : log1pf(expf(sc));
+            const float sp_neg = sp_pos - sc;
+            const float gs = ok ? (sig * (pw * y + 1.f - y) - pw * y) * inv_b : 0.f;
+            if (g == 0 && ok) {
+                loss_part += (pw * y * sp_neg + (1.f - y) * sp_pos) * inv_b;
+                gc_part += gs;
+            }
+            if (g == 0) gsv[wave][nt * 16 + j] = gs;
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int h = mt * 16 + g * 4 + t;
+                    const float gh = hp[mt][t] > 0.f ? gs * P.w2[h] : 0.f;
+                    ghT[wave][h][nt * 16 + j] = to_bf16(gh);
+                }
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+        // dW1 (128 x 32) += GH^T (128 x 32 samples) * F (32 samples x 32 features)
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            v8bf A;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) A[e] = ghT[wave][mt * 16 + j][g * 8 + e];
+#pragma unroll
+            for (int ntf = 0; ntf < 2; ++ntf) {
+                v8bf Bf;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) Bf[e] = fs[wave][g * 8 + e][ntf * 16 + j];
+                dW[mt][ntf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bf, dW[mt][ntf], 0, 0, 0);
+            }
+        }
+        // gb1, gw2 (fp32 sums over the 32 samples; lane owns hidden lane and lane + 64)
+#pragma unroll
+        for (int z = 0; z < 2; ++z) {
+            const int h = lane + 64 * z;
+            float sb = 0.f, sw = 0.f;
+            for (int q = 0; q < 32; ++q) {
+                const float gsq = gsv[wave][q];
+                const float hv = hval[wave][h][q];
+                sw += gsq * hv;
+                sb += hv > 0.f ? gsq * P.w2[h] : 0.f;
+            }
+            gb1_part[z] += sb;
+            gw2_part[z] += sw;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    // flush: dW tile (mt, ntf): lane (j + 16 g) holds rows 16 mt + 4 g + t, column 16 ntf + j
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+        for (int ntf = 0; ntf < 2; ++ntf)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float v = dW[mt][ntf][t];
+                if (v != 0.f) atomicAdd(G.gW1 + (mt * 16 + g * 4 + t) * 32 + ntf * 16 + j, v);
+            }
+#pragma unroll
+    for (int z = 0; z < 2; ++z) {
+        if (gb1_part[z] != 0.f) atomicAdd(G.gb1 + lane + 64 * z, gb1_part[z]);
+        if (gw2_part[z] != 0.f) atomicAdd(G.gw2 + lane + 64 * z, gw2_part[z]);
+    }
+    for (int sh = 32; sh >= 1; sh >>= 1) {
+        gc_part += __shfl_xor(gc_part, sh);
+        loss_part += __shfl_xor(loss_part, sh);
+    }
+    if (lane == 0) {
+        atomicAdd(G.gc, gc_part);
+        atomicAdd(G.loss, loss_part);
+    }
+}
+
+// Adam (Kingma & Ba) on the flat parameter vector; zeroes the gradients.
+__global__ void __launch_bounds__(256) prop_adam_kernel(float *theta, float *grad, float *mom, float *vel, int n,
+                                                        float lr, float b1, float b2, float eps, float c1, float c2) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float g = grad[i];
+        const float m = b1 * mom[i] + (1.f - b1) * g;
+        const float v = b2 * vel[i] + (1.f - b2) * g * g;
+        mom[i] = m;
+        vel[i] = v;
+        theta[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+        grad[i] = 0.f;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// ordering: bitonic sort of (score desc, id asc) in one workgroup's LDS
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ unsigned order_key(float s) {
+    // monotone float -> uint map, then inverted so that larger scores come first
+    const unsigned b = __float_as_uint(s);
+    const unsigned u = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+    return ~u;
+}
+
+__global__ void __launch_bounds__(1024) prop_sort_kernel(const float *scores, int N, int32_t *order) {
+    extern __shared__ unsigned long long keys[];
+    int P2 = 1;
+    while (P2 < N) P2 <<= 1;
+    for (int t = threadIdx.x; t < P2; t += blockDim.x)
+        keys[t] = t < N ? ((unsigned long long)order_key(scores[t]) << 32) | (unsigned)t : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= P2; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int t = threadIdx.x; t < P2; t += blockDim.x) {
+                const int partner = t ^ jj;
+                if (partner > t) {
+                    const bool up = (t & k) == 0;
+                    const unsigned long long a = keys[t], b = keys[partner];
+                    if ((a > b) == up) { keys[t] = b; keys[partner] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = threadIdx.x; t < N; t += blockDim.x) order[t] = (int32_t)(keys[t] & 0xffffffffu);
+}
+
+// ---------------------------------------------------------------------------
+// candidate labels: every (pixel, delta) that occurs in a counterexample
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) label_candidates_kernel(int n, int m, const CexRec *recs, int64_t nrec,
+                                                               float *labels) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nrec;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int k = recs[r].k;
+        if (k < 1 || k > kMaxK) continue;
+        int64_t mk = 1;
+        for (int j = 0; j < k; ++j) mk *= m;
+        int p[kMaxK];
+        lex_unrank_subset(recs[r].rank / mk, k, n, p);
+        int64_t d = recs[r].rank % mk;
+        for (int j = k - 1; j >= 0; --j) {
+            labels[(int64_t)p[j] * m + (int)(d % m)] = 1.f;
+            d /= m;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_prop_features(const QNetDev &net, const uint8_t *image, int rows, int cols, const PropCand &pc,
+                                float *feat, hipStream_t s) {
+    hipLaunchKernelGGL(prop_features_kernel, dim3(1), dim3(256), 0, s, net, image, rows, cols, pc, feat);
+    return hipGetLastError();
+}
+
+hipError_t launch_prop_score(const PropParams &P, const float *feat, int64_t N, float *scores, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>((N + 63) / 64, 2048);
+    hipLaunchKernelGGL(prop_score_kernel, dim3(grid), dim3(256), 0, s, P, feat, N, scores);
+    return hipGetLastError();
+}
+
+hipError_t launch_prop_train(const PropParams &P, const float *feat, const float *labels, const int32_t *index,
+                             int64_t begin, int64_t count, float inv_b, float pw, const PropGrads &G, int n_cu,
+                             hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>((count + 127) / 128, (int64_t)n_cu * 2);
+    hipLaunchKernelGGL(prop_train_kernel, dim3(grid), dim3(256), 0, s, P, feat, labels, index, begin, count, inv_b,
+                       pw, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_prop_adam(float *theta, float *grad, float *mom, float *vel, int n, float lr, float b1, float b2,
+                            float eps, float c1, float c2, hipStream_t s) {
+    hipLaunchKernelGGL(prop_adam_kernel, dim3((n + 255) / 256), dim3(256), 0, s, theta, grad, mom, vel, n, lr, b1, b2,
+                       eps, c1, c2);
+    return hipGetLastError();
+}
+
+int prop_sort_max() { return 16384; }
+
+hipError_t launch_prop_sort(const float *scores, int N, int32_t *order, hipStream_t s) {
+    int P2 = 1;
+    while (P2 < N) P2 <<= 1;
+    hipLaunchKernelGGL(prop_sort_kernel, dim3(1), dim3(1024), (size_t)P2 * 8, s, scores, N, order);
+    return hipGetLastError();
+}
+
+hipError_t launch_label_candidates(int n, int m, const CexRec *recs, int64_t nrec, float *labels, hipStream_t s) {
+    if (nrec <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>((nrec + 255) / 256, 4096);
+    hipLaunchKernelGGL(label_candidates_kernel, dim3(grid), dim3(256), 0, s, n, m, recs, nrec, labels);
+    return hipGetLastError();
+}
+
+}  // namespace ibmc

@@ -132,6 +132,7 @@ SIGNATURES = {
     "ibmc_proposer_grad": (I32, [VP, VP, P_F32, P_F32, I32, C.c_float, P_F32, P_F32, P_F32, P_F32, P_F32]),
     "ibmc_proposer_train": (I32, [VP, VP, P_F32, P_F32, I64, C.POINTER(ibmc_train_opts), P_F32]),
     "ibmc_proposer_score": (I32, [VP, VP, VP, P_U8, I32, I32, P_I16, I32, P_F32]),
+    "ibmc_label_candidates": (I32, [VP, I32, I32, P_CEX, I64, P_F32]),
     "ibmc_check_property_ranked": (I32, [VP, VP, VP, P_U8, I32, I32, I32, P_I16, I32, P_OPTS, P_SUM, P_CEX]),
     "ibmc_autotune": (I32, [VP, VP, I32, I32, C.c_char_p, I64]),
     "ibmc_set_variant": (I32, [VP, VP, C.c_char_p]),
@@ -530,6 +531,15 @@ def ibmc_proposer_score(ctx, prop, net, image, rows, cols, deltas):
     _ck(lib().ibmc_proposer_score(ctx.handle, prop.handle, net.handle, _ptr(image, P_U8), rows, cols,
                                   _ptr(D, P_I16), D.size, _ptr(s, P_F32)))
     return s
+
+
+def ibmc_label_candidates(ctx, n_pixels, n_deltas, recs):
+    """1.0 for every (pixel, delta index) candidate that occurs in the records, else 0.0."""
+    recs = np.ascontiguousarray(recs, CEX_DTYPE)
+    out = np.zeros(n_pixels * n_deltas, np.float32)
+    _ck(lib().ibmc_label_candidates(ctx.handle, n_pixels, n_deltas, recs.ctypes.data_as(P_CEX), len(recs),
+                                    _ptr(out, P_F32)))
+    return out
 
 
 def ibmc_check_property_ranked(ctx, net, prop, image, rows, cols, deltas, k_min=1, k_max=2, stop_at_first=False,

@@ -158,3 +158,29 @@ def test_load_errors(ctx):
     with pytest.raises(ibmc.IbmcError) as e:
         ibmc.Mlp(ctx, rng_net)
     assert e.value.code == ibmc.IBMC_E_RANGE
+
+
+def test_general_first_layer_path(orc, monkeypatch):
+    """The int32 first-layer path (taken when the packed int16 bound fails)
+    gives the same records: forced on the same inputs, and reached naturally
+    with deltas whose update bound exceeds the packed range."""
+    from paper_1907_12933_amd import ibmc
+    monkeypatch.setenv("IBMC_FIRST_LAYER", "int32")
+    ctx32 = ibmc.Context(0)
+    monkeypatch.delenv("IBMC_FIRST_LAYER")
+    g = I.rng(31)
+    net = I.random_qnet(g, [24, 64, 16, 5], shift=4, wmax=12, bmax=200)
+    m = ibmc.Mlp(ctx32, net)
+    D = np.array([-48, -16, 16, 48], np.int16)
+    x = g.integers(0, 255, size=24, endpoint=True).astype(np.uint8)
+    s, cex, _ = ibmc.ibmc_check_property(ctx32, m, x, D, 1, 2)
+    assert_same(s, cex, orc.q8_check(net, x, D, 1, 2))
+    # natural: 8-bit shift scale 2^(8-7)=2, |d| up to 200, |w| up to 64 -> 25600 > 8191
+    net2 = I.random_qnet(g, [40, 64, 64, 10], shift=7, wmax=64, bmax=500)
+    ctx = ibmc.Context(0)
+    m2 = ibmc.Mlp(ctx, net2)
+    D2 = np.array([-200, -100, 100, 200], np.int16)
+    for t in range(2):
+        x2 = g.integers(0, 255, size=40, endpoint=True).astype(np.uint8)
+        s, cex, _ = ibmc.ibmc_check_property(ctx, m2, x2, D2, 1, 2)
+        assert_same(s, cex, orc.q8_check(net2, x2, D2, 1, 2))

@@ -1,0 +1,121 @@
+"""GPU parity of the learned proposal network: features against the oracle,
+bf16 MFMA gradients against the FP64 oracle gradients, training, the
+bitonic ordering, and the ordered search keeping the plain verdicts."""
+import numpy as np
+import pytest
+
+from paper_1907_12933_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1907_12933_amd import ibmc
+    return ibmc.Context(0)
+
+
+def bf16_round(a):
+    """Round-to-nearest-even to bfloat16, returned as float64."""
+    a = np.ascontiguousarray(a, np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def test_features_match_oracle(ctx, orc):
+    from paper_1907_12933_amd import ibmc
+    w = I.workload_blob784(count=3)
+    m = ibmc.Mlp(ctx, w.net)
+    for i in range(3):
+        g = ibmc.ibmc_proposer_features(ctx, m, w.images[i], 28, 28, w.deltas)
+        r = orc.prop_features(w.net, w.images[i], 28, 28, w.deltas)
+        np.testing.assert_allclose(g, r, rtol=2e-6, atol=1e-7)
+
+
+def test_gradients_match_fp64(ctx, orc):
+    from paper_1907_12933_amd import ibmc
+    g = I.rng(17)
+    prop = ibmc.Proposer(ctx, seed=3)
+    W1, b1, w2, c = prop.get()
+    b1 = (g.normal(size=128) * 0.2).astype(np.float32)
+    c = 0.1
+    prop.set(W1, b1, w2, c)
+    for B in (64, 1000, 4096):
+        f = g.random((B, 32)).astype(np.float32)
+        f[:, 9:] = 0.0
+        y = (g.random(B) < 0.2).astype(np.float32)
+        pw = 3.0
+        got = ibmc.ibmc_proposer_grad(ctx, prop, f, y, pw)
+        ref = orc.prop_loss_grad(bf16_round(f), y.astype(np.float64), pw, bf16_round(W1), b1.astype(np.float64),
+                                 w2.astype(np.float64), float(c))
+        assert abs(got["loss"] - ref["loss"]) <= 2e-3 * abs(ref["loss"])
+        for k in ("W1", "b1", "w2"):
+            a, b = got[k].astype(np.float64).ravel(), ref[k].ravel()
+            rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+            cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
+            assert rel <= 2e-2 and cos >= 0.999, (B, k, rel, cos)
+        assert abs(got["c"] - ref["c"]) <= 2e-3 * max(abs(ref["c"]), 1e-3)
+
+
+def test_training_learns_separable_labels(ctx):
+    from paper_1907_12933_amd import ibmc
+    g = I.rng(21)
+    N = 20000
+    f = g.random((N, 32)).astype(np.float32)
+    f[:, 9:] = 0.0
+    f[:, 8] = 1.0
+    y = ((f[:, 0] + 0.5 * f[:, 4] - 0.3 * f[:, 2]) > 0.9).astype(np.float32)
+    prop = ibmc.Proposer(ctx, seed=5)
+    losses = ibmc.ibmc_proposer_train(ctx, prop, f, y, epochs=15, batch=1024, lr=3e-3, seed=9)
+    assert losses[-1] < 0.5 * losses[0]
+    # the learned scores rank positives first (AUC)
+    from paper_1907_12933_amd.ibmc import PROP_FEATURES  # noqa: F401
+    W1, b1, w2, c = prop.get()
+    h = np.maximum(f.astype(np.float64) @ W1.T.astype(np.float64) + b1, 0)
+    s = h @ w2 + c
+    pos, neg = s[y > 0.5], s[y < 0.5]
+    auc = (np.searchsorted(np.sort(neg), pos).sum()) / (len(pos) * len(neg))
+    assert auc > 0.95
+
+
+def test_ranked_search_keeps_the_plain_verdicts(ctx, orc):
+    from paper_1907_12933_amd import ibmc
+    g = I.rng(41)
+    net = I.random_qnet(g, [64, 64, 64, 10], shift=5, wmax=16, bmax=200)
+    m = ibmc.Mlp(ctx, net)
+    D = np.array([-64, -32, 32, 64], np.int16)
+    prop = ibmc.Proposer(ctx, seed=1)
+    for t in range(3):
+        x = g.integers(0, 255, size=64, endpoint=True).astype(np.uint8)
+        plain, pc = ibmc.ibmc_check_property_ranked(ctx, m, None, x, 8, 8, D, 1, 2)
+        ranked, rc = ibmc.ibmc_check_property_ranked(ctx, m, prop, x, 8, 8, D, 1, 2)
+        ref = orc.q8_check(net, x, D, 1, 2)
+        for s, cx in ((plain, pc), (ranked, rc)):
+            assert list(s["cex"]) == [int(v) for v in ref["cex"]]
+            assert np.array_equal(cx["rank"], ref["cex_rank"]) and np.array_equal(cx["k"], ref["cex_k"])
+            assert np.array_equal(cx["new_label"], ref["cex_label"])
+            if ref["cex_total"]:
+                assert s["ttfc_seconds"] > 0 and 0 <= s["points_before_first"] < s["points_total"]
+            else:
+                assert s["points_before_first"] == -1
+        # plain order: level 1 is pixel-major, so the first counterexample's
+        # position is computable from the sorted records
+        if ref["cex_total"] and ref["cex_k"][0] == 1:
+            assert plain["points_before_first"] == ref["cex_rank"][0]
+
+
+def test_labels_from_records(ctx, orc):
+    from paper_1907_12933_amd import ibmc
+    g = I.rng(43)
+    net = I.random_qnet(g, [30, 64, 16, 5], shift=4, wmax=12, bmax=200)
+    m = ibmc.Mlp(ctx, net)
+    D = np.array([-48, -16, 16, 48], np.int16)
+    x = g.integers(0, 255, size=30, endpoint=True).astype(np.uint8)
+    s, cex, _ = ibmc.ibmc_check_property(ctx, m, x, D, 1, 2)
+    lab = ibmc.ibmc_label_candidates(ctx, 30, 4, cex)
+    exp = np.zeros(30 * 4, np.float32)
+    for k, r in zip(cex["k"], cex["rank"]):
+        pix, dig = orc.decode(30, 4, int(k), int(r))
+        exp[pix * 4 + dig] = 1.0
+    assert np.array_equal(lab, exp)

@@ -62,3 +62,31 @@ def test_adam_first_step(orc):
     exp = -0.01 * g / (np.abs(g) + 1e-8)
     np.testing.assert_allclose(th, exp, rtol=1e-12, atol=0)
     assert abs(th[0] + 0.01) < 1e-9 and abs(th[1] - 0.01) < 1e-9 and th[3] == 0.0
+
+
+def test_features_hand_built(orc):
+    # 2x2 image, 3 first-layer units, shift 2 (window [0, 512)).
+    # W1 rows (units) over pixels 0..3; x = (10, 0, 255, 100)
+    W1 = np.array([[1, -2, 0, 3],
+                   [-4, 0, 1, 1],
+                   [2, 2, 2, 2]], np.int8)
+    b1 = np.array([0, 100, -1000], np.int32)
+    x = np.array([10, 0, 255, 100], np.uint8)
+    # u = (10 + 300, -40 + 255 + 100 + 100, 20 + 510 + 200 - 1000) = (310, 415, -270)
+    # live (0 <= u < 512): units 0 and 1
+    net = I.QNet([4, 3, 2], [W1, np.ones((2, 3), np.int8)], [b1, np.zeros(2, np.int32)], [2])
+    D = np.array([-20, 5], np.int16)
+    f = orc.prop_features(net, x, 2, 2, D)
+    assert f.shape == (8, 32)
+    n1 = np.array([7, 4, 3, 6], float)
+    n2 = np.sqrt(np.array([21, 8, 5, 14], float))
+    nl = np.array([5, 2, 1, 4], float)
+    for p in range(4):
+        for i, d in enumerate(D):
+            row = f[p * 2 + i]
+            e = min(max(int(x[p]) + int(d), 0), 255) - int(x[p])
+            assert np.allclose(row[:9], [p // 2, p % 2, x[p] / 255, d / 20, e / 20,
+                                         n1[p] / 7, n2[p] / np.sqrt(21), nl[p] / 5, 1.0])
+            assert np.all(row[9:] == 0)
+    # clamping: pixel 2 (255) with +5 has e = 0; pixel 1 (0) with -20 has e = 0
+    assert f[2 * 2 + 1][4] == 0 and f[1 * 2 + 0][4] == 0
