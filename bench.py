@@ -51,6 +51,105 @@ def cpu_baseline(w, target_seconds=15.0):
                        f"full int64 forward per point, {total_t:.1f} s")
 
 
+def proposer_leg(ctx, ibmc, inputs, w, net, recs, args):
+    """Train the proposal network on plain-enumeration labels (10 glyph images
+    of the 35-16-5 net and the step's 64 blob images), then compare the time to
+    the first counterexample, plain order vs learned order, on 64 held-out blob
+    images; every held-out verdict and record list must be identical."""
+    t_all = time.perf_counter()
+    feats, labels = [], []
+    g1 = inputs.workload_glyph35()
+    m1 = ibmc.Mlp(ctx, g1.net)
+    for img in g1.images:
+        s, cex, _ = ibmc.ibmc_check_property(ctx, m1, img, g1.deltas, 1, 2, cex_capacity=1 << 21)
+        labels.append(ibmc.ibmc_label_candidates(ctx, 35, len(g1.deltas), cex))
+        feats.append(ibmc.ibmc_proposer_features(ctx, m1, img, 7, 5, g1.deltas))
+    props_col = recs["prop"]
+    for i in range(len(w.images)):
+        lo, hi = np.searchsorted(props_col, i, "left"), np.searchsorted(props_col, i, "right")
+        labels.append(ibmc.ibmc_label_candidates(ctx, 784, len(w.deltas), recs[lo:hi]))
+        feats.append(ibmc.ibmc_proposer_features(ctx, net, w.images[i], 28, 28, w.deltas))
+    F = np.concatenate(feats)
+    Y = np.concatenate(labels)
+    prop = ibmc.Proposer(ctx, seed=4)
+    t0 = time.perf_counter()
+    losses = ibmc.ibmc_proposer_train(ctx, prop, F, Y, epochs=20, batch=4096, lr=1e-3, seed=4)
+    t_train = time.perf_counter() - t0
+    held = inputs.heldout_blob_images()
+    rows = []
+    for x in held:
+        sp, cp = ibmc.ibmc_check_property_ranked(ctx, net, None, x, 28, 28, w.deltas, 1, 2, cex_capacity=1 << 22)
+        sl, cl = ibmc.ibmc_check_property_ranked(ctx, net, prop, x, 28, 28, w.deltas, 1, 2, cex_capacity=1 << 22)
+        same = (sp["cex"] == sl["cex"] and sp["clean_label"] == sl["clean_label"]
+                and np.array_equal(cp["rank"], cl["rank"]) and np.array_equal(cp["k"], cl["k"]))
+        rows.append((sp["cex_total"] > 0, same, sp["ttfc_seconds"], sl["ttfc_seconds"],
+                     sp["points_before_first"], sl["points_before_first"]))
+    unsafe = [r for r in rows if r[0]]
+    med = lambda v: float(np.median(v)) if len(v) else None
+    out = dict(
+        train_samples=int(len(Y)), train_positive=int(Y.sum()), epochs=20, batch=4096,
+        loss_first=float(losses[0]), loss_last=float(losses[-1]), train_seconds=round(t_train, 3),
+        heldout_images=len(held), heldout_unsafe=len(unsafe),
+        identical_verdicts=all(r[1] for r in rows),
+        ttfc_plain_median_s=med([r[2] for r in unsafe]), ttfc_learned_median_s=med([r[3] for r in unsafe]),
+        points_before_first_plain_median=med([r[4] for r in unsafe]),
+        points_before_first_learned_median=med([r[5] for r in unsafe]),
+        learned_first_earlier=int(sum(1 for r in unsafe if r[5] < r[4])),
+        leg_seconds=round(time.perf_counter() - t_all, 2))
+    if unsafe:
+        out["ttfc_speedup_median"] = med([r[2] / r[3] for r in unsafe if r[3] > 0])
+        out["points_before_first_ratio_median"] = med([(r[4] + 1) / (r[5] + 1) for r in unsafe])
+    return out
+
+
+def coverage_leg(ctx, ibmc, inputs, torch):
+    """SS/DS/SV/DV over 4,096 pairs of the 784-1024-1024-1024-10 net."""
+    net, x1, x2 = inputs.coverage_pairs_blob784()
+    m = ibmc.Mlp(ctx, net)
+    d1, d2 = torch.from_numpy(x1).cuda(), torch.from_numpy(x2).cuda()
+    ibmc.ibmc_coverage_all_dev(ctx, m, d1, d2, want_bits=False)
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        res = ibmc.ibmc_coverage_all_dev(ctx, m, d1, d2, want_bits=False)
+        ts.append(time.perf_counter() - t0)
+    dims = net.dims
+    macs = 2 * len(x1) * sum(dims[l] * dims[l + 1] for l in range(len(dims) - 1))
+    t = float(np.median(ts))
+    return dict(workload="784-1024-1024-1024-10, 4096 pairs differing in 1-8 pixels", seconds=round(t, 6),
+                device_seconds=round(res[0]["seconds"], 6),
+                forward_int8_tops=round(2 * macs / res[0]["seconds"] / 1e12, 2),
+                criteria={c: dict(covered_pairs=r["covered_pairs"], total_pairs=r["total_pairs"],
+                                  covered_neurons=r["covered_neurons"], total_neurons=r["total_neurons"],
+                                  fraction=round(r["fraction"], 4), literal=r["literal"])
+                          for c, r in zip(["SS", "DS", "SV", "DV"], res)})
+
+
+def batch_leg(ctx, ibmc, inputs):
+    """256 properties over eight uneven nets (k <= 3, per-property deltas) as one
+    graph of persistent launches; and 64 FP32-sigmoid properties."""
+    nets, props = inputs.batch_workload(seed=3)
+    ms = [ibmc.Mlp(ctx, n) for n in nets]
+    P = [(ms[p.net_index], p.image, p.deltas, 1, p.k) for p in props]
+    ibmc.ibmc_check_batch(ctx, P, cex_capacity=1 << 24)
+    t0 = time.perf_counter()
+    sums, cex, _, rc = ibmc.ibmc_check_batch(ctx, P, cex_capacity=1 << 24)
+    t = time.perf_counter() - t0
+    pts = sum(s["points_total"] for s in sums)
+    fn, fp = inputs.batch_workload(seed=33, per_net=8, mac_budget=2e11)
+    fms = [ibmc.Mlp(ctx, inputs.fnet_from_qnet(n)) for n in fn]
+    FP = [(fms[p.net_index], p.image, p.deltas, 1, p.k) for p in fp]
+    ibmc.ibmc_check_batch(ctx, FP, cex_capacity=1 << 22, near_tie_capacity=1 << 20)
+    t1 = time.perf_counter()
+    fs, fc, ft, _ = ibmc.ibmc_check_batch(ctx, FP, cex_capacity=1 << 22, near_tie_capacity=1 << 20)
+    tf = time.perf_counter() - t1
+    fpts = sum(s["points_total"] for s in fs)
+    return dict(properties=len(props), networks=len(nets), points=pts, seconds=round(t, 4),
+                points_per_s=pts / t, counterexamples=int(sum(s["cex_total"] for s in sums)),
+                fp32_properties=len(fp), fp32_points=fpts, fp32_seconds=round(tf, 4), fp32_points_per_s=fpts / tf,
+                fp32_near_ties=int(sum(s["near_ties_total"] for s in fs)))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +158,7 @@ def main():
     ap.add_argument("--images", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", default=None)
+    ap.add_argument("--no-extras", action="store_true", help="skip the proposer, coverage and batch legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -74,10 +174,12 @@ def main():
         ibmc.ibmc_set_variant(ctx, net, args.variant)
     imgs = torch.from_numpy(w.images).cuda()
     props = [(net, imgs[i], w.deltas, 1, 2) for i in range(args.images)]
-    cap = 1 << 22
+    cap = 1 << 25
+
+    buf = np.empty(cap, ibmc.CEX_DTYPE)
 
     def step():
-        return ibmc.ibmc_check_batch_dev(ctx, props, cex_capacity=cap)
+        return ibmc.ibmc_check_batch_dev(ctx, props, cex_capacity=cap, cex_buf=buf)
 
     for _ in range(args.warmup):
         step()
@@ -115,7 +217,15 @@ def main():
         "roofline": roof,
         "counterexamples_per_step": n_cex, "unsafe_images": unsafe,
     }
+    if not args.no_extras:
+        log("[bench] proposer leg")
+        out["ttfc"] = proposer_leg(ctx, ibmc, inputs, w, net, cex, args)
+        log("[bench] coverage leg")
+        out["coverage"] = coverage_leg(ctx, ibmc, inputs, torch)
+        log("[bench] batch leg")
+        out["batch"] = batch_leg(ctx, ibmc, inputs)
     if not args.no_cpu_baseline:
+        log("[bench] cpu baseline")
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
 

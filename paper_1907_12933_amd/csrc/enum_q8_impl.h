@@ -24,6 +24,21 @@ __device__ __forceinline__ int requant4_offset(v4i acc, int s) {
     return (int)(lo | hi);
 }
 
+// Fast hidden epilogue: the accumulator is alpha * u with alpha * 2^s = 256,
+// so a = clamp(floor(u / 2^s), 0, 127) is byte 1 of clamp(acc, 0, 32767).
+__device__ __forceinline__ int requant4_byte1(v4i acc) {
+    int m[4];
+#pragma unroll
+    for (int z = 0; z < 4; ++z) m[z] = min(max(acc[z], 0), 32767);
+    const unsigned lo = __builtin_amdgcn_perm((unsigned)m[1], (unsigned)m[0], 0x0c0c0501u);
+    const unsigned hi = __builtin_amdgcn_perm((unsigned)m[3], (unsigned)m[2], 0x05010c0cu);
+    return (int)(lo | hi);
+}
+
+// a - 64 bytes -> 2 (a - 64) bytes (still int8: [-128, 126]); the bit that
+// crosses into the next byte is masked off.
+__device__ __forceinline__ int double_bytes(int d) { return (int)(((unsigned)d << 1) & 0xfefefefeu); }
+
 __device__ __forceinline__ int as_int(short2_t v) { return __builtin_bit_cast(int, v); }
 __device__ __forceinline__ short2_t as_s2(int v) { return __builtin_bit_cast(short2_t, v); }
 
@@ -145,6 +160,10 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
     const int s1 = net.shift[0];
     const int s2 = (L == 3) ? net.shift[1] : 0;
     const int ncls = net.dims[L];
+    // fast hidden epilogue (3-layer nets, shift[1] in {7, 8}): layer 1 emits
+    // fast2 * (a1 - 64) (doubled bytes when fast2 == 2), layer 2 emits plain a2
+    const bool fast = (L == 3) && net.fast2 != 0;
+    const bool dbl1 = fast && net.fast2 == 2;
     const short2_t vlo = {(short)-16384, (short)-16384};
     const short2_t vhi = {(short)16383, (short)16383};
     int vb[KB1][8];
@@ -204,10 +223,13 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
                         pr2[t] = as_int(u);
                     }
                     // byte 1 of each 16-bit value is a - 64
-                    a1[nt][kb] = v4i{(int)__builtin_amdgcn_perm(pr2[1], pr2[0], 0x07050301u),
-                                     (int)__builtin_amdgcn_perm(pr2[3], pr2[2], 0x07050301u),
-                                     (int)__builtin_amdgcn_perm(pr2[5], pr2[4], 0x07050301u),
-                                     (int)__builtin_amdgcn_perm(pr2[7], pr2[6], 0x07050301u)};
+                    v4i o = {(int)__builtin_amdgcn_perm(pr2[1], pr2[0], 0x07050301u),
+                             (int)__builtin_amdgcn_perm(pr2[3], pr2[2], 0x07050301u),
+                             (int)__builtin_amdgcn_perm(pr2[5], pr2[4], 0x07050301u),
+                             (int)__builtin_amdgcn_perm(pr2[7], pr2[6], 0x07050301u)};
+                    if (L == 3 && dbl1)
+                        o = v4i{double_bytes(o[0]), double_bytes(o[1]), double_bytes(o[2]), double_bytes(o[3])};
+                    a1[nt][kb] = o;
                 }
             } else {
                 const int8_t *wcol = net.W1T + (int64_t)p * H1 + g * 16;
@@ -225,7 +247,11 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
                                  bv.z + e * (int)(int8_t)((w >> 16) & 0xff), bv.w + e * (int)(int8_t)(w >> 24)};
                         out[t] = requant4_offset(u, s1);
                     }
-                    a1[nt][kb] = v4i{out[0], out[1], out[2], out[3]};
+                    if (L == 3 && dbl1)
+                        a1[nt][kb] = v4i{double_bytes(out[0]), double_bytes(out[1]), double_bytes(out[2]),
+                                         double_bytes(out[3])};
+                    else
+                        a1[nt][kb] = v4i{out[0], out[1], out[2], out[3]};
                 }
             }
         }
@@ -238,7 +264,7 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
             v4i Acur[KB1], Anext[KB1];
 #pragma unroll
             for (int kb = 0; kb < KB1; ++kb) Acur[kb] = wt2[kb * 64];
-            const int4 *bias2 = reinterpret_cast<const int4 *>(net.bo[2] + g * 4);
+            const int4 *bias2 = reinterpret_cast<const int4 *>((fast ? net.bf2 : net.bo[2]) + g * 4);
 #pragma unroll
             for (int mt = 0; mt < MT2; ++mt) {
                 if (mt + 1 < MT2) {
@@ -256,7 +282,8 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
                         acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Acur[kb], a1[nt][kb], acc[nt], 0, 0, 0);
                 }
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) a2[nt][mt >> 2][mt & 3] = requant4_offset(acc[nt], s2);
+                for (int nt = 0; nt < NT; ++nt)
+                    a2[nt][mt >> 2][mt & 3] = fast ? requant4_byte1(acc[nt]) : requant4_offset(acc[nt], s2);
 #pragma unroll
                 for (int kb = 0; kb < KB1; ++kb) Acur[kb] = Anext[kb];
                 __builtin_amdgcn_sched_barrier(0);
@@ -268,7 +295,7 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) { bestv[nt] = INT32_MIN; besti[nt] = 0x7fffffff; bestc[nt] = 0; }
         for (int mt = 0; mt < MTL; ++mt) {
-            const int4 bias = *reinterpret_cast<const int4 *>(net.bo[L] + mt * 16 + g * 4);
+            const int4 bias = *reinterpret_cast<const int4 *>(((L == 3 && fast) ? net.bn[L] : net.bo[L]) + mt * 16 + g * 4);
             v4i acc[NT];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[nt] = v4i{bias.x, bias.y, bias.z, bias.w};

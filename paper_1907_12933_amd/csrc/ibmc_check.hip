@@ -119,6 +119,50 @@ static ibmc_status validate_props(const ibmc_property *props, int32_t n_props, c
     return IBMC_OK;
 }
 
+
+// Copy n device records to the host ordered by (prop, k, rank): radix-sorted
+// on the device when the packed key fits 64 bits, else sorted on the host.
+static ibmc_status fetch_sorted(ibmc_ctx *ctx, const CexRec *drecs, int64_t n, int max_prop, int max_k,
+                                int64_t max_rank, std::vector<CexRec> &outv, CexRec *direct = nullptr) {
+    hipStream_t s = ctx->stream;
+    if (!direct) outv.resize(n);
+    CexRec *out = direct ? direct : outv.data();
+    if (n == 0) return IBMC_OK;
+    IBMC_TRY(ctx->sortbuf.reserve(sort_scratch_bytes(n)));
+    SortScratch S;
+    sort_scratch_carve(ctx->sortbuf.p, n, S);
+    int bits = 0;
+    const int st = sort_records_device(drecs, n, max_prop, max_k, max_rank, S, s, &bits);
+    if (st == SORT_HIP_ERROR) return fail(IBMC_E_HIP, "record sort launch failed");
+    if (st == SORT_UNSUPPORTED) {
+        HIP_OK(hipMemcpyAsync(out, drecs, n * sizeof(CexRec), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        std::sort(out, out + n, [](const CexRec &a, const CexRec &b) {
+            if (a.prop != b.prop) return a.prop < b.prop;
+            if (a.k != b.k) return a.k < b.k;
+            return a.rank < b.rank;
+        });
+        return IBMC_OK;
+    }
+    ctx->hkeys.resize(n);
+    ctx->hvals.resize(n);
+    HIP_OK(hipMemcpyAsync(ctx->hkeys.data(), S.keys_out, n * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(ctx->hvals.data(), S.vals_out, n * 4, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    const uint64_t rmask = (S.kshift >= 64) ? ~0ull : ((1ull << S.kshift) - 1ull);
+    const uint64_t kmask = (1ull << (S.pshift - S.kshift)) - 1ull;
+    for (int64_t i = 0; i < n; ++i) {
+        const uint64_t key = ctx->hkeys[i];
+        CexRec &r = out[i];
+        r.prop = (int32_t)(S.pshift >= 64 ? 0 : (key >> S.pshift));
+        r.k = (int32_t)((key >> S.kshift) & kmask);
+        r.rank = (int64_t)(key & rmask);
+        r.label = (int32_t)ctx->hvals[i];
+        r.reserved = 0;
+    }
+    return IBMC_OK;
+}
+
 // Run the given levels (subset of every property's level list): a clean
 // pass and one persistent enumeration launch per network.  All plans are
 // uploaded first; with several networks the launches are captured as one HIP
@@ -139,7 +183,8 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
                               const std::vector<std::vector<int>> &level_sel, bool images_on_device,
                               std::vector<unsigned long long> &slot_cex, std::vector<unsigned long long> &slot_ties,
                               std::vector<CexRec> &recs, std::vector<CexRec> &ties, int64_t &rec_total,
-                              int64_t &tie_total, double &kernel_seconds, int &launches) {
+                              int64_t &tie_total, double &kernel_seconds, int &launches,
+                              CexRec *direct_recs = nullptr, CexRec *direct_ties = nullptr) {
     (void)images_on_device;
     hipStream_t s = ctx->stream;
     std::vector<NetPlan> plans;
@@ -374,10 +419,15 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
     slot_cex.assign(h.begin() + sc0, h.begin() + st0);
     slot_ties.assign(h.begin() + st0, h.begin() + st0 + B.n_slots);
     const int64_t nr = std::min(rec_total, cap), nt = std::min(tie_total, tcap);
-    recs.resize(nr);
-    ties.resize(nt);
-    if (nr) HIP_OK(hipMemcpyAsync(recs.data(), ctx->recs.p, nr * sizeof(CexRec), hipMemcpyDeviceToHost, s));
-    if (nt) HIP_OK(hipMemcpyAsync(ties.data(), ctx->ties.p, nt * sizeof(CexRec), hipMemcpyDeviceToHost, s));
+    int max_k = 0;
+    int64_t max_rank = 0;
+    for (const EnumJob &J : jobs) {
+        max_k = std::max(max_k, J.k);
+        const int pid = J.prop;
+        max_rank = std::max(max_rank, binom_small(props[pid].net->dims[0], J.k) * ipow64(props[pid].n_deltas, J.k));
+    }
+    IBMC_TRY(fetch_sorted(ctx, ctx->recs.as<CexRec>(), nr, n_props - 1, max_k, max_rank, recs, direct_recs));
+    IBMC_TRY(fetch_sorted(ctx, ctx->ties.as<CexRec>(), nt, n_props - 1, max_k, max_rank, ties, direct_ties));
     HIP_OK(hipMemcpyAsync(B.hprops.data(), ctx->props.p, n_props * sizeof(PropDev), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     if (ctx->flags_host[0]) return fail(IBMC_E_ABORTED, "check aborted");
@@ -443,6 +493,7 @@ ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props, int32_t 
     std::vector<bool> stopped(n_props, false);
     std::vector<int> next_level(n_props, 0);
     ibmc_status st = IBMC_OK;
+    int rounds = 0;
     while (true) {
         std::vector<std::vector<int>> sel(n_props);
         bool any = false;
@@ -465,7 +516,12 @@ ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props, int32_t 
         ibmc_check_opts oo = *o;
         oo.cex_capacity = std::max<int64_t>(0, o->cex_capacity - (int64_t)all_recs.size());
         oo.near_tie_capacity = std::max<int64_t>(0, o->near_tie_capacity - (int64_t)all_ties.size());
-        st = run_levels(ctx, props, n_props, &oo, B, sel, images_on_device, sc, stt, r, t, rt, tt, ks, nl);
+        // a single round writes the sorted records straight into the caller's buffers
+        const bool direct = !o->stop_at_first;
+        st = run_levels(ctx, props, n_props, &oo, B, sel, images_on_device, sc, stt, r, t, rt, tt, ks, nl,
+                        direct ? reinterpret_cast<CexRec *>(cex_buf) : nullptr,
+                        direct ? reinterpret_cast<CexRec *>(tie_buf) : nullptr);
+        rounds++;
         if (st < 0 && st != IBMC_E_ABORTED) return st;
         ksec += ks;
         nlaunch += nl;
@@ -490,10 +546,14 @@ ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props, int32_t 
     ctx->last_kernel_seconds = ksec;
     ctx->last_kernel_launches = nlaunch;
 
-    std::sort(all_recs.begin(), all_recs.end(), rec_less);
-    std::sort(all_ties.begin(), all_ties.end(), rec_less);
-    if (cex_buf && !all_recs.empty()) memcpy(cex_buf, all_recs.data(), all_recs.size() * sizeof(CexRec));
-    if (tie_buf && !all_ties.empty()) memcpy(tie_buf, all_ties.data(), all_ties.size() * sizeof(CexRec));
+    if (rounds > 1) {  // every round comes back ordered; rounds interleave properties
+        std::sort(all_recs.begin(), all_recs.end(), rec_less);
+        std::sort(all_ties.begin(), all_ties.end(), rec_less);
+    }
+    if (o->stop_at_first) {
+        if (cex_buf && !all_recs.empty()) memcpy(cex_buf, all_recs.data(), all_recs.size() * sizeof(CexRec));
+        if (tie_buf && !all_ties.empty()) memcpy(tie_buf, all_ties.data(), all_ties.size() * sizeof(CexRec));
+    }
     for (int i = 0; i < n_props; ++i) {
         ibmc_check_summary &S = outs[i];
         memset(&S, 0, sizeof(S));
@@ -739,8 +799,8 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
     HIP_OK(hipStreamSynchronize(s));
     rec_total = (int64_t)h[1];
     const int64_t nr = std::min(rec_total, cap);
-    std::vector<CexRec> recs(nr);
-    if (nr) HIP_OK(hipMemcpy(recs.data(), ctx->recs.p, nr * sizeof(CexRec), hipMemcpyDeviceToHost));
+    std::vector<CexRec> recs;
+    IBMC_TRY(fetch_sorted(ctx, ctx->recs.as<CexRec>(), nr, 0, o->k_max, binom_small(n, 2) * m * m, recs));
     if (p) {
         order.resize(N1);
         HIP_OK(hipMemcpy(order.data(), ctx->order.p, N1 * 4, hipMemcpyDeviceToHost));
@@ -749,7 +809,6 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
     HIP_OK(hipEventSynchronize(ctx->ev1));
     float ms = 0.f;
     HIP_OK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    std::sort(recs.begin(), recs.end(), rec_less);
     if (cex_buf && nr) memcpy(cex_buf, recs.data(), nr * sizeof(CexRec));
 
     // position of every record in the visiting order (hardware independent)

@@ -13,6 +13,7 @@
 #include "kernels_f32.h"
 #include "kernels_cov.h"
 #include "kernels_prop.h"
+#include "kernels_sort.h"
 
 namespace ibmc {
 
@@ -62,7 +63,9 @@ struct ibmc_ctx {
     int32_t *flags_dev = nullptr;    // device view of flags_host
     // scratch of the check driver (grow-only)
     ibmc::DevBuf images, props, jobs, qcum, u0, u0_index, prop_ids, counters, recs, ties, order;
-    ibmc::DevBuf u0f;
+    ibmc::DevBuf u0f, sortbuf;
+    std::vector<uint64_t> hkeys;
+    std::vector<uint32_t> hvals;
     ibmc::DevBuf cov_img, cov_pots, cov_bits, cov_sums, cov_out;
     // tuned kernel variant per network shape key
     std::map<std::string, std::string> tuned;

@@ -267,6 +267,20 @@ static ibmc_status build_q8(ibmc_ctx *ctx, ibmc_mlp *m) {
         q.bn[l] = (const int32_t *)m->buf.back().p;
         IBMC_TRY(m->buf.emplace_back().upload(bo.data(), bo.size() * 4, s));
         q.bo[l] = (const int32_t *)m->buf.back().p;
+        if (l == 2 && L == 3 && (m->shift[1] == 7 || m->shift[1] == 8)) {
+            // layer 2 fed with alpha (a1 - 64), alpha = 2^(8 - s2): its accumulator is alpha * u2,
+            // so byte 1 of clamp(acc, 0, 32767) is the requantised activation
+            const int alpha = 1 << (8 - m->shift[1]);
+            std::vector<int32_t> bf(Hout, 0);
+            for (int j = 0; j < nout; ++j) {
+                int64_t rs = 0;
+                for (int i = 0; i < nin; ++i) rs += m->Wq[l - 1][(size_t)j * nin + i];
+                bf[j] = (int32_t)(alpha * ((int64_t)m->bq[l - 1][j] + 64 * rs));
+            }
+            IBMC_TRY(m->buf.emplace_back().upload(bf.data(), bf.size() * 4, s));
+            q.bf2 = (const int32_t *)m->buf.back().p;
+            q.fast2 = alpha;
+        }
     }
     // batched forward: natural-K tiles of layers >= 2 and accumulator inits
     {

@@ -146,6 +146,13 @@ def lib():
     """Load libibmc.so; raises if it has not been built (no fallback)."""
     global _LIB
     if _LIB is None:
+        # PyTorch ships its own HIP runtime under the same soname as the
+        # system one; importing it first makes the library bind to the
+        # runtime torch uses, so torch tensors and streams stay valid.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_1907_12933_amd/build.py")
         L = C.CDLL(LIB_PATH)
@@ -276,8 +283,8 @@ def ibmc_check_property(ctx, net, image, deltas, k_min=1, k_max=2, k_step=1, sto
     """Returns (summary dict, cex records, near-tie records) as numpy structured arrays."""
     image = np.ascontiguousarray(image, np.uint8)
     D = np.ascontiguousarray(deltas, np.int16)
-    cex = np.zeros(max(cex_capacity, 1), CEX_DTYPE)
-    ties = np.zeros(max(near_tie_capacity, 1), CEX_DTYPE)
+    cex = np.empty(max(cex_capacity, 1), CEX_DTYPE)
+    ties = np.empty(max(near_tie_capacity, 1), CEX_DTYPE)
     o = _opts(k_min, k_max, k_step, stop_at_first, cex_capacity, near_tie_capacity, near_tie_rel)
     s = ibmc_check_summary()
     rc = _ck(lib().ibmc_check_property(ctx.handle, net.handle, _ptr(image, P_U8), image.size, _ptr(D, P_I16),
@@ -309,14 +316,18 @@ def _props(props, on_device):
 
 
 def ibmc_check_batch(ctx, props, stop_at_first=False, cex_capacity=1 << 20, near_tie_capacity=0,
-                     near_tie_rel=0.0, on_device=False):
+                     near_tie_rel=0.0, on_device=False, cex_buf=None):
     """props: list of (net, image, deltas, k_min, k_max[, k_step]); with on_device the images are
-    torch device tensors (uint8).  Returns (list of summary dicts, cex records, near-tie records)."""
+    torch device tensors (uint8).  cex_buf: optional preallocated CEX_DTYPE array of at least
+    cex_capacity records (reused across calls).  Returns (list of summary dicts, cex records
+    (a view into cex_buf when given), near-tie records, status)."""
     arr, keep = _props(props, on_device)
     n = len(props)
     outs = (ibmc_check_summary * n)()
-    cex = np.zeros(max(cex_capacity, 1), CEX_DTYPE)
-    ties = np.zeros(max(near_tie_capacity, 1), CEX_DTYPE)
+    if cex_buf is None or len(cex_buf) < cex_capacity:
+        cex_buf = np.empty(max(cex_capacity, 1), CEX_DTYPE)
+    cex = cex_buf
+    ties = np.empty(max(near_tie_capacity, 1), CEX_DTYPE)
     o = _opts(0, 0, 1, stop_at_first, cex_capacity, near_tie_capacity, near_tie_rel)
     fn = lib().ibmc_check_batch_dev if on_device else lib().ibmc_check_batch
     rc = _ck(fn(ctx.handle, arr, n, C.byref(o), outs, cex.ctypes.data_as(P_CEX), ties.ctypes.data_as(P_CEX)))
@@ -324,7 +335,7 @@ def ibmc_check_batch(ctx, props, stop_at_first=False, cex_capacity=1 << 20, near
     tot = sum(s["cex_total"] for s in sums)
     ttot = sum(s["near_ties_total"] for s in sums)
     del keep
-    return sums, cex[:min(tot, cex_capacity)].copy(), ties[:min(ttot, near_tie_capacity)].copy(), rc
+    return sums, cex[:min(tot, cex_capacity)], ties[:min(ttot, near_tie_capacity)].copy(), rc
 
 
 def ibmc_check_batch_dev(ctx, props, **kw):
@@ -546,7 +557,7 @@ def ibmc_check_property_ranked(ctx, net, prop, image, rows, cols, deltas, k_min=
                                cex_capacity=1 << 20):
     image = np.ascontiguousarray(image, np.uint8)
     D = np.ascontiguousarray(deltas, np.int16)
-    cex = np.zeros(max(cex_capacity, 1), CEX_DTYPE)
+    cex = np.empty(max(cex_capacity, 1), CEX_DTYPE)
     o = _opts(k_min, k_max, 1, stop_at_first, cex_capacity, 0, 0.0)
     s = ibmc_check_summary()
     rc = _ck(lib().ibmc_check_property_ranked(ctx.handle, net.handle, prop.handle if prop is not None else None,

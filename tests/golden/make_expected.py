@@ -1,0 +1,81 @@
+"""Write full-size expected results computed by the CPU oracle only.
+
+blob784_expected.json: for the first images of the 784-256-256-10 blob
+workload (k = 1, 2, deltas +-8/+-16/+-32), the oracle's clean label, per-level
+counterexample and exact-tie counts, and a SHA-256 of the sorted
+(k, rank, new label) records.
+coverage784_expected.json: SS/DS/SV/DV coverage of the 784-1024-1024-1024-10
+net over its 4,096 seeded pairs (counts and a SHA-256 of the bit array).
+
+Usage: python tests/golden/make_expected.py [n_images]
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+from oracle import oracle as O  # noqa: E402
+from paper_1907_12933_amd import inputs as I  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def rec_digest(k, rank, label):
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(k, np.int32).tobytes())
+    h.update(np.ascontiguousarray(rank, np.int64).tobytes())
+    h.update(np.ascontiguousarray(label, np.int32).tobytes())
+    return h.hexdigest()
+
+
+def blob784(n_images):
+    path = os.path.join(HERE, "blob784_expected.json")
+    data = json.load(open(path)) if os.path.exists(path) else {}
+    w = I.workload_blob784()
+    data["workload"] = "blob784 (seed 2): 784-256-256-10 shift 7, deltas +-8/+-16/+-32, k=1..2"
+    data["net_sha256"] = w.net.digest()
+    imgs = data.setdefault("images", {})
+    for i in range(n_images):
+        if str(i) in imgs:
+            continue
+        t = time.time()
+        r = O.q8_check(w.net, w.images[i], w.deltas, 1, 2, cap=1 << 24)
+        imgs[str(i)] = dict(image_sha256=I.array_digest(w.images[i]), clean_label=r["clean_label"],
+                            cex=[int(v) for v in r["cex"]], ties=[int(v) for v in r["ties"]],
+                            cex_total=r["cex_total"],
+                            records_sha256=rec_digest(r["cex_k"], r["cex_rank"], r["cex_label"]),
+                            first_records=[[int(a), int(b), int(c)] for a, b, c in
+                                           zip(r["cex_k"][:5], r["cex_rank"][:5], r["cex_label"][:5])],
+                            oracle_seconds=round(time.time() - t, 1))
+        print(i, imgs[str(i)]["cex"], imgs[str(i)]["oracle_seconds"], flush=True)
+        json.dump(data, open(path, "w"), indent=1)
+
+
+def coverage784():
+    net, x1, x2 = I.coverage_pairs_blob784()
+    t = time.time()
+    P1 = np.stack([O.q8_forward(net, x)[0] for x in x1])
+    P2 = np.stack([O.q8_forward(net, x)[0] for x in x2])
+    out = dict(workload="coverage784 (seed 5): 784-1024-1024-1024-10 shift 7, 4096 pairs",
+               net_sha256=net.digest(), pairs_sha256=I.array_digest(x1, x2), criteria={})
+    for c in ("SS", "DS", "SV", "DV"):
+        r = O.coverage(net.dims[1:], P1, P2, c)
+        out["criteria"][c] = dict(covered_pairs=r["covered_pairs"], total_pairs=r["total_pairs"],
+                                  covered_neurons=r["covered_neurons"], total_neurons=r["total_neurons"],
+                                  literal=r["literal"], bits_sha256=hashlib.sha256(r["bits"].tobytes()).hexdigest())
+        print(c, out["criteria"][c], flush=True)
+    out["oracle_seconds"] = round(time.time() - t, 1)
+    json.dump(out, open(os.path.join(HERE, "coverage784_expected.json"), "w"), indent=1)
+
+
+if __name__ == "__main__":
+    n = int(sys.argv[1]) if len(sys.argv) > 1 else 4
+    if "--coverage" in sys.argv or not os.path.exists(os.path.join(HERE, "coverage784_expected.json")):
+        coverage784()
+    blob784(n)

@@ -57,17 +57,30 @@ def test_closed_form_nets(ctx, orc, x, w1, shift, deltas):
     (4, [70, 64, 64, 10], 5, 16, 2, [-64, -32, 32, 64]),
     (5, [17, 130, 40, 3], 4, 10, 3, [-80, 80]),
     (6, [40, 200, 10], 4, 10, 2, [-50, -25, 25, 50]),
+    # three layers with layer-2 shift 7 / 8 (the fast hidden requantiser); the
+    # last two make every image a near tie (see below) for dense counterexamples
+    (7, [40, 128, 64, 6], 7, 60, 2, [-60, -30, 30, 60]),
+    (8, [48, 64, 192, 10], [7, 8], 64, 2, [-120, -60, 60, 120]),
+    (9, [33, 256, 256, 10], [6, 7], 50, 2, [-100, -50, 50, 100]),
 ])
 def test_random_nets_full_lists(ctx, orc, seed, dims, shift, wmax, k_max, deltas):
     """Nets with dense counterexamples, several tiles and ragged tails: every
     record must match the oracle's."""
     from paper_1907_12933_amd import ibmc
     g = I.rng(100 + seed)
-    net = I.random_qnet(g, dims, shift=shift, wmax=wmax, bmax=200)
+    net = I.random_qnet(g, dims, shift=shift, wmax=wmax, bmax=200 if seed < 7 else 3000)
     m = ibmc.Mlp(ctx, net)
     D = np.array(deltas, np.int16)
     for t in range(3):
         x = g.integers(0, 255, size=dims[0], endpoint=True).astype(np.uint8)
+        if seed >= 8:
+            # move the runner-up logit to one below the top: many nearby points flip
+            pot, lab = orc.q8_forward(net, x)
+            z = pot[-dims[-1]:]
+            j = int(np.argsort(z)[-2]) if int(np.argsort(z)[-1]) == lab else int(np.argsort(z)[-1])
+            net.b[-1] = net.b[-1].copy()
+            net.b[-1][j] += np.int32(z[lab] - z[j] - 1 - (1 if j < lab else 0))
+            m = ibmc.Mlp(ctx, net)
         print(f"[check] seed={seed} dims={dims} image={t}", flush=True)
         s, cex, _ = ibmc.ibmc_check_property(ctx, m, x, D, 0, k_max)
         r = orc.q8_check(net, x, D, 0, k_max)

@@ -1,0 +1,95 @@
+"""Full-size parity in the benchmark's launch configuration.
+
+Expected values come from tests/golden/make_expected.py, which runs only the
+CPU oracle: exact record lists (as SHA-256 digests) of blob784 images at
+11,054,400 points each, and the coverage of the 784-1024-1024-1024-10 net
+over all 4,096 pairs."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1907_12933_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1907_12933_amd import ibmc
+    return ibmc.Context(0)
+
+
+def rec_digest(k, rank, label):
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(k, np.int32).tobytes())
+    h.update(np.ascontiguousarray(rank, np.int64).tobytes())
+    h.update(np.ascontiguousarray(label, np.int32).tobytes())
+    return h.hexdigest()
+
+
+def test_blob784_full_batch_matches_oracle(ctx):
+    """All 64 images in one batch (exactly as the benchmark step), every
+    image the oracle has finished compared record for record."""
+    import torch
+    from paper_1907_12933_amd import ibmc
+    exp = json.load(open(os.path.join(GOLD, "blob784_expected.json")))
+    w = I.workload_blob784()
+    assert w.net.digest() == exp["net_sha256"]
+    m = ibmc.Mlp(ctx, w.net)
+    imgs = torch.from_numpy(w.images).cuda()
+    props = [(m, imgs[i], w.deltas, 1, 2) for i in range(len(w.images))]
+    sums, cex, _, rc = ibmc.ibmc_check_batch_dev(ctx, props, cex_capacity=1 << 25)
+    assert rc == ibmc.IBMC_OK
+    assert all(s["points_total"] == 11054400 for s in sums)
+    assert np.all(np.diff(cex["prop"]) >= 0)
+    for key, e in exp["images"].items():
+        i = int(key)
+        assert I.array_digest(w.images[i]) == e["image_sha256"]
+        s = sums[i]
+        assert s["clean_label"] == e["clean_label"]
+        assert s["cex"] == e["cex"] and s["ties"] == e["ties"]
+        lo, hi = np.searchsorted(cex["prop"], i, "left"), np.searchsorted(cex["prop"], i, "right")
+        sel = cex[lo:hi]
+        assert rec_digest(sel["k"], sel["rank"], sel["new_label"]) == e["records_sha256"], i
+
+
+def test_blob784_counterexamples_replay(ctx, orc):
+    """Every counterexample of a full image replays on the device and on the
+    oracle; a seeded sample of 2,000 other points agrees with the oracle."""
+    from paper_1907_12933_amd import ibmc
+    w = I.workload_blob784(count=8)
+    m = ibmc.Mlp(ctx, w.net)
+    g = I.rng(77)
+    for i in range(8):
+        s, cex, _ = ibmc.ibmc_check_property(ctx, m, w.images[i], w.deltas, 1, 2, cex_capacity=1 << 22)
+        if len(cex):
+            lab = ibmc.ibmc_replay(ctx, m, w.images[i], w.deltas, cex)
+            assert np.array_equal(lab, cex["new_label"])
+            pick = g.choice(len(cex), size=min(500, len(cex)), replace=False)
+            ol = orc.q8_eval_points(w.net, w.images[i], w.deltas, cex["k"][pick], cex["rank"][pick])
+            assert np.array_equal(ol, cex["new_label"][pick])
+        ks = np.where(g.random(2000) < 0.01, 1, 2).astype(np.int32)
+        rk = np.where(ks == 1, g.integers(0, 4704, 2000), g.integers(0, 11049696, 2000)).astype(np.int64)
+        ol = orc.q8_eval_points(w.net, w.images[i], w.deltas, ks, rk)
+        viol = set(zip(cex["k"].tolist(), cex["rank"].tolist()))
+        for k, r, l in zip(ks, rk, ol):
+            assert ((int(k), int(r)) in viol) == (l != s["clean_label"])
+
+
+def test_coverage784_full(ctx):
+    import torch
+    from paper_1907_12933_amd import ibmc
+    exp = json.load(open(os.path.join(GOLD, "coverage784_expected.json")))
+    net, x1, x2 = I.coverage_pairs_blob784()
+    assert net.digest() == exp["net_sha256"] and I.array_digest(x1, x2) == exp["pairs_sha256"]
+    m = ibmc.Mlp(ctx, net)
+    res = ibmc.ibmc_coverage_all_dev(ctx, m, torch.from_numpy(x1).cuda(), torch.from_numpy(x2).cuda())
+    for c, r in zip(["SS", "DS", "SV", "DV"], res):
+        e = exp["criteria"][c]
+        for key in ("covered_pairs", "total_pairs", "covered_neurons", "total_neurons", "literal"):
+            assert r[key] == e[key], (c, key)
+        assert hashlib.sha256(r["bits"].tobytes()).hexdigest() == e["bits_sha256"], c
