@@ -204,7 +204,8 @@ void ibmc_free_mlp(ibmc_mlp *net);
  * n_deltas int16 values (1..64).  cex_buf: room for opts->cex_capacity
  * records (may be NULL when the capacity is 0); near_tie_buf likewise
  * (float nets).  Returns IBMC_W_TRUNCATED when a buffer was too small; the
- * summary's totals stay exact. */
+ * summary's totals stay exact.  IBMC_E_UNIMPL when dims[0] * n_deltas is
+ * 2^24 or more (single-pixel candidates are indexed in 32-bit arithmetic). */
 ibmc_status ibmc_check_property(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *image,
                                 int32_t n_pixels, const int16_t *delta_set, int32_t n_deltas,
                                 const ibmc_check_opts *opts, ibmc_check_summary *out,

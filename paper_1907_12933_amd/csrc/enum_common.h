@@ -10,6 +10,23 @@ namespace ibmc {
 
 __device__ __forceinline__ int clamp_pixel(int v) { return min(max(v, 0), 255); }
 
+// Load through a global-address-space pointer: pointers read from memory
+// (the property's image and deltas, job tables) are generic to the compiler,
+// and generic (flat) loads count against both memory and LDS waits.
+template <class T>
+__device__ __forceinline__ T gld(const T *p) {
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+
+// Values that are equal in every lane, made visibly uniform to the compiler
+// (scalar registers and scalar branches instead of VGPRs and exec masks).
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ unsigned long long wave_uniform(unsigned long long v) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 // Segment cursor: position of a wave in the global chunk order
 // (job, last-prefix pixel q, prefix subset, prefix deltas, chunk).  All its
 // fields are wave-uniform.
@@ -23,6 +40,10 @@ struct Cursor {
     int64_t seglen;        // candidates of the last element in this segment
     int64_t chunk;         // global chunk index
     int64_t job_end;
+    const uint8_t *img;    // the property's image and delta set
+    const int16_t *dl;
+    unsigned mmagic;       // ceil(2^32 / m) for m >= 2, else 0 (see div_m)
+    unsigned m1;           // m == 1
 };
 
 
@@ -49,13 +70,17 @@ template <int CH, class PT>
 __device__ __forceinline__ void cursor_job_start(Cursor &c, const PT &P, int job) {
     const EnumJob &J = P.jobs[job];
     c.job = job;
-    c.k = J.k;
-    c.prop = J.prop;
-    c.slot = J.slot;
-    c.mode = J.mode;
-    c.m = P.props[J.prop].m;
-    c.n = P.props[J.prop].n;
-    c.job_end = J.chunk_end;
+    c.k = wave_uniform(J.k);
+    c.prop = wave_uniform(J.prop);
+    c.slot = wave_uniform(J.slot);
+    c.mode = wave_uniform(J.mode);
+    c.m = wave_uniform(P.props[c.prop].m);
+    c.n = wave_uniform(P.props[c.prop].n);
+    c.job_end = (int64_t)wave_uniform((unsigned long long)J.chunk_end);
+    c.img = reinterpret_cast<const uint8_t *>(wave_uniform((unsigned long long)P.props[c.prop].image));
+    c.dl = P.props[c.prop].deltas;
+    c.mmagic = c.m > 1 ? (unsigned)((0x100000000ull + (unsigned)c.m - 1) / (unsigned)c.m) : 0u;
+    c.m1 = c.m == 1 ? 1u : 0u;
 }
 
 template <int CH>
@@ -70,11 +95,11 @@ __device__ __forceinline__ void cursor_decode(Cursor &c, const PT &P, int64_t ch
     int lo = 0, hi = P.n_jobs - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (P.jobs[mid].chunk_begin <= chunk) lo = mid; else hi = mid - 1;
+        if ((int64_t)wave_uniform((unsigned long long)P.jobs[mid].chunk_begin) <= chunk) lo = mid; else hi = mid - 1;
     }
     cursor_job_start<CH, PT>(c, P, lo);
     const EnumJob &J = P.jobs[lo];
-    int64_t r = chunk - J.chunk_begin;
+    int64_t r = chunk - (int64_t)wave_uniform((unsigned long long)J.chunk_begin);
     c.chunk = chunk;
     if (c.mode == SEG_LIST1) {
         c.q = -1; c.shell = 0;
@@ -89,12 +114,12 @@ __device__ __forceinline__ void cursor_decode(Cursor &c, const PT &P, int64_t ch
         int64_t a = 1, b = N1 - 1;
         while (a < b) {
             const int64_t mid = (a + b + 1) >> 1;
-            if (J.shell_cum[mid] <= r) a = mid; else b = mid - 1;
+            if ((int64_t)wave_uniform((unsigned long long)J.shell_cum[mid]) <= r) a = mid; else b = mid - 1;
         }
         c.shell = a;
         c.seglen = a;
         c.nch = (a + CH - 1) / CH;
-        c.ch = r - J.shell_cum[a];
+        c.ch = r - (int64_t)wave_uniform((unsigned long long)J.shell_cum[a]);
         return;
     }
     if (c.k == 1) {
@@ -108,11 +133,11 @@ __device__ __forceinline__ void cursor_decode(Cursor &c, const PT &P, int64_t ch
     int a = c.k - 2, b = c.n - 2;
     while (a < b) {
         const int mid = (a + b + 1) >> 1;
-        if (J.qcum[mid] <= r) a = mid; else b = mid - 1;
+        if ((int64_t)wave_uniform((unsigned long long)J.qcum[mid]) <= r) a = mid; else b = mid - 1;
     }
     c.q = a;
     cursor_set_q<CH>(c);
-    const int64_t rr = r - J.qcum[a];
+    const int64_t rr = r - (int64_t)wave_uniform((unsigned long long)J.qcum[a]);
     const int64_t seg = rr / c.nch;
     c.ch = rr % c.nch;
     int64_t mk1 = 1;
@@ -215,27 +240,38 @@ __device__ __forceinline__ bool last_element(const Cursor &c, const PT &P, int64
 }
 
 
+// Quotient floor(x / m) for the per-point hot path: a multiply-high by
+// M = ceil(2^32 / m) (cursor field mmagic) is exact for x < 2^32 / m, which
+// holds for every candidate index (below n * |D| <= 2^24 here).  For m == 1,
+// whose M does not fit 32 bits, mmagic is 0 and m1 is 1.
+__device__ __forceinline__ unsigned div_m(const Cursor &c, unsigned x) {
+    return __umulhi(x, c.mmagic) + x * c.m1;
+}
+
 // 32-bit form of last_element for the per-point hot path (segment lengths
-// are below 2^31: at most n * |D| candidates).
+// are below 2^31: at most n * |D| candidates).  Positions past the segment
+// end report false and resolve to its first candidate, so that every lane
+// reads in bounds.
 template <class PT>
 __device__ __forceinline__ bool last_element32(const Cursor &c, const PT &P, int o, int &p, int &i) {
-    if (o >= (int)c.seglen) return false;
+    const bool ok = o < (int)c.seglen;
+    const unsigned uo = ok ? (unsigned)o : 0u;
     if (c.mode == SEG_PLAIN) {
-        const unsigned uo = (unsigned)o, um = (unsigned)c.m;
-        const unsigned qd = uo / um;
+        const unsigned qd = div_m(c, uo);
         p = c.q + 1 + (int)qd;
-        i = (int)(uo - qd * um);
-        return true;
+        i = (int)(uo - qd * (unsigned)c.m);
+        return ok;
     }
     const EnumJob &J = P.jobs[c.job];
-    const int cand = J.order[o];
-    p = cand / c.m;
-    i = cand - p * c.m;
+    const int cand = gld(J.order + uo);
+    const unsigned qd = div_m(c, (unsigned)cand);
+    p = (int)qd;
+    i = cand - (int)qd * c.m;
     if (c.mode == SEG_SHELL) {
-        const int head = J.order[c.shell];
-        return p != head / c.m;
+        const int head = wave_uniform(gld(J.order + c.shell));
+        return ok && p != (int)div_m(c, (unsigned)head);
     }
-    return true;
+    return ok;
 }
 
 // Point rank (see the header) of a point given by its prefix and last element.
@@ -251,7 +287,7 @@ __device__ __forceinline__ int64_t point_rank(const Cursor &c, const PT &P, int 
             else { pix[j] = 0; dig[j] = 0; }
         }
     } else if (c.mode == SEG_SHELL) {
-        const int head = P.jobs[c.job].order[c.shell];
+        const int head = wave_uniform(P.jobs[c.job].order[c.shell]);
         const int ph = head / c.m, ih = head % c.m;
         if (ph < p) { pix[0] = ph; dig[0] = ih; pix[1] = p; dig[1] = i; }
         else { pix[0] = p; dig[0] = i; pix[1] = ph; dig[1] = ih; }

@@ -20,6 +20,7 @@ namespace ibmc {
 std::string shape_key(const ibmc_mlp *m) {
     std::string s = (m->act == IBMC_ACT_RELU_Q8) ? "q8" : "f32";
     for (int d : m->dims) s += "_" + std::to_string(d);
+    if (m->act == IBMC_ACT_RELU_Q8 && m->L == 3 && m->qd.fast2 != 0) s += "_f";
     return s;
 }
 
@@ -45,14 +46,22 @@ static int64_t plan_plain_level(int n, int m, int k, int CH, std::vector<int64_t
     return acc;
 }
 
+// A kernel instance serves a network when its layer count, hidden widths,
+// hidden epilogue form and output width class (at most 16 classes or more)
+// agree with it.
+static bool variant_matches(const EnumVariant &v, const ibmc_mlp *net) {
+    const int L = net->L;
+    const int kb2 = (L == 3) ? net->qd.H[2] / 64 : 0;
+    const int epi = (L == 3 && net->qd.fast2 != 0) ? 1 : 0;
+    const bool out16 = net->qd.H[L] == 16;
+    return v.L == L && v.kb1 == net->qd.H[1] / 64 && v.kb2 == kb2 && v.epi == epi && v.out16 == out16;
+}
+
 // Variant choice for an integer network: the tuned one if any, else the
 // widest point tile whose weights fit the LDS budget.
 const EnumVariant *pick_variant(ibmc_ctx *ctx, const ibmc_mlp *net) {
     int nv = 0;
     const EnumVariant *vs = enum_variants(&nv);
-    const int L = net->L;
-    const int kb1 = net->qd.H[1] / 64;
-    const int kb2 = (L == 3) ? net->qd.H[2] / 64 : 0;
     std::string want = net->forced_variant;
     if (want.empty()) {
         auto it = ctx->tuned.find(shape_key(net));
@@ -60,11 +69,11 @@ const EnumVariant *pick_variant(ibmc_ctx *ctx, const ibmc_mlp *net) {
     }
     if (!want.empty())
         for (int i = 0; i < nv; ++i)
-            if (want == vs[i].name && vs[i].L == L && vs[i].kb1 == kb1 && vs[i].kb2 == kb2) return &vs[i];
+            if (want == vs[i].name && variant_matches(vs[i], net)) return &vs[i];
     const EnumVariant *best = nullptr;
     for (int i = 0; i < nv; ++i) {
         const EnumVariant &v = vs[i];
-        if (v.L != L || v.kb1 != kb1 || v.kb2 != kb2) continue;
+        if (!variant_matches(v, net)) continue;
         if (enum_lds_bytes(v, net->qd) > 96 * 1024) continue;
         const int score = (v.wlds ? 100 : 0) + (v.nt == 2 ? 10 : v.nt);
         if (!best || score > (best->wlds ? 100 : 0) + (best->nt == 2 ? 10 : best->nt)) best = &v;
@@ -96,6 +105,9 @@ static ibmc_status validate_props(const ibmc_property *props, int32_t n_props, c
         if (p.n_deltas < 1 || p.n_deltas > kMaxDeltas)
             return fail(IBMC_E_INVALID, "property %d: n_deltas %d outside [1, %d]", i, p.n_deltas, kMaxDeltas);
         const int n = p.net->dims[0];
+        if ((int64_t)n * p.n_deltas >= ((int64_t)1 << 24))
+            return fail(IBMC_E_UNIMPL, "property %d: pixels * deltas = %lld must be below 2^24", i,
+                        (long long)n * p.n_deltas);
         if (p.k_min < 0 || p.k_max < p.k_min || p.k_step < 1)
             return fail(IBMC_E_INVALID, "property %d: bad k range %d..%d step %d", i, p.k_min, p.k_max, p.k_step);
         if (p.k_max > n || p.k_max > kMaxK)
@@ -630,8 +642,7 @@ extern "C" ibmc_status ibmc_set_variant(ibmc_ctx *ctx, const ibmc_mlp *net, cons
     const EnumVariant *vs = enum_variants(&nv);
     for (int i = 0; i < nv; ++i)
         if (std::string(variant) == vs[i].name) {
-            if (vs[i].L != net->L || vs[i].kb1 != net->qd.H[1] / 64 ||
-                vs[i].kb2 != (net->L == 3 ? net->qd.H[2] / 64 : 0))
+            if (!variant_matches(vs[i], net))
                 return fail(IBMC_E_INVALID, "variant %s does not match the network", variant);
             m->forced_variant = variant;
             return IBMC_OK;
@@ -908,7 +919,6 @@ extern "C" ibmc_status ibmc_autotune(ibmc_ctx *ctx, const ibmc_mlp *net, int32_t
     for (int i = 0; i < n_deltas; ++i) D[i] = (int16_t)((i % 2 ? 1 : -1) * 8 * (1 + i / 2));
     int nv = 0;
     const EnumVariant *vs = enum_variants(&nv);
-    const int kb1 = net->qd.H[1] / 64, kb2 = (net->L == 3) ? net->qd.H[2] / 64 : 0;
     ibmc_mlp *m = const_cast<ibmc_mlp *>(net);
     const std::string saved = m->forced_variant;
     std::string json = "{\"shape\": \"" + shape_key(net) + "\", \"k\": " + std::to_string(k) + ", \"variants\": [";
@@ -922,7 +932,7 @@ extern "C" ibmc_status ibmc_autotune(ibmc_ctx *ctx, const ibmc_mlp *net, int32_t
     o.cex_capacity = 0;
     for (int i = 0; i < nv; ++i) {
         const EnumVariant &v = vs[i];
-        if (v.L != net->L || v.kb1 != kb1 || v.kb2 != kb2) continue;
+        if (!variant_matches(v, net)) continue;
         int occ = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, v.fn, 256, (size_t)enum_lds_bytes(v, net->qd)) !=
                 hipSuccess || occ < 1)

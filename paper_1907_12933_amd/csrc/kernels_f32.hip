@@ -142,8 +142,8 @@ __global__ void __launch_bounds__(256) enum_f32_kernel(FEnumParams P, const int3
                 s_stop = (*P.stop_flag) || (P.abort_host && *P.abort_host);
             }
             __syncthreads();
-            const int64_t start = (int64_t)s_start;
-            const int stop = s_stop;
+            const int64_t start = (int64_t)wave_uniform(s_start);
+            const int stop = wave_uniform(s_stop);
             __syncthreads();
             if (start >= P.total_chunks || stop) break;
             cur = start;

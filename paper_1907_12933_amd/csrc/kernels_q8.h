@@ -9,6 +9,8 @@ namespace ibmc {
 struct EnumVariant {
     int L, kb1, kb2, nt;
     bool wlds;
+    int epi;           // 3-layer nets: 1 = fast hidden epilogue (QNetDev::fast2 != 0), else 0
+    bool out16;        // at most 16 classes (one output M-tile); else any number
     int chunk;         // points per chunk (16 * nt)
     const char *name;
     const void *fn;
@@ -18,6 +20,9 @@ const EnumVariant *enum_variants(int *count);
 const EnumVariant *enum_variants_l2(int *count);
 const EnumVariant *enum_variants_l3a(int *count);
 const EnumVariant *enum_variants_l3b(int *count);
+const EnumVariant *enum_variants_l3a_fast(int *count);
+const EnumVariant *enum_variants_l3b_fast(int *count);
+const EnumVariant *enum_variants_general(int *count);
 int64_t enum_lds_bytes(const EnumVariant &v, const QNetDev &net);
 
 

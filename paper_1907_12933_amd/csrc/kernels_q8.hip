@@ -169,6 +169,12 @@ const EnumVariant *enum_variants(int *count) {
         all.insert(all.end(), v, v + n);
         v = enum_variants_l3b(&n);
         all.insert(all.end(), v, v + n);
+        v = enum_variants_l3a_fast(&n);
+        all.insert(all.end(), v, v + n);
+        v = enum_variants_l3b_fast(&n);
+        all.insert(all.end(), v, v + n);
+        v = enum_variants_general(&n);
+        all.insert(all.end(), v, v + n);
     }
     *count = (int)all.size();
     return all.data();
@@ -219,7 +225,8 @@ int64_t enum_lds_bytes(const EnumVariant &v, const QNetDev &net) {
         const int kbl = (v.L == 3) ? v.kb2 : v.kb1;
         w += (int64_t)(net.H[v.L] / 16) * kbl * 1024;
     }
-    return w + 4LL * v.kb1 * 64 * 4;
+    const int64_t biases = 4LL * ((v.L == 3 ? (int64_t)v.kb2 * 64 : 0) + net.H[v.L]);
+    return w + biases + 4LL * v.kb1 * 64 * 4;
 }
 
 hipError_t launch_enum_q8(const EnumVariant &v, int grid, const EnumParams &P,

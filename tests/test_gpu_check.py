@@ -62,18 +62,23 @@ def test_closed_form_nets(ctx, orc, x, w1, shift, deltas):
     (7, [40, 128, 64, 6], 7, 60, 2, [-60, -30, 30, 60]),
     (8, [48, 64, 192, 10], [7, 8], 64, 2, [-120, -60, 60, 120]),
     (9, [33, 256, 256, 10], [6, 7], 50, 2, [-100, -50, 50, 100]),
+    # more than 16 classes: the output layer spans several M-tiles
+    (10, [30, 64, 20], 4, 12, 2, [-60, -20, 20, 60]),
+    (11, [24, 128, 64, 40], [5, 7], 20, 2, [-50, 50]),
+    (12, [26, 64, 64, 17], 5, 16, 2, [-64, -32, 32, 64]),
 ])
 def test_random_nets_full_lists(ctx, orc, seed, dims, shift, wmax, k_max, deltas):
     """Nets with dense counterexamples, several tiles and ragged tails: every
     record must match the oracle's."""
     from paper_1907_12933_amd import ibmc
     g = I.rng(100 + seed)
-    net = I.random_qnet(g, dims, shift=shift, wmax=wmax, bmax=200 if seed < 7 else 3000)
+    dense = seed in (7, 8, 9)
+    net = I.random_qnet(g, dims, shift=shift, wmax=wmax, bmax=3000 if dense else 200)
     m = ibmc.Mlp(ctx, net)
     D = np.array(deltas, np.int16)
     for t in range(3):
         x = g.integers(0, 255, size=dims[0], endpoint=True).astype(np.uint8)
-        if seed >= 8:
+        if seed in (8, 9):
             # move the runner-up logit to one below the top: many nearby points flip
             pot, lab = orc.q8_forward(net, x)
             z = pot[-dims[-1]:]
