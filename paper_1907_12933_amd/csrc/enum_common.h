@@ -44,6 +44,9 @@ struct Cursor {
     const int16_t *dl;
     unsigned mmagic;       // ceil(2^32 / m) for m >= 2, else 0 (see div_m)
     unsigned m1;           // m == 1
+    int wseg;              // segments per group of this job
+    int nw;                // segments in the current group (pre / dg: its first)
+    int64_t s0, nseg;      // plain k >= 2: first segment of the group, segments of q
 };
 
 
@@ -81,6 +84,10 @@ __device__ __forceinline__ void cursor_job_start(Cursor &c, const PT &P, int job
     c.dl = P.props[c.prop].deltas;
     c.mmagic = c.m > 1 ? (unsigned)((0x100000000ull + (unsigned)c.m - 1) / (unsigned)c.m) : 0u;
     c.m1 = c.m == 1 ? 1u : 0u;
+    c.wseg = max(1, wave_uniform(J.wseg));
+    c.nw = 1;
+    c.s0 = 0;
+    c.nseg = 1;
 }
 
 template <int CH>
@@ -138,12 +145,15 @@ __device__ __forceinline__ void cursor_decode(Cursor &c, const PT &P, int64_t ch
     c.q = a;
     cursor_set_q<CH>(c);
     const int64_t rr = r - (int64_t)wave_uniform((unsigned long long)J.qcum[a]);
-    const int64_t seg = rr / c.nch;
+    const int64_t grp = rr / c.nch;
     c.ch = rr % c.nch;
     int64_t mk1 = 1;
     for (int j = 0; j < c.k - 1; ++j) mk1 *= c.m;
-    const int64_t combo = seg / mk1;
-    int64_t dig = seg % mk1;
+    c.nseg = binom_small(a, c.k - 2) * mk1;
+    c.s0 = grp * c.wseg;
+    c.nw = (int)min<int64_t>(c.wseg, c.nseg - c.s0);
+    const int64_t combo = c.s0 / mk1;
+    int64_t dig = c.s0 % mk1;
 #pragma unroll
     for (int j = kMaxK - 1; j >= 0; --j) {
         if (j < c.k - 1) { c.dg[j] = (int)(dig % c.m); dig /= c.m; }
@@ -155,6 +165,35 @@ __device__ __forceinline__ void cursor_decode(Cursor &c, const PT &P, int64_t ch
         if (j < c.k - 2) c.pre[j] = tmp[j];
         if (j == c.k - 2) c.pre[j] = c.q;
     }
+}
+
+// Step a plain (k >= 2) cursor to the next segment of the same q: prefix
+// deltas with the last digit fastest, then the next (k-2)-subset of [0, q) in
+// lexicographic order.  Returns false when q has no further segment (the
+// deltas are then back at zero).
+__device__ __forceinline__ bool seg_step(Cursor &c) {
+    bool carry = true;
+#pragma unroll
+    for (int j = kMaxK - 1; j >= 0; --j) {
+        if (carry && j < c.k - 1) {
+            if (++c.dg[j] < c.m) carry = false;
+            else c.dg[j] = 0;
+        }
+    }
+    if (!carry) return true;
+    const int r = c.k - 2;
+    int piv = -1;
+#pragma unroll
+    for (int j = kMaxK - 1; j >= 0; --j)
+        if (piv < 0 && j < r && c.pre[j] < c.q - (r - j)) piv = j;
+    if (piv < 0) return false;
+    int run = 0;
+#pragma unroll
+    for (int t = 0; t < kMaxK; ++t) {
+        if (t == piv) { c.pre[t]++; run = c.pre[t]; }
+        else if (t > piv && t < r) { run++; c.pre[t] = run; }
+    }
+    return true;
 }
 
 // Move to the next chunk.  Returns true when the segment (hence the base)
@@ -175,36 +214,16 @@ __device__ __forceinline__ bool cursor_next(Cursor &c, const PT &P) {
         return true;
     }
     if (c.mode == SEG_LIST1 || c.k == 1) return true;  // single segment: end of job handled above
-    // prefix deltas, last digit fastest
-    {
-        bool carry = true;
-#pragma unroll
-        for (int j = kMaxK - 1; j >= 0; --j) {
-            if (carry && j < c.k - 1) {
-                if (++c.dg[j] < c.m) carry = false;
-                else c.dg[j] = 0;
-            }
-        }
-        if (!carry) return true;
+    // next group: step over this group's segments
+    bool within = true;
+    for (int t = 0; t < c.nw; ++t) within = seg_step(c);
+    if (within) {
+        c.s0 += c.nw;
+        c.nw = (int)min<int64_t>(c.wseg, c.nseg - c.s0);
+        return true;
     }
-    // next (k-2)-subset of [0, q) in lexicographic order
+    // next q: first (k-2)-subset of [0, q), zero prefix deltas (already wrapped)
     const int r = c.k - 2;
-    {
-        int piv = -1;
-#pragma unroll
-        for (int j = kMaxK - 1; j >= 0; --j)
-            if (piv < 0 && j < r && c.pre[j] < c.q - (r - j)) piv = j;
-        if (piv >= 0) {
-            int run = 0;
-#pragma unroll
-            for (int t = 0; t < kMaxK; ++t) {
-                if (t == piv) { c.pre[t]++; run = c.pre[t]; }
-                else if (t > piv && t < r) { run++; c.pre[t] = run; }
-            }
-            return true;
-        }
-    }
-    // next q
     c.q++;
 #pragma unroll
     for (int t = 0; t < kMaxK; ++t) {
@@ -212,6 +231,11 @@ __device__ __forceinline__ bool cursor_next(Cursor &c, const PT &P) {
         if (t == r) c.pre[t] = c.q;
     }
     cursor_set_q<CH>(c);
+    int64_t mk1 = 1;
+    for (int j = 0; j < c.k - 1; ++j) mk1 *= c.m;
+    c.nseg = binom_small(c.q, r) * mk1;
+    c.s0 = 0;
+    c.nw = (int)min<int64_t>(c.wseg, c.nseg);
     return true;
 }
 
@@ -227,18 +251,17 @@ __device__ __forceinline__ bool last_element(const Cursor &c, const PT &P, int64
         i = (int)(o % c.m);
         return true;
     }
-    const int cand = J.order[o];
+    const int cand = gld(J.order + o);
     p = cand / c.m;
     i = cand % c.m;
     if (c.mode == SEG_SHELL) {
-        const int head = J.order[c.shell];
+        const int head = gld(J.order + c.shell);
         pfirst = head / c.m;
         ifirst = head % c.m;
         return p != pfirst;
     }
     return true;
 }
-
 
 // Quotient floor(x / m) for the per-point hot path: a multiply-high by
 // M = ceil(2^32 / m) (cursor field mmagic) is exact for x < 2^32 / m, which

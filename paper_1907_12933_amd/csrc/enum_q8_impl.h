@@ -47,16 +47,14 @@ __device__ __forceinline__ int as_int(short2_t v) { return __builtin_bit_cast(in
 __device__ __forceinline__ short2_t as_s2(int v) { return __builtin_bit_cast(short2_t, v); }
 
 // Base of the current segment: clean first-layer potentials plus the
-// prefix's column updates e * W1[:, p].  Every lane computes the values of
-// its lane group g for all K-blocks (positions 64 kb + 16 g + b): as packed
-// int16 in the scaled window form v = f*u - 16384 (clamped so that adding
-// any last-element update cannot overflow) for the packed path, and as
-// int32 u - 64 * 2^s into the wave's LDS slice for the general path.
+// prefix's column updates e * W1[:, p], one position per lane and K-block
+// (positions lane + 64 r, coalesced).  Packed path: int16 v = f u - 16384
+// into the wave's LDS slice base16, clamped so that adding any last-element
+// update cannot overflow; int32 path: u - 64 * 2^s into base32.
 template <int KB1>
 __device__ __forceinline__ void build_base(const Cursor &c, const EnumParams &P, const int32_t *u0s, int32_t *base32,
-                                           int (&vb)[KB1][8], int lane, int ulo, int uhi) {
+                                           int16_t *base16, int lane, int ulo, int uhi) {
     const int H1 = KB1 * 64;
-    const int g = lane >> 4;
     int pp[kMaxK], ee[kMaxK];
     int np = 0;
     if (c.mode == SEG_PLAIN) {
@@ -76,47 +74,84 @@ __device__ __forceinline__ void build_base(const Cursor &c, const EnumParams &P,
         for (int j = 0; j < kMaxK; ++j) { pp[j] = 0; ee[j] = 0; }
         if (c.mode == SEG_SHELL) {
             np = 1;
-            const int head = wave_uniform(P.jobs[c.job].order[c.shell]);
+            const int head = wave_uniform(gld(P.jobs[c.job].order + c.shell));
             pp[0] = head / c.m;
             const int xv = wave_uniform((int)gld(c.img + pp[0]));
             ee[0] = clamp_pixel(xv + wave_uniform((int)gld(c.dl + head - pp[0] * c.m))) - xv;
         }
     }
-    // u = u0 + sum_j e_j W1[:, p_j] at positions lane + 64 r (coalesced)
     const int off = 64 << P.net.shift[0];
+    const int f = P.net.f1;
 #pragma unroll
     for (int r = 0; r < KB1; ++r) {
         const int q = lane + 64 * r;
         int v = u0s[q];
         for (int j = 0; j < np; ++j) v += ee[j] * (int)P.net.W1T[(int64_t)pp[j] * H1 + q];
-        base32[q] = P.packed ? v : v - off;
+        if (P.packed) {
+            // u is first clamped to [ulo, uhi], outside of which the product
+            // clamps to the same bound, so that f u fits in 32 bits
+            const int w = min(max(v, ulo), uhi) * f - 16384;
+            base16[q] = (int16_t)min(max(w, P.vb_lo), P.vb_hi);
+        } else {
+            base32[q] = v - off;
+        }
     }
-    if (P.packed) {
-        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
-        __builtin_amdgcn_wave_barrier();
-        // this lane group's positions 64 kb + 16 g + b as packed int16 v = f u - 16384,
-        // clamped so that adding any last-element update cannot overflow
-        const int f = P.net.f1;
+}
+
+// Rank of a recorded point (see the header's point rank) from the segment's
+// uniform part: plain segments and single-pixel lists add p m^k + i to r0;
+// level-2 shells combine the head (ph, ih) and the partner (p, i) in pixel
+// order.
+struct EmitInfo {
+    int prop, k, slot, mode, n, m, ph, ih;
+    int64_t r0, mk;
+};
+
+template <class PT>
+__device__ __forceinline__ EmitInfo make_emit_info(const Cursor &c, const PT &P) {
+    EmitInfo e;
+    e.prop = c.prop;
+    e.k = c.k;
+    e.slot = c.slot;
+    e.mode = c.mode;
+    e.n = c.n;
+    e.m = c.m;
+    e.ph = 0;
+    e.ih = 0;
+    int64_t mk = 1;
+    for (int j = 0; j < c.k; ++j) mk *= c.m;
+    e.mk = mk;
+    if (c.mode == SEG_SHELL) {
+        const int head = wave_uniform(gld(P.jobs[c.job].order + c.shell));
+        e.ph = head / c.m;
+        e.ih = head - e.ph * c.m;
+        e.r0 = 0;
+        return e;
+    }
+    // plain k >= 1 (and single-pixel lists, k == 1): prefix pixels pre[0..k-2]
+    int64_t s = 0, d = 0;
+    if (c.mode == SEG_PLAIN) {
+        // fixed trip count: the cursor's arrays stay in registers
 #pragma unroll
-        for (int kb = 0; kb < KB1; ++kb) {
-            const int4 *src = reinterpret_cast<const int4 *>(base32 + kb * 64 + g * 16);
-#pragma unroll
-            for (int t4 = 0; t4 < 4; ++t4) {
-                const int4 u = src[t4];
-                const int uu[4] = {u.x, u.y, u.z, u.w};
-                int h[4];
-#pragma unroll
-                for (int z = 0; z < 4; ++z) {
-                    // u is first clamped to [ulo, uhi], outside of which the
-                    // product clamps to the same bound, so that f u fits in 32 bits
-                    const int w = min(max(uu[z], ulo), uhi) * f - 16384;
-                    h[z] = min(max(w, P.vb_lo), P.vb_hi);
-                }
-                vb[kb][2 * t4] = (h[0] & 0xffff) | (h[1] << 16);
-                vb[kb][2 * t4 + 1] = (h[2] & 0xffff) | (h[3] << 16);
+        for (int j = 0; j < kMaxK; ++j) {
+            if (j < c.k - 1) {
+                s += binom_small(c.n - 1 - c.pre[j], c.k - j);
+                d = d * c.m + c.dg[j];
             }
         }
     }
+    e.r0 = (binom_small(c.n, c.k) - 1 - s - (c.n - 1)) * mk + d * c.m;
+    return e;
+}
+
+__device__ __forceinline__ int64_t rank_of(const EmitInfo &e, int p, int i) {
+    if (e.mode != SEG_SHELL) return e.r0 + (int64_t)p * e.mk + i;
+    const bool hf = e.ph < p;
+    const int a = hf ? e.ph : p, b = hf ? p : e.ph;
+    const int da = hf ? e.ih : i, db = hf ? i : e.ih;
+    const int64_t x = e.n - 1 - a;
+    const int64_t c2n = (int64_t)e.n * (e.n - 1) / 2;
+    return (c2n - 1 - x * (x - 1) / 2 - (e.n - 1 - b)) * e.mk + (int64_t)da * e.m + db;
 }
 
 // Lowest-index maximum over one 16-row tile of logits (this lane's four
@@ -148,42 +183,89 @@ __device__ __forceinline__ void argmax_combine(int &bv, int &bi, int &bc) {
     }
 }
 
-// Record the violations of one 16-point tile (lanes of group 0 carry the
-// points): one atomic per wave reserves the slots, lanes write their record.
-__device__ __forceinline__ void emit_tile(const EnumParams &P, const Cursor &c, bool viol, int p, int i, int label,
+// Per-wave record output: slots come in blocks of kRecBlock from one atomic
+// (most tiles then write without any atomic), and counterexample / tie
+// counts gather per level slot until the slot changes.  All fields are
+// wave-uniform.
+struct RecOut {
+    int64_t next, end;   // free slots of the current block
+    int slot;            // level slot being counted
+    unsigned long long cex, ties;
+};
+
+__device__ __forceinline__ void rec_flush_counts(const EnumParams &P, RecOut &o, int lane) {
+    if (o.slot >= 0 && lane == 0) {
+        if (o.cex) atomicAdd(P.slot_cex + o.slot, o.cex);
+        if (o.ties) atomicAdd(P.slot_ties + o.slot, o.ties);
+    }
+    o.cex = 0;
+    o.ties = 0;
+}
+
+__device__ __forceinline__ void rec_tally(const EnumParams &P, RecOut &o, int slot, unsigned ncex, unsigned nties,
                                           int lane) {
+    if (slot != o.slot) {
+        rec_flush_counts(P, o, lane);
+        o.slot = slot;
+    }
+    o.cex += ncex;
+    o.ties += nties;
+}
+
+// At the wave's end: counts out, sentinels into the block's unused slots.
+__device__ __forceinline__ void rec_finish(const EnumParams &P, RecOut &o, int lane) {
+    rec_flush_counts(P, o, lane);
+    const int64_t idx = o.next + lane;
+    if (lane < kRecBlock && idx < o.end && idx < P.rec_cap) {
+        CexRec r;
+        r.prop = -1;
+        r.k = 0;
+        r.rank = -1;
+        r.label = -1;
+        r.reserved = 0;
+        P.recs[idx] = r;
+    }
+}
+
+// Record the violations of one 16-point tile (lanes of group 0 carry the
+// points) in the wave's current block, continuing in a new block when it
+// runs out (a tile holds at most 16 records, a block 64).
+__device__ __forceinline__ void emit_tile(const EnumParams &P, RecOut &o, const EmitInfo &e, int64_t gchunk,
+                                          bool viol, int p, int i, int label, int lane) {
     const unsigned long long vm = __ballot(viol);
     if (!vm) return;
-    unsigned long long start = 0;
+    const int n = __popcll(vm);
+    const int64_t room = o.end - o.next;
+    int64_t nb = 0;
+    if (n > room) {
+        unsigned long long start = 0;
+        if (lane == 0) start = atomicAdd(P.rec_count, (unsigned long long)kRecBlock);
+        nb = (int64_t)wave_uniform(start);  // lane 0's value
+    }
     if (lane == 0) {
-        start = atomicAdd(P.rec_count, (unsigned long long)__popcll(vm));
-        atomicAdd(P.slot_cex + c.slot, (unsigned long long)__popcll(vm));
-        atomicMin(P.first_chunk, (unsigned long long)c.chunk);
+        if (P.track_first) atomicMin(P.first_chunk, (unsigned long long)gchunk);
         if (P.hit_host) *P.hit_host = 1;
         if (P.stop_on_first) *P.stop_flag = 1;
     }
-    start = wave_uniform(start);  // lane 0's value
-    // The rank arithmetic runs for tiles with counterexamples only: passing
-    // the level's shape through an empty asm keeps the compiler from hoisting
-    // its many uniform conditions into the common path.
-    Cursor cl = c;
-    cl.k = wave_uniform(c.k);
-    cl.n = wave_uniform(c.n);
-    cl.m = wave_uniform(c.m);
-    cl.mode = wave_uniform(c.mode);
-    asm volatile("" : "+s"(cl.k), "+s"(cl.n), "+s"(cl.m), "+s"(cl.mode));
+    rec_tally(P, o, e.slot, (unsigned)n, 0u, lane);
     if (viol) {
-        const unsigned long long below = vm & ((1ull << lane) - 1ull);
-        const int64_t idx = (int64_t)start + __popcll(below);
+        const int t = __popcll(vm & ((1ull << lane) - 1ull));
+        const int64_t idx = t < room ? o.next + t : nb + (t - room);
         if (idx < P.rec_cap) {
             CexRec r;
-            r.prop = c.prop;
-            r.k = c.k;
-            r.rank = point_rank(cl, P, p, i);
+            r.prop = e.prop;
+            r.k = e.k;
+            r.rank = rank_of(e, p, i);
             r.label = label;
             r.reserved = 0;
             P.recs[idx] = r;
         }
+    }
+    if (n > room) {
+        o.next = nb + (n - room);
+        o.end = nb + kRecBlock;
+    } else {
+        o.next += n;
     }
 }
 
@@ -191,53 +273,63 @@ __device__ __forceinline__ unsigned fold_groups(unsigned long long m) {
     return (unsigned)((m | (m >> 16) | (m >> 32) | (m >> 48)) & 0xffffull);
 }
 
-// Loads of one chunk's first layer, issued together before any is used:
-// each tile's pixel, delta and weight column slice (packed path: 16 int16 of
-// f W1 per K-block in two 16-byte halves; int32 path: 16 int8 of W1, the
-// second half then repeats the first).  The path is a uniform select, so that
-// no branch separates the loads from each other.
+// Loads of one chunk's first layer, issued together (a chunk ahead of
+// their use): each tile's pixel, delta and weight column slice (packed path:
+// 16 int16 of f W1 per K-block in two 16-byte halves; int32 path: 16 int8 of
+// W1, the second half then repeats the first).  The path is a uniform
+// select, so that no branch separates the loads from each other.
 template <int KB1, int NT>
-__device__ __forceinline__ void layer1_loads(const Cursor &c, const QNetDev &net, bool packed, const int (&plast)[NT],
-                                             const int (&ilast)[NT], int g, int (&ev)[NT], v4i (&wa)[NT][KB1],
-                                             v4i (&wb)[NT][KB1]) {
+struct L1Loads {
+    int xv[NT], dv[NT];
+    v4i wa[NT][KB1], wb[NT][KB1];
+};
+
+template <int KB1, int NT>
+__device__ __forceinline__ void layer1_issue(const Cursor &c, const QNetDev &net, bool packed, const int (&plast)[NT],
+                                             const int (&ilast)[NT], int g, L1Loads<KB1, NT> &ld) {
     constexpr int H1 = KB1 * 64;
     const int kstride = packed ? 128 : 64;  // bytes per K-block of a column
     const int boff = packed ? 16 : 0;
-    int xv[NT], dv[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-        xv[nt] = gld(c.img + plast[nt]);
-        dv[nt] = gld(c.dl + ilast[nt]);
+        ld.xv[nt] = gld(c.img + plast[nt]);
+        ld.dv[nt] = gld(c.dl + ilast[nt]);
         const char *wp = packed ? reinterpret_cast<const char *>(net.W1T16 + plast[nt] * H1 + g * 16)
                                 : reinterpret_cast<const char *>(net.W1T + plast[nt] * H1 + g * 16);
 #pragma unroll
         for (int kb = 0; kb < KB1; ++kb) {
-            wa[nt][kb] = gld(reinterpret_cast<const v4i *>(wp + kb * kstride));
-            wb[nt][kb] = gld(reinterpret_cast<const v4i *>(wp + kb * kstride + boff));
+            ld.wa[nt][kb] = gld(reinterpret_cast<const v4i *>(wp + kb * kstride));
+            ld.wb[nt][kb] = gld(reinterpret_cast<const v4i *>(wp + kb * kstride + boff));
         }
     }
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) ev[nt] = clamp_pixel(xv[nt] + dv[nt]) - xv[nt];
 }
 
 // First layer, packed int16 path: u = base + e W1[:, p] as v = f u - 16384
-// in 16-bit halves, clamped to [-16384, 16383], whose byte 1 is a - 64.
+// in 16-bit halves, clamped to [-16384, 16383], whose byte 1 is a - 64.  The
+// base of this lane group's 16 positions per K-block comes from LDS.
 template <int KB1, int NT>
-__device__ __forceinline__ void layer1_packed(const int (&ev)[NT], const v4i (&wa)[NT][KB1], const v4i (&wb)[NT][KB1],
-                                              const int (&vb)[KB1][8], v4i (&a1)[NT][KB1]) {
+__device__ __forceinline__ void layer1_packed(const L1Loads<KB1, NT> &ld, const int (&ev)[NT], const int16_t *base16,
+                                              int g, v4i (&a1)[NT][KB1]) {
     const short2_t vlo = {(short)-16384, (short)-16384};
     const short2_t vhi = {(short)16383, (short)16383};
+    v4i bl[KB1], bh[KB1];
+#pragma unroll
+    for (int kb = 0; kb < KB1; ++kb) {
+        bl[kb] = *reinterpret_cast<const v4i *>(base16 + kb * 64 + g * 16);
+        bh[kb] = *reinterpret_cast<const v4i *>(base16 + kb * 64 + g * 16 + 8);
+    }
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
         const short2_t e2 = {(short)ev[nt], (short)ev[nt]};
 #pragma unroll
         for (int kb = 0; kb < KB1; ++kb) {
-            const int wv[8] = {wa[nt][kb][0], wa[nt][kb][1], wa[nt][kb][2], wa[nt][kb][3],
-                               wb[nt][kb][0], wb[nt][kb][1], wb[nt][kb][2], wb[nt][kb][3]};
+            const int wv[8] = {ld.wa[nt][kb][0], ld.wa[nt][kb][1], ld.wa[nt][kb][2], ld.wa[nt][kb][3],
+                               ld.wb[nt][kb][0], ld.wb[nt][kb][1], ld.wb[nt][kb][2], ld.wb[nt][kb][3]};
+            const int bv[8] = {bl[kb][0], bl[kb][1], bl[kb][2], bl[kb][3], bh[kb][0], bh[kb][1], bh[kb][2], bh[kb][3]};
             int pr2[8];
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                short2_t u = as_s2(vb[kb][t]) + e2 * as_s2(wv[t]);
+                short2_t u = as_s2(bv[t]) + e2 * as_s2(wv[t]);
                 u = __builtin_elementwise_max(u, vlo);
                 u = __builtin_elementwise_min(u, vhi);
                 pr2[t] = as_int(u);
@@ -253,14 +345,14 @@ __device__ __forceinline__ void layer1_packed(const int (&ev)[NT], const v4i (&w
 // First layer, int32 path: u - 64 * 2^s from the wave's LDS base plus
 // e W1[:, p], requantised to a - 64.
 template <int KB1, int NT>
-__device__ __forceinline__ void layer1_int32(const int (&ev)[NT], const v4i (&wa)[NT][KB1], const v4i (&wb)[NT][KB1],
-                                             const int32_t *base32, int s1, int g, v4i (&a1)[NT][KB1]) {
+__device__ __forceinline__ void layer1_int32(const L1Loads<KB1, NT> &ld, const int (&ev)[NT], const int32_t *base32,
+                                             int s1, int g, v4i (&a1)[NT][KB1]) {
     // wb repeats wa on this path; consuming it here keeps its loads beside
     // the others instead of being sunk into the packed path
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-        for (int kb = 0; kb < KB1; ++kb) asm volatile("" ::"v"(wb[nt][kb]));
+        for (int kb = 0; kb < KB1; ++kb) asm volatile("" ::"v"(ld.wb[nt][kb]));
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
         const int e = ev[nt];
@@ -271,7 +363,7 @@ __device__ __forceinline__ void layer1_int32(const int (&ev)[NT], const v4i (&wa
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int4 bv = bp[t];
-                const int w = wa[nt][kb][t];
+                const int w = ld.wa[nt][kb][t];
                 v4i u = {bv.x + e * (int)(int8_t)(w & 0xff), bv.y + e * (int)(int8_t)((w >> 8) & 0xff),
                          bv.z + e * (int)(int8_t)((w >> 16) & 0xff), bv.w + e * (int)(int8_t)(w >> 24)};
                 out[t] = requant4_offset(u, s1);
@@ -340,7 +432,11 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
     const int32_t *bls = b2s + nb2;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int j16 = lane & 15, g = lane >> 4;
-    int32_t *base32 = reinterpret_cast<int32_t *>(smem + wbytes) + nb2 + nbl + wave * H1;
+    // per wave: one int32 base (int32 path) or kSegGroup int16 bases (packed path)
+    constexpr int SLOT = (H1 * 4 > kSegGroup * H1 * 2) ? H1 * 4 : kSegGroup * H1 * 2;  // bytes
+    char *wslot = smem + wbytes + 4 * (nb2 + nbl) + wave * SLOT;
+    int32_t *base32 = reinterpret_cast<int32_t *>(wslot);
+    int16_t *base16 = reinterpret_cast<int16_t *>(wslot);
 
     // output layer of at most 16 classes: weights and init held in registers
     v4i Wo[OUT16 ? KBL : 1];
@@ -356,11 +452,6 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
             if (g * 4 + t >= net.dims[L]) bo4[t] = INT32_MIN;
     }
 
-    Cursor c;
-    c.job = -1;
-    bool have = false;
-    int64_t cur_chunk = 0, end_chunk = 0;
-    int fetches = 0;
     const int s1 = net.shift[0];
     const int s2 = (L == 3) ? net.shift[1] : 0;
     const int ncls = net.dims[L];
@@ -377,60 +468,114 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
         ulo = a0 >= 0 ? a0 / f : -((-a0 + f - 1) / f);   // floor(a0 / f)
         uhi = a1v >= 0 ? (a1v + f - 1) / f : -((-a1v) / f);  // ceil(a1v / f)
     }
-    int vb[KB1][8];
-    // clean label of the current property and, per lane (OUT16), bit t set
-    // when this lane's class 4 g + t has a lower index than the label
-    int label0 = -1, cur_prop = -1;
-    int lowbits = 0;
 
-    while (true) {
-        if (cur_chunk >= end_chunk) {
-            unsigned long long start = 0;
-            if (lane == 0) start = atomicAdd(P.queue, (unsigned long long)P.batch);
-            start = wave_uniform(start);  // lane 0's value
-            if ((int64_t)start >= P.total_chunks) break;
-            if (wave_uniform(*P.stop_flag)) break;
-            // host-mapped: poll sparsely
-            if (P.abort_host && (fetches++ & 15) == 0 && wave_uniform(*P.abort_host)) break;
-            cur_chunk = (int64_t)start;
-            end_chunk = min((int64_t)start + P.batch, P.total_chunks);
-            cursor_decode<CH, EnumParams>(c, P, cur_chunk);
-            have = false;
+    // ---- work distribution: batches of chunks from the global queue; the
+    // cursor always describes the chunk whose first-layer loads are in flight
+    Cursor c;
+    c.job = -1;
+    int64_t cur_chunk = 0, end_chunk = 0;
+    int fetches = 0;
+    // next chunk of this wave; false when the queue is exhausted or a stop
+    // or abort was requested.  seg: the segment (hence the base) changed.
+    auto advance = [&](bool first, bool &seg) __attribute__((always_inline)) -> bool {
+        if (!first && ++cur_chunk < end_chunk) {
+            seg = cursor_next<CH, EnumParams>(c, P);
+            return true;
         }
-        if (!have) {
+        unsigned long long start = 0;
+        if (lane == 0) start = atomicAdd(P.queue, (unsigned long long)P.batch);
+        start = wave_uniform(start);  // lane 0's value
+        if ((int64_t)start >= P.total_chunks) return false;
+        if (wave_uniform(*P.stop_flag)) return false;
+        // host-mapped: poll sparsely
+        if (P.abort_host && (fetches++ & 15) == 0 && wave_uniform(*P.abort_host)) return false;
+        cur_chunk = (int64_t)start;
+        end_chunk = min((int64_t)start + P.batch, P.total_chunks);
+        cursor_decode<CH, EnumParams>(c, P, cur_chunk);
+        seg = true;
+        return true;
+    };
+
+    // state of the chunk at the cursor (prepared a chunk ahead)
+    EmitInfo ein;
+    int64_t gchunk_n = 0;
+    int label_n = -1, lowbits_n = 0, prop_n = -1;
+    bool valid_n[NT];
+    int plast_n[NT], ilast_n[NT];
+    L1Loads<KB1, NT> ld;
+    // segment set-up when needed, then positions and first-layer loads
+    // segments of the group: their bases in LDS slots, their rank offsets
+    // in lane w of r0lo / r0hi
+    int nw_n = 1, r0lo_n = 0, r0hi_n = 0;
+    auto prepare = [&](bool seg) __attribute__((always_inline)) {
+        if (seg) {
             const int32_t *u0s = u0_store + (int64_t)wave_uniform(u0_index[c.prop]) * u0_stride;
-            build_base<KB1>(c, P, u0s, base32, vb, lane, ulo, uhi);
+            Cursor ct = c;
+            for (int w = 0; w < c.nw; ++w) {
+                build_base<KB1>(ct, P, u0s, base32, base16 + w * H1, lane, ulo, uhi);
+                const EmitInfo e = make_emit_info<EnumParams>(ct, P);
+                if (w == 0) ein = e;
+                if (lane == w) { r0lo_n = (int)(uint32_t)e.r0; r0hi_n = (int)(e.r0 >> 32); }
+                if (w + 1 < c.nw) seg_step(ct);
+            }
+            nw_n = c.nw;
             __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): LDS writes done
             __builtin_amdgcn_wave_barrier();
-            have = true;
         }
-        if (c.prop != cur_prop) {
-            cur_prop = c.prop;
-            label0 = wave_uniform(P.props[c.prop].label0);
-            lowbits = 0;
+        if (c.prop != prop_n) {
+            prop_n = c.prop;
+            label_n = wave_uniform(P.props[c.prop].label0);
+            // bit t: this lane's class 4 g + t has a lower index than the label
+            lowbits_n = 0;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) lowbits |= (4 * g + t < label0 ? 1 : 0) << t;
+            for (int t = 0; t < 4; ++t) lowbits_n |= (4 * g + t < label_n ? 1 : 0) << t;
         }
-
-        // ---- positions of the chunk's points: last element (p, i)
-        bool valid[NT];
-        int plast[NT], ilast[NT];
+        gchunk_n = c.chunk;
         const int obase = (int)c.ch * CH;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
-            valid[nt] = last_element32(c, P, obase + nt * 16 + j16, plast[nt], ilast[nt]);
+            valid_n[nt] = last_element32(c, P, obase + nt * 16 + j16, plast_n[nt], ilast_n[nt]);
+        layer1_issue<KB1, NT>(c, net, P.packed != 0, plast_n, ilast_n, g, ld);
+    };
 
-        // ---- layer 1: incremental update, requantisation, B operands.  All
-        // loads of the chunk (pixel, delta, weight column) are issued before
-        // any of them is used.
-        int ev[NT];
-        v4i wa[NT][KB1], wb[NT][KB1];
-        layer1_loads<KB1, NT>(c, net, P.packed != 0, plast, ilast, g, ev, wa, wb);
+    bool seg = false;
+    if (!advance(true, seg)) return;
+    prepare(seg);
+    RecOut ro;
+    ro.next = 0;
+    ro.end = 0;
+    ro.slot = -1;
+    ro.cex = 0;
+    ro.ties = 0;
+
+    while (true) {
+        // ---- the current chunk is the prepared one: the same last-element
+        // positions for each of the group's nw segments
+        const EmitInfo ei = ein;
+        const int64_t gchunk = gchunk_n;
+        const int label0 = label_n, lowbits = lowbits_n;
+        const int nw = nw_n, r0lo = r0lo_n, r0hi = r0hi_n;
+        bool valid[NT];
+        int plast[NT], ilast[NT], ev[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            valid[nt] = valid_n[nt];
+            plast[nt] = plast_n[nt];
+            ilast[nt] = ilast_n[nt];
+            ev[nt] = clamp_pixel(ld.xv[nt] + ld.dv[nt]) - ld.xv[nt];
+        }
+        bool more = true;
+        for (int w = 0; w < nw; ++w) {
+        EmitInfo ew = ei;
+        ew.r0 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(r0hi, w) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane(r0lo, w));
+
+        // ---- layer 1: incremental update, requantisation, B operands
         v4i a1[NT][KB1];
         if (P.packed)
-            layer1_packed<KB1, NT>(ev, wa, wb, vb, a1);
+            layer1_packed<KB1, NT>(ld, ev, base16 + w * H1, g, a1);
         else
-            layer1_int32<KB1, NT>(ev, wa, wb, base32, s1, g, a1);
+            layer1_int32<KB1, NT>(ld, ev, base32, s1, g, a1);
         if constexpr (L == 3) {
             if (dbl1) {  // uniform: one branch per chunk
 #pragma unroll
@@ -440,6 +585,13 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
 #pragma unroll
                         for (int z = 0; z < 4; ++z) a1[nt][kb][z] = double_bytes(a1[nt][kb][z]);
             }
+        }
+
+        // ---- after the group's last segment has used them, the next chunk's
+        // loads fly while this one goes through the MFMAs
+        if (w == nw - 1) {
+            more = advance(false, seg);
+            if (more) prepare(seg);
         }
 
         // ---- hidden layer 2 (L == 3): int8 MFMA, requantise into B operands;
@@ -555,9 +707,9 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
                     argmax_combine(bv, bi, bc);
                     const bool mine = g == 0 && ((viol16 >> j16) & 1u);
                     ties += (unsigned)__popcll(__ballot(mine && bc > 1));
-                    emit_tile(P, c, mine, plast[nt], ilast[nt], bi, lane);
+                    emit_tile(P, ro, ew, gchunk, mine, plast[nt], ilast[nt], bi, lane);
                 }
-                if (ties && lane == 0) atomicAdd(P.slot_ties + c.slot, (unsigned long long)ties);
+                if (ties) rec_tally(P, ro, ei.slot, 0u, ties, lane);
             }
         } else {
             // ---- general output layer: M-tiles in turn, full lowest-index argmax
@@ -588,17 +740,15 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
                 argmax_combine(bestv[nt], besti[nt], bestc[nt]);
                 const bool mine = valid[nt] && g == 0;
                 const unsigned long long tm = __ballot(mine && bestc[nt] > 1);
-                if (tm && lane == 0) atomicAdd(P.slot_ties + c.slot, (unsigned long long)__popcll(tm));
-                emit_tile(P, c, mine && besti[nt] != label0, plast[nt], ilast[nt], besti[nt], lane);
+                if (tm) rec_tally(P, ro, ei.slot, 0u, (unsigned)__popcll(tm), lane);
+                emit_tile(P, ro, ew, gchunk, mine && besti[nt] != label0, plast[nt], ilast[nt], besti[nt], lane);
             }
         }
 
-        // ---- advance
-        cur_chunk++;
-        if (cur_chunk < end_chunk) {
-            if (cursor_next<CH, EnumParams>(c, P)) have = false;
-        }
+        }  // segments of the group
+        if (!more) break;
     }
+    rec_finish(P, ro, lane);
 }
 
 #define IBMC_ENUM_VARIANT(L_, KB1_, KB2_, NT_, WLDS_, EPI_, O16_, TAG_)                                      \

@@ -34,14 +34,18 @@ static int64_t ipow64(int64_t a, int e) {
 
 // Chunks of a plain level; qcum receives the chunks before each last-prefix
 // pixel q (k >= 2).
-static int64_t plan_plain_level(int n, int m, int k, int CH, std::vector<int64_t> &qcum) {
+// Chunks of one plain level: for each last-prefix pixel q, its segments
+// (prefix subsets times prefix deltas) in groups of W, times the chunks of
+// one segment's last-element range.  qcum[q]: chunks before q.
+static int64_t plan_plain_level(int n, int m, int k, int CH, int W, std::vector<int64_t> &qcum) {
     if (k == 1) return ceil_div((int64_t)n * m, CH);
     qcum.assign(n, 0);
     const int64_t mk1 = ipow64(m, k - 1);
     int64_t acc = 0;
     for (int q = 0; q < n; ++q) {
         qcum[q] = acc;
-        if (q >= k - 2 && q <= n - 2) acc += binom_small(q, k - 2) * mk1 * ceil_div((int64_t)(n - 1 - q) * m, CH);
+        if (q >= k - 2 && q <= n - 2)
+            acc += ceil_div(binom_small(q, k - 2) * mk1, W) * ceil_div((int64_t)(n - 1 - q) * m, CH);
     }
     return acc;
 }
@@ -134,12 +138,14 @@ static ibmc_status validate_props(const ibmc_property *props, int32_t n_props, c
 
 // Copy n device records to the host ordered by (prop, k, rank): radix-sorted
 // on the device when the packed key fits 64 bits, else sorted on the host.
-static ibmc_status fetch_sorted(ibmc_ctx *ctx, const CexRec *drecs, int64_t n, int max_prop, int max_k,
+// Sort the first n record slots on the device and bring back the first
+// `keep` records in (prop, k, rank) order, without the sentinels of unused
+// slots (prop -1), into outv or, when given, into `direct` (room for keep).
+static ibmc_status fetch_sorted(ibmc_ctx *ctx, const CexRec *drecs, int64_t n, int64_t keep, int max_prop, int max_k,
                                 int64_t max_rank, std::vector<CexRec> &outv, CexRec *direct = nullptr) {
     hipStream_t s = ctx->stream;
-    if (!direct) outv.resize(n);
-    CexRec *out = direct ? direct : outv.data();
-    if (n == 0) return IBMC_OK;
+    outv.clear();
+    if (n == 0 || keep == 0) return IBMC_OK;
     IBMC_TRY(ctx->sortbuf.reserve(sort_scratch_bytes(n)));
     SortScratch S;
     sort_scratch_carve(ctx->sortbuf.p, n, S);
@@ -147,23 +153,34 @@ static ibmc_status fetch_sorted(ibmc_ctx *ctx, const CexRec *drecs, int64_t n, i
     const int st = sort_records_device(drecs, n, max_prop, max_k, max_rank, S, s, &bits);
     if (st == SORT_HIP_ERROR) return fail(IBMC_E_HIP, "record sort launch failed");
     if (st == SORT_UNSUPPORTED) {
-        HIP_OK(hipMemcpyAsync(out, drecs, n * sizeof(CexRec), hipMemcpyDeviceToHost, s));
+        std::vector<CexRec> all(n);
+        HIP_OK(hipMemcpyAsync(all.data(), drecs, n * sizeof(CexRec), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
-        std::sort(out, out + n, [](const CexRec &a, const CexRec &b) {
+        all.erase(std::remove_if(all.begin(), all.end(), [](const CexRec &r) { return r.prop < 0; }), all.end());
+        std::sort(all.begin(), all.end(), [](const CexRec &a, const CexRec &b) {
             if (a.prop != b.prop) return a.prop < b.prop;
             if (a.k != b.k) return a.k < b.k;
             return a.rank < b.rank;
         });
+        if ((int64_t)all.size() > keep) all.resize(keep);
+        if (direct) memcpy(direct, all.data(), all.size() * sizeof(CexRec));
+        else outv.swap(all);
         return IBMC_OK;
     }
-    ctx->hkeys.resize(n);
-    ctx->hvals.resize(n);
-    HIP_OK(hipMemcpyAsync(ctx->hkeys.data(), S.keys_out, n * 8, hipMemcpyDeviceToHost, s));
-    HIP_OK(hipMemcpyAsync(ctx->hvals.data(), S.vals_out, n * 4, hipMemcpyDeviceToHost, s));
+    // sentinels sort last (all key bits set); only the first keep slots matter
+    const int64_t m = std::min(n, keep);
+    ctx->hkeys.resize(m);
+    ctx->hvals.resize(m);
+    HIP_OK(hipMemcpyAsync(ctx->hkeys.data(), S.keys_out, m * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(ctx->hvals.data(), S.vals_out, m * 4, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
+    int64_t valid = m;
+    while (valid > 0 && ctx->hkeys[valid - 1] == ~0ull) --valid;
+    if (!direct) outv.resize(valid);
+    CexRec *out = direct ? direct : outv.data();
     const uint64_t rmask = (S.kshift >= 64) ? ~0ull : ((1ull << S.kshift) - 1ull);
     const uint64_t kmask = (1ull << (S.pshift - S.kshift)) - 1ull;
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t i = 0; i < valid; ++i) {
         const uint64_t key = ctx->hkeys[i];
         CexRec &r = out[i];
         r.prop = (int32_t)(S.pshift >= 64 ? 0 : (key >> S.pshift));
@@ -223,7 +240,6 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
     IBMC_TRY(ctx->counters.reserve(n_ctr * 8));
     unsigned long long *ctr = ctx->counters.as<unsigned long long>();
     const int64_t cap = o->cex_capacity, tcap = o->near_tie_capacity;
-    IBMC_TRY(ctx->recs.reserve((size_t)std::max<int64_t>(cap, 1) * sizeof(CexRec)));
     IBMC_TRY(ctx->ties.reserve((size_t)std::max<int64_t>(tcap, 1) * sizeof(CexRec)));
     int64_t max_h1 = 64;
     for (auto &pl : plans)
@@ -246,6 +262,18 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
             if (!pl.v) return fail(IBMC_E_UNIMPL, "no enumeration kernel for network %s", shape_key(net).c_str());
             CH = pl.v->chunk;
         }
+        if (q8) {
+            int maxe = 0;
+            for (int pid : pl.ids)
+                for (int j = 0; j < props[pid].n_deltas; ++j)
+                    maxe = std::max(maxe, std::min(255, std::abs((int)props[pid].deltas[j])));
+            const int64_t M2 = (int64_t)net->qd.f1 * maxe * net->qd.maxw1;
+            pl.packed = (net->qd.f1 > 0 && M2 <= 8191 && !ctx->force_int32_layer1) ? 1 : 0;
+            pl.vb_lo = (int32_t)(-16385 - M2);
+            pl.vb_hi = (int32_t)(16384 + M2);
+        }
+        // segment groups: the packed integer path keeps kSegGroup bases per wave
+        const int W = (q8 && pl.packed) ? kSegGroup : 1;
         pl.job_off = jobs.size();
         for (int pid : pl.ids) {
             const int n = net->dims[0], m = props[pid].n_deltas;
@@ -253,12 +281,13 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
                 const int k = B.level_k[pid][li];
                 if (k == 0) continue;
                 std::vector<int64_t> qc;
-                const int64_t ch = plan_plain_level(n, m, k, CH, qc);
+                const int64_t ch = plan_plain_level(n, m, k, CH, W, qc);
                 EnumJob J{};
                 J.prop = pid;
                 J.k = k;
                 J.slot = B.slot_base[pid] + li;
                 J.mode = SEG_PLAIN;
+                J.wseg = W;
                 J.chunk_begin = pl.total;
                 J.chunk_end = pl.total + ch;
                 qcum_off.push_back(k >= 2 ? qcum_all.size() : (size_t)-1);
@@ -269,14 +298,6 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
         }
         pl.n_jobs = jobs.size() - pl.job_off;
         if (q8) {
-            int maxe = 0;
-            for (int pid : pl.ids)
-                for (int j = 0; j < props[pid].n_deltas; ++j)
-                    maxe = std::max(maxe, std::min(255, std::abs((int)props[pid].deltas[j])));
-            const int64_t M2 = (int64_t)net->qd.f1 * maxe * net->qd.maxw1;
-            pl.packed = (net->qd.f1 > 0 && M2 <= 8191 && !ctx->force_int32_layer1) ? 1 : 0;
-            pl.vb_lo = (int32_t)(-16385 - M2);
-            pl.vb_hi = (int32_t)(16384 + M2);
             int occ = 0;
             HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, pl.v->fn, 256,
                                                                 (size_t)enum_lds_bytes(*pl.v, net->qd)));
@@ -287,6 +308,12 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
         }
         all_ids.insert(all_ids.end(), pl.ids.begin(), pl.ids.end());
     }
+    // record slots: the capacity plus one partly used block per wave of the
+    // integer kernels (whose unused slots hold sentinels)
+    int64_t rec_slots = cap;
+    for (auto &pl : plans)
+        if (pl.net->act == IBMC_ACT_RELU_Q8) rec_slots += (int64_t)pl.grid * 4 * kRecBlock;
+    IBMC_TRY(ctx->recs.reserve((size_t)std::max<int64_t>(rec_slots, 1) * sizeof(CexRec)));
     IBMC_TRY(ctx->qcum.reserve(std::max<size_t>(qcum_all.size(), 1) * 8));
     if (!qcum_all.empty())
         HIP_OK(hipMemcpyAsync(ctx->qcum.p, qcum_all.data(), qcum_all.size() * 8, hipMemcpyHostToDevice, s));
@@ -320,11 +347,12 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
             P.stop_flag = reinterpret_cast<volatile int32_t *>(ctr + 4);
             P.abort_host = ctx->flags_dev;
             P.hit_host = nullptr;
-            P.rec_cap = cap;
+            P.rec_cap = rec_slots;
             P.recs = ctx->recs.as<CexRec>();
             P.slot_cex = ctr + sc0;
             P.slot_ties = ctr + st0;
             P.stop_on_first = 0;
+            P.track_first = 0;
             P.packed = pl.packed;
             P.vb_lo = pl.vb_lo;
             P.vb_hi = pl.vb_hi;
@@ -342,7 +370,7 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
             P.tie_rel = (o->near_tie_rel > 0) ? o->near_tie_rel : kDefaultTieRel;
             P.queue = ctr + q0 + pi;
             P.rec_count = ctr + 1;
-            P.rec_cap = cap;
+            P.rec_cap = rec_slots;
             P.recs = ctx->recs.as<CexRec>();
             P.tie_count = ctr + 3;
             P.tie_cap = tcap;
@@ -426,11 +454,15 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
     std::vector<unsigned long long> h(n_ctr);
     HIP_OK(hipMemcpyAsync(h.data(), ctr, n_ctr * 8, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
-    rec_total = (int64_t)h[1];
     tie_total = (int64_t)h[3];
     slot_cex.assign(h.begin() + sc0, h.begin() + st0);
     slot_ties.assign(h.begin() + st0, h.begin() + st0 + B.n_slots);
-    const int64_t nr = std::min(rec_total, cap), nt = std::min(tie_total, tcap);
+    // exact total from the level counters; record slots handed out (with the
+    // sentinels of partly used blocks) from the record counter
+    rec_total = 0;
+    for (int i = 0; i < n_props; ++i)
+        for (int li : level_sel[i]) rec_total += (int64_t)slot_cex[B.slot_base[i] + li];
+    const int64_t nr = std::min((int64_t)h[1], rec_slots), nt = std::min(tie_total, tcap);
     int max_k = 0;
     int64_t max_rank = 0;
     for (const EnumJob &J : jobs) {
@@ -438,8 +470,8 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
         const int pid = J.prop;
         max_rank = std::max(max_rank, binom_small(props[pid].net->dims[0], J.k) * ipow64(props[pid].n_deltas, J.k));
     }
-    IBMC_TRY(fetch_sorted(ctx, ctx->recs.as<CexRec>(), nr, n_props - 1, max_k, max_rank, recs, direct_recs));
-    IBMC_TRY(fetch_sorted(ctx, ctx->ties.as<CexRec>(), nt, n_props - 1, max_k, max_rank, ties, direct_ties));
+    IBMC_TRY(fetch_sorted(ctx, ctx->recs.as<CexRec>(), nr, cap, n_props - 1, max_k, max_rank, recs, direct_recs));
+    IBMC_TRY(fetch_sorted(ctx, ctx->ties.as<CexRec>(), nt, tcap, n_props - 1, max_k, max_rank, ties, direct_ties));
     HIP_OK(hipMemcpyAsync(B.hprops.data(), ctx->props.p, n_props * sizeof(PropDev), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     if (ctx->flags_host[0]) return fail(IBMC_E_ABORTED, "check aborted");
@@ -719,10 +751,11 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
         J.k = k;
         J.slot = (int)li;
         J.chunk_begin = total;
+        J.wseg = 1;  // rank order
         int64_t ch = 0;
         if (!p) {
             J.mode = SEG_PLAIN;
-            ch = plan_plain_level(n, m, k, CH, qc);
+            ch = plan_plain_level(n, m, k, CH, 1, qc);
         } else if (k == 1) {
             J.mode = SEG_LIST1;
             ch = ceil_div(N1, CH);
@@ -743,7 +776,14 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
     HIP_OK(launch_fill_u64(ctr, n_ctr, 0ull, s));
     HIP_OK(launch_fill_u64(ctr + 2, 1, ~0ull, s));
     const int64_t cap = o->cex_capacity;
-    IBMC_TRY(ctx->recs.reserve((size_t)std::max<int64_t>(cap, 1) * sizeof(CexRec)));
+    // record slots: the capacity plus one partly used block per wave
+    int occ = 0;
+    const int64_t lds = enum_lds_bytes(*v, net->qd);
+    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, v->fn, 256, (size_t)lds));
+    if (occ < 1) return fail(IBMC_E_UNIMPL, "variant %s does not fit", v->name);
+    const int64_t grid = std::min<int64_t>((int64_t)ctx->n_cu * occ, std::max<int64_t>(1, total));
+    const int64_t rec_slots = cap + grid * 4 * kRecBlock;
+    IBMC_TRY(ctx->recs.reserve((size_t)std::max<int64_t>(rec_slots, 1) * sizeof(CexRec)));
     if (!qc.empty()) IBMC_TRY(ctx->qcum.upload(qc.data(), qc.size() * 8, s));
     DevBuf dscum;
     if (!scum.empty()) IBMC_TRY(dscum.upload(scum.data(), scum.size() * 8, s));
@@ -771,21 +811,17 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
         P.abort_host = ctx->flags_dev;
         P.hit_host = ctx->flags_dev + 1;
         P.stop_on_first = o->stop_at_first ? 1 : 0;
-        P.rec_cap = cap;
+        P.rec_cap = rec_slots;
         P.recs = ctx->recs.as<CexRec>();
         P.slot_cex = ctr + 8;
         P.slot_ties = ctr + 8 + n_slots;
+        P.track_first = 1;
         int maxe = 0;
         for (int i = 0; i < m; ++i) maxe = std::max(maxe, std::min(255, std::abs((int)deltas[i])));
         const int64_t M2 = (int64_t)net->qd.f1 * maxe * net->qd.maxw1;
         P.packed = (net->qd.f1 > 0 && M2 <= 8191 && !ctx->force_int32_layer1) ? 1 : 0;
         P.vb_lo = (int32_t)(-16385 - M2);
         P.vb_hi = (int32_t)(16384 + M2);
-        int occ = 0;
-        const int64_t lds = enum_lds_bytes(*v, net->qd);
-        HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, v->fn, 256, (size_t)lds));
-        if (occ < 1) return fail(IBMC_E_UNIMPL, "variant %s does not fit", v->name);
-        const int64_t grid = std::min<int64_t>((int64_t)ctx->n_cu * occ, std::max<int64_t>(1, total));
         HIP_OK(hipEventRecord(ctx->ek0, s));
         HIP_OK(launch_enum_q8(*v, (int)grid, P, ctx->u0.as<int32_t>(), net->qd.H[1], ctx->u0_index.as<int32_t>(), s));
         HIP_OK(hipEventRecord(ctx->ek1, s));
@@ -808,10 +844,12 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
     PropDev back;
     HIP_OK(hipMemcpyAsync(&back, ctx->props.p, sizeof(back), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
-    rec_total = (int64_t)h[1];
-    const int64_t nr = std::min(rec_total, cap);
+    rec_total = 0;
+    for (int li = 0; li < n_slots; ++li) rec_total += (int64_t)h[8 + li];
+    const int64_t nr = std::min((int64_t)h[1], rec_slots);
     std::vector<CexRec> recs;
-    IBMC_TRY(fetch_sorted(ctx, ctx->recs.as<CexRec>(), nr, 0, o->k_max, binom_small(n, 2) * m * m, recs));
+    IBMC_TRY(fetch_sorted(ctx, ctx->recs.as<CexRec>(), nr, cap, 0, o->k_max, binom_small(n, 2) * m * m, recs));
+    const int64_t nkept = (int64_t)recs.size();
     if (p) {
         order.resize(N1);
         HIP_OK(hipMemcpy(order.data(), ctx->order.p, N1 * 4, hipMemcpyDeviceToHost));
@@ -820,7 +858,7 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
     HIP_OK(hipEventSynchronize(ctx->ev1));
     float ms = 0.f;
     HIP_OK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    if (cex_buf && nr) memcpy(cex_buf, recs.data(), nr * sizeof(CexRec));
+    if (cex_buf && nkept) memcpy(cex_buf, recs.data(), nkept * sizeof(CexRec));
 
     // position of every record in the visiting order (hardware independent)
     int64_t first_pos = -1;

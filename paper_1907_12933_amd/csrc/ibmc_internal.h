@@ -118,7 +118,13 @@ struct EnumJob {
     const int64_t *qcum;   // plain k >= 2: chunks before last-prefix pixel q, [n]
     const int32_t *order;  // shell / list modes: candidate ids (p * m + i) by decreasing score
     const int64_t *shell_cum; // shell mode: chunks before shell t, [n*m + 1]
+    int32_t wseg;          // plain k >= 2: segments per group (one chunk covers the same
+                           // last-element positions of wseg consecutive segments); else 1
+    int32_t pad_;
 };
+
+// Segments per group of the integer kernel's packed path.
+constexpr int kSegGroup = 4;
 
 struct EnumParams {
     QNetDev net;
@@ -128,9 +134,9 @@ struct EnumParams {
     int64_t total_chunks;
     const PropDev *props;
     unsigned long long *queue;         // next unassigned chunk
-    unsigned long long *rec_count;     // records appended (exact, may exceed capacity)
-    int64_t rec_cap;
-    CexRec *recs;
+    unsigned long long *rec_count;     // record slots handed out (whole blocks of kRecBlock per wave)
+    int64_t rec_cap;                   // record slots in recs: capacity + kRecBlock per wave of the grid
+    CexRec *recs;                      // unused slots of a wave's last block hold a sentinel (prop -1)
     unsigned long long *slot_cex;      // per slot counterexamples
     unsigned long long *slot_ties;     // per slot exact top-2 ties
     unsigned long long *first_chunk;   // min chunk index holding a counterexample (ordered searches)
@@ -140,7 +146,12 @@ struct EnumParams {
     int32_t stop_on_first;
     int32_t packed;                    // packed int16 first layer (bound checked by the host)
     int32_t vb_lo, vb_hi;              // pre-clamp of the scaled base for the packed path
+    int32_t track_first;               // maintain first_chunk (ordered searches)
+    int32_t pad_;
 };
+
+// Record slots a wave of the integer kernel reserves at a time.
+constexpr int kRecBlock = 64;
 
 // Float enumeration parameters.
 struct FEnumParams {

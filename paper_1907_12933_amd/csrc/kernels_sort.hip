@@ -14,7 +14,8 @@ __global__ void __launch_bounds__(256) rec_to_key_kernel(const CexRec *recs, int
                                                          uint64_t *keys, uint32_t *vals) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const CexRec r = recs[i];
-        keys[i] = ((uint64_t)r.prop << pshift) | ((uint64_t)r.k << kshift) | (uint64_t)r.rank;
+        // sentinels of unused record slots (prop -1) sort last
+        keys[i] = r.prop < 0 ? ~0ull : ((uint64_t)r.prop << pshift) | ((uint64_t)r.k << kshift) | (uint64_t)r.rank;
         vals[i] = (uint32_t)r.label;
     }
 }
