@@ -217,12 +217,10 @@ __device__ __forceinline__ void rec_finish(const EnumParams &P, RecOut &o, int l
     rec_flush_counts(P, o, lane);
     const int64_t idx = o.next + lane;
     if (lane < kRecBlock && idx < o.end && idx < P.rec_cap) {
-        CexRec r;
-        r.prop = -1;
-        r.k = 0;
+        DevRec r;
         r.rank = -1;
-        r.label = -1;
-        r.reserved = 0;
+        r.prop = -1;
+        r.klab = 0;
         P.recs[idx] = r;
     }
 }
@@ -252,12 +250,10 @@ __device__ __forceinline__ void emit_tile(const EnumParams &P, RecOut &o, const 
         const int t = __popcll(vm & ((1ull << lane) - 1ull));
         const int64_t idx = t < room ? o.next + t : nb + (t - room);
         if (idx < P.rec_cap) {
-            CexRec r;
-            r.prop = e.prop;
-            r.k = e.k;
+            DevRec r;
             r.rank = rank_of(e, p, i);
-            r.label = label;
-            r.reserved = 0;
+            r.prop = e.prop;
+            r.klab = (e.k << 24) | (label & 0xffffff);
             P.recs[idx] = r;
         }
     }
@@ -438,12 +434,11 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
     int32_t *base32 = reinterpret_cast<int32_t *>(wslot);
     int16_t *base16 = reinterpret_cast<int16_t *>(wslot);
 
-    // output layer of at most 16 classes: weights and init held in registers
-    v4i Wo[OUT16 ? KBL : 1];
+    // output layer of at most 16 classes: one M-tile, its weight tiles read
+    // when needed, its init held in registers
+    const v4i *wo = reinterpret_cast<const v4i *>(wls) + lane;
     v4i bo4 = v4i{0, 0, 0, 0};
     if constexpr (OUT16) {
-#pragma unroll
-        for (int kb = 0; kb < KBL; ++kb) Wo[kb] = reinterpret_cast<const v4i *>(wls)[kb * 64 + lane];
         const int4 b = *reinterpret_cast<const int4 *>(bls + g * 4);
         bo4 = v4i{b.x, b.y, b.z, b.w};
         // padding classes start (and, with zero weights, stay) at INT32_MIN
@@ -645,9 +640,10 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
                     }
                     if constexpr (OUT16) {
                         if ((pm & 3) == 3) {
+                            const v4i w = wo[(pm >> 2) * 64];
 #pragma unroll
                             for (int nt = 0; nt < NT; ++nt)
-                                acco[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Wo[pm >> 2], blk[nt], acco[nt], 0, 0, 0);
+                                acco[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(w, blk[nt], acco[nt], 0, 0, 0);
                         }
                     }
                     if (mt < MT2) {
@@ -673,7 +669,7 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
             for (int kb = 0; kb < KBL; ++kb)
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt)
-                    acco[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Wo[kb], a1[nt][kb], acco[nt], 0, 0, 0);
+                    acco[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(wo[kb * 64], a1[nt][kb], acco[nt], 0, 0, 0);
         }
 
         if constexpr (OUT16) {

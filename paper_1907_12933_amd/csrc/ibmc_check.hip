@@ -141,7 +141,7 @@ static ibmc_status validate_props(const ibmc_property *props, int32_t n_props, c
 // Sort the first n record slots on the device and bring back the first
 // `keep` records in (prop, k, rank) order, without the sentinels of unused
 // slots (prop -1), into outv or, when given, into `direct` (room for keep).
-static ibmc_status fetch_sorted(ibmc_ctx *ctx, const CexRec *drecs, int64_t n, int64_t keep, int max_prop, int max_k,
+static ibmc_status fetch_sorted(ibmc_ctx *ctx, const DevRec *drecs, int64_t n, int64_t keep, int max_prop, int max_k,
                                 int64_t max_rank, std::vector<CexRec> &outv, CexRec *direct = nullptr) {
     hipStream_t s = ctx->stream;
     outv.clear();
@@ -153,10 +153,15 @@ static ibmc_status fetch_sorted(ibmc_ctx *ctx, const CexRec *drecs, int64_t n, i
     const int st = sort_records_device(drecs, n, max_prop, max_k, max_rank, S, s, &bits);
     if (st == SORT_HIP_ERROR) return fail(IBMC_E_HIP, "record sort launch failed");
     if (st == SORT_UNSUPPORTED) {
-        std::vector<CexRec> all(n);
-        HIP_OK(hipMemcpyAsync(all.data(), drecs, n * sizeof(CexRec), hipMemcpyDeviceToHost, s));
+        std::vector<DevRec> raw(n);
+        HIP_OK(hipMemcpyAsync(raw.data(), drecs, n * sizeof(DevRec), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
-        all.erase(std::remove_if(all.begin(), all.end(), [](const CexRec &r) { return r.prop < 0; }), all.end());
+        std::vector<CexRec> all;
+        all.reserve(n);
+        for (const DevRec &d : raw)
+            if (d.prop >= 0)
+                all.push_back(CexRec{d.prop, (int32_t)((uint32_t)d.klab >> 24), d.rank,
+                                     (int32_t)((uint32_t)d.klab & 0xffffffu), 0});
         std::sort(all.begin(), all.end(), [](const CexRec &a, const CexRec &b) {
             if (a.prop != b.prop) return a.prop < b.prop;
             if (a.k != b.k) return a.k < b.k;
@@ -240,7 +245,7 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
     IBMC_TRY(ctx->counters.reserve(n_ctr * 8));
     unsigned long long *ctr = ctx->counters.as<unsigned long long>();
     const int64_t cap = o->cex_capacity, tcap = o->near_tie_capacity;
-    IBMC_TRY(ctx->ties.reserve((size_t)std::max<int64_t>(tcap, 1) * sizeof(CexRec)));
+    IBMC_TRY(ctx->ties.reserve((size_t)std::max<int64_t>(tcap, 1) * sizeof(DevRec)));
     int64_t max_h1 = 64;
     for (auto &pl : plans)
         max_h1 = std::max<int64_t>(max_h1, pl.net->act == IBMC_ACT_RELU_Q8 ? pl.net->qd.H[1] : pl.net->dims[1]);
@@ -313,7 +318,7 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
     int64_t rec_slots = cap;
     for (auto &pl : plans)
         if (pl.net->act == IBMC_ACT_RELU_Q8) rec_slots += (int64_t)pl.grid * 4 * kRecBlock;
-    IBMC_TRY(ctx->recs.reserve((size_t)std::max<int64_t>(rec_slots, 1) * sizeof(CexRec)));
+    IBMC_TRY(ctx->recs.reserve((size_t)std::max<int64_t>(rec_slots, 1) * sizeof(DevRec)));
     IBMC_TRY(ctx->qcum.reserve(std::max<size_t>(qcum_all.size(), 1) * 8));
     if (!qcum_all.empty())
         HIP_OK(hipMemcpyAsync(ctx->qcum.p, qcum_all.data(), qcum_all.size() * 8, hipMemcpyHostToDevice, s));
@@ -348,7 +353,7 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
             P.abort_host = ctx->flags_dev;
             P.hit_host = nullptr;
             P.rec_cap = rec_slots;
-            P.recs = ctx->recs.as<CexRec>();
+            P.recs = ctx->recs.as<DevRec>();
             P.slot_cex = ctr + sc0;
             P.slot_ties = ctr + st0;
             P.stop_on_first = 0;
@@ -371,10 +376,10 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
             P.queue = ctr + q0 + pi;
             P.rec_count = ctr + 1;
             P.rec_cap = rec_slots;
-            P.recs = ctx->recs.as<CexRec>();
+            P.recs = ctx->recs.as<DevRec>();
             P.tie_count = ctr + 3;
             P.tie_cap = tcap;
-            P.ties = ctx->ties.as<CexRec>();
+            P.ties = ctx->ties.as<DevRec>();
             P.slot_cex = ctr + sc0;
             P.slot_ties = ctr + st0;
             P.stop_flag = reinterpret_cast<volatile int32_t *>(ctr + 4);
@@ -470,8 +475,8 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
         const int pid = J.prop;
         max_rank = std::max(max_rank, binom_small(props[pid].net->dims[0], J.k) * ipow64(props[pid].n_deltas, J.k));
     }
-    IBMC_TRY(fetch_sorted(ctx, ctx->recs.as<CexRec>(), nr, cap, n_props - 1, max_k, max_rank, recs, direct_recs));
-    IBMC_TRY(fetch_sorted(ctx, ctx->ties.as<CexRec>(), nt, tcap, n_props - 1, max_k, max_rank, ties, direct_ties));
+    IBMC_TRY(fetch_sorted(ctx, ctx->recs.as<DevRec>(), nr, cap, n_props - 1, max_k, max_rank, recs, direct_recs));
+    IBMC_TRY(fetch_sorted(ctx, ctx->ties.as<DevRec>(), nt, tcap, n_props - 1, max_k, max_rank, ties, direct_ties));
     HIP_OK(hipMemcpyAsync(B.hprops.data(), ctx->props.p, n_props * sizeof(PropDev), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     if (ctx->flags_host[0]) return fail(IBMC_E_ABORTED, "check aborted");
@@ -783,7 +788,7 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
     if (occ < 1) return fail(IBMC_E_UNIMPL, "variant %s does not fit", v->name);
     const int64_t grid = std::min<int64_t>((int64_t)ctx->n_cu * occ, std::max<int64_t>(1, total));
     const int64_t rec_slots = cap + grid * 4 * kRecBlock;
-    IBMC_TRY(ctx->recs.reserve((size_t)std::max<int64_t>(rec_slots, 1) * sizeof(CexRec)));
+    IBMC_TRY(ctx->recs.reserve((size_t)std::max<int64_t>(rec_slots, 1) * sizeof(DevRec)));
     if (!qc.empty()) IBMC_TRY(ctx->qcum.upload(qc.data(), qc.size() * 8, s));
     DevBuf dscum;
     if (!scum.empty()) IBMC_TRY(dscum.upload(scum.data(), scum.size() * 8, s));
@@ -812,7 +817,7 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
         P.hit_host = ctx->flags_dev + 1;
         P.stop_on_first = o->stop_at_first ? 1 : 0;
         P.rec_cap = rec_slots;
-        P.recs = ctx->recs.as<CexRec>();
+        P.recs = ctx->recs.as<DevRec>();
         P.slot_cex = ctr + 8;
         P.slot_ties = ctr + 8 + n_slots;
         P.track_first = 1;
@@ -848,7 +853,7 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
     for (int li = 0; li < n_slots; ++li) rec_total += (int64_t)h[8 + li];
     const int64_t nr = std::min((int64_t)h[1], rec_slots);
     std::vector<CexRec> recs;
-    IBMC_TRY(fetch_sorted(ctx, ctx->recs.as<CexRec>(), nr, cap, 0, o->k_max, binom_small(n, 2) * m * m, recs));
+    IBMC_TRY(fetch_sorted(ctx, ctx->recs.as<DevRec>(), nr, cap, 0, o->k_max, binom_small(n, 2) * m * m, recs));
     const int64_t nkept = (int64_t)recs.size();
     if (p) {
         order.resize(N1);

@@ -89,6 +89,15 @@ struct CexRec {
 };
 static_assert(sizeof(CexRec) == sizeof(ibmc_cex), "record layout");
 
+// Record as the enumeration kernels write it: 16 bytes, one vector store per
+// lane.  klab = k << 24 | new label.  prop -1 marks an unused slot.
+struct DevRec {
+    int64_t rank;
+    int32_t prop;
+    int32_t klab;
+};
+static_assert(sizeof(DevRec) == 16, "device record layout");
+
 // Per-property device data.
 struct PropDev {
     const uint8_t *image;  // dims[0] bytes
@@ -136,7 +145,7 @@ struct EnumParams {
     unsigned long long *queue;         // next unassigned chunk
     unsigned long long *rec_count;     // record slots handed out (whole blocks of kRecBlock per wave)
     int64_t rec_cap;                   // record slots in recs: capacity + kRecBlock per wave of the grid
-    CexRec *recs;                      // unused slots of a wave's last block hold a sentinel (prop -1)
+    DevRec *recs;                      // unused slots of a wave's last block hold a sentinel (prop -1)
     unsigned long long *slot_cex;      // per slot counterexamples
     unsigned long long *slot_ties;     // per slot exact top-2 ties
     unsigned long long *first_chunk;   // min chunk index holding a counterexample (ordered searches)
@@ -167,10 +176,10 @@ struct FEnumParams {
     unsigned long long *queue;
     unsigned long long *rec_count;
     int64_t rec_cap;
-    CexRec *recs;
+    DevRec *recs;
     unsigned long long *tie_count;
     int64_t tie_cap;
-    CexRec *ties;
+    DevRec *ties;
     unsigned long long *slot_cex;
     unsigned long long *slot_ties;
     volatile int32_t *stop_flag;

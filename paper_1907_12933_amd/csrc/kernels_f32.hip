@@ -229,9 +229,10 @@ __global__ void __launch_bounds__(256) enum_f32_kernel(FEnumParams P, const int3
                 atomicAdd(P.slot_ties + c.slot, 1ull);
                 const unsigned long long idx = atomicAdd(P.tie_count, 1ull);
                 if ((int64_t)idx < P.tie_cap) {
-                    CexRec r;
-                    r.prop = c.prop; r.k = c.k; r.rank = point_rank(c, P, s_p[tid], s_i[tid]);
-                    r.label = best; r.reserved = 0;
+                    DevRec r;
+                    r.rank = point_rank(c, P, s_p[tid], s_i[tid]);
+                    r.prop = c.prop;
+                    r.klab = (c.k << 24) | best;
                     P.ties[idx] = r;
                 }
             }
@@ -239,9 +240,10 @@ __global__ void __launch_bounds__(256) enum_f32_kernel(FEnumParams P, const int3
                 atomicAdd(P.slot_cex + c.slot, 1ull);
                 const unsigned long long idx = atomicAdd(P.rec_count, 1ull);
                 if ((int64_t)idx < P.rec_cap) {
-                    CexRec r;
-                    r.prop = c.prop; r.k = c.k; r.rank = point_rank(c, P, s_p[tid], s_i[tid]);
-                    r.label = best; r.reserved = 0;
+                    DevRec r;
+                    r.rank = point_rank(c, P, s_p[tid], s_i[tid]);
+                    r.prop = c.prop;
+                    r.klab = (c.k << 24) | best;
                     P.recs[idx] = r;
                 }
             }

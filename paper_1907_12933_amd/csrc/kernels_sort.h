@@ -21,7 +21,7 @@ size_t sort_scratch_bytes(int64_t n);
 void sort_scratch_carve(void *p, int64_t n, SortScratch &S);
 // Sort n records by (prop, k, rank).  SORT_UNSUPPORTED when the packed key
 // would need more than 64 bits (the caller then sorts on the host).
-ibmc_status_t sort_records_device(const CexRec *recs, int64_t n, int max_prop, int max_k, int64_t max_rank,
+ibmc_status_t sort_records_device(const DevRec *recs, int64_t n, int max_prop, int max_k, int64_t max_rank,
                                   SortScratch &S, hipStream_t s, int *key_bits_out);
 
 }  // namespace ibmc

@@ -10,13 +10,14 @@ constexpr int kRsThreads = 256;
 constexpr int kRsChunks = 16;                       // 256-key chunks per block tile
 constexpr int kRsTile = kRsThreads * kRsChunks;     // 4096 keys per block
 
-__global__ void __launch_bounds__(256) rec_to_key_kernel(const CexRec *recs, int64_t n, int kshift, int pshift,
+__global__ void __launch_bounds__(256) rec_to_key_kernel(const DevRec *recs, int64_t n, int kshift, int pshift,
                                                          uint64_t *keys, uint32_t *vals) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const CexRec r = recs[i];
+        const DevRec r = recs[i];
+        const uint64_t k = (uint32_t)r.klab >> 24;
         // sentinels of unused record slots (prop -1) sort last
-        keys[i] = r.prop < 0 ? ~0ull : ((uint64_t)r.prop << pshift) | ((uint64_t)r.k << kshift) | (uint64_t)r.rank;
-        vals[i] = (uint32_t)r.label;
+        keys[i] = r.prop < 0 ? ~0ull : ((uint64_t)r.prop << pshift) | (k << kshift) | (uint64_t)r.rank;
+        vals[i] = (uint32_t)r.klab & 0xffffffu;
     }
 }
 
@@ -96,7 +97,7 @@ __global__ void __launch_bounds__(256) rs_scatter_kernel(const uint64_t *kin, co
     }
 }
 
-ibmc_status_t sort_records_device(const CexRec *recs, int64_t n, int max_prop, int max_k, int64_t max_rank,
+ibmc_status_t sort_records_device(const DevRec *recs, int64_t n, int max_prop, int max_k, int64_t max_rank,
                                   SortScratch &S, hipStream_t s, int *key_bits_out) {
     int rbits = 1;
     while (rbits < 63 && ((int64_t)1 << rbits) <= max_rank) ++rbits;
