@@ -175,11 +175,11 @@ def main():
     imgs = torch.from_numpy(w.images).cuda()
     props = [(net, imgs[i], w.deltas, 1, 2) for i in range(args.images)]
     cap = 1 << 25
-
-    buf = np.empty(cap, ibmc.CEX_DTYPE)
+    # images and counterexample records both stay in HBM
+    buf = torch.empty(cap * ibmc.CEX_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
 
     def step():
-        return ibmc.ibmc_check_batch_dev(ctx, props, cex_capacity=cap, cex_buf=buf)
+        return ibmc.ibmc_check_batch_dev(ctx, props, cex_capacity=cap, cex_buf=buf, records_on_device=True)
 
     for _ in range(args.warmup):
         step()
@@ -192,6 +192,7 @@ def main():
         ksec.append(ks)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    cex = np.frombuffer(cex.cpu().numpy().tobytes(), dtype=ibmc.CEX_DTYPE)
     points = sum(s["points_total"] for s in sums)
     value = points * args.steps / dt
     n_cex = sum(s["cex_total"] for s in sums)

@@ -113,13 +113,15 @@ typedef struct {
  * point, never a counterexample).  stop_at_first: stop after the first level
  * that has a counterexample (Sec. II-B stops at the first violation).
  * cex_capacity / near_tie_capacity: room in the caller's record buffers.
- * near_tie_rel: float nets only; <= 0 selects 1e-4. */
+ * near_tie_rel: float nets only; <= 0 selects 1e-4.
+ * records_on_device: nonzero when cex_buf / near_tie_buf are device memory
+ * of the context's device (the records then never cross to the host). */
 typedef struct {
     int32_t k_min, k_max, k_step, stop_at_first;
     int64_t cex_capacity;
     int64_t near_tie_capacity;
     float near_tie_rel;
-    int32_t reserved;
+    int32_t records_on_device;
 } ibmc_check_opts;
 
 /* One counterexample (or near tie): decode with ibmc_decode_point.  prop is

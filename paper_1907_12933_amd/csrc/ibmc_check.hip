@@ -136,15 +136,16 @@ static ibmc_status validate_props(const ibmc_property *props, int32_t n_props, c
 }
 
 
-// Copy n device records to the host ordered by (prop, k, rank): radix-sorted
-// on the device when the packed key fits 64 bits, else sorted on the host.
-// Sort the first n record slots on the device and bring back the first
-// `keep` records in (prop, k, rank) order, without the sentinels of unused
-// slots (prop -1), into outv or, when given, into `direct` (room for keep).
+// Sort the first n record slots on the device by (prop, k, rank) and hand
+// out the first `keep` records without the sentinels of unused slots (prop
+// -1): into `direct` when given (device memory when direct_dev, else host;
+// room for keep records), else into outv.  *nout: records handed out.
 static ibmc_status fetch_sorted(ibmc_ctx *ctx, const DevRec *drecs, int64_t n, int64_t keep, int max_prop, int max_k,
-                                int64_t max_rank, std::vector<CexRec> &outv, CexRec *direct = nullptr) {
+                                int64_t max_rank, std::vector<CexRec> &outv, CexRec *direct, bool direct_dev,
+                                int64_t *nout) {
     hipStream_t s = ctx->stream;
     outv.clear();
+    *nout = 0;
     if (n == 0 || keep == 0) return IBMC_OK;
     IBMC_TRY(ctx->sortbuf.reserve(sort_scratch_bytes(n)));
     SortScratch S;
@@ -152,7 +153,7 @@ static ibmc_status fetch_sorted(ibmc_ctx *ctx, const DevRec *drecs, int64_t n, i
     int bits = 0;
     const int st = sort_records_device(drecs, n, max_prop, max_k, max_rank, S, s, &bits);
     if (st == SORT_HIP_ERROR) return fail(IBMC_E_HIP, "record sort launch failed");
-    if (st == SORT_UNSUPPORTED) {
+    if (st == SORT_UNSUPPORTED) {  // keys wider than 64 bits: order on the host
         std::vector<DevRec> raw(n);
         HIP_OK(hipMemcpyAsync(raw.data(), drecs, n * sizeof(DevRec), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
@@ -168,31 +169,38 @@ static ibmc_status fetch_sorted(ibmc_ctx *ctx, const DevRec *drecs, int64_t n, i
             return a.rank < b.rank;
         });
         if ((int64_t)all.size() > keep) all.resize(keep);
-        if (direct) memcpy(direct, all.data(), all.size() * sizeof(CexRec));
-        else outv.swap(all);
+        *nout = (int64_t)all.size();
+        if (direct && direct_dev) {
+            HIP_OK(hipMemcpyAsync(direct, all.data(), all.size() * sizeof(CexRec), hipMemcpyHostToDevice, s));
+            HIP_OK(hipStreamSynchronize(s));
+        } else if (direct) {
+            memcpy(direct, all.data(), all.size() * sizeof(CexRec));
+        } else {
+            outv.swap(all);
+        }
         return IBMC_OK;
     }
     // sentinels sort last (all key bits set); only the first keep slots matter
     const int64_t m = std::min(n, keep);
-    ctx->hkeys.resize(m);
-    ctx->hvals.resize(m);
-    HIP_OK(hipMemcpyAsync(ctx->hkeys.data(), S.keys_out, m * 8, hipMemcpyDeviceToHost, s));
-    HIP_OK(hipMemcpyAsync(ctx->hvals.data(), S.vals_out, m * 4, hipMemcpyDeviceToHost, s));
+    CexRec *dout = direct_dev ? direct : nullptr;
+    if (!dout) {
+        IBMC_TRY(ctx->recout.reserve((size_t)m * sizeof(CexRec)));
+        dout = ctx->recout.as<CexRec>();
+    }
+    HIP_OK(sorted_to_records(S, m, dout, s));
+    int64_t valid = 0;
+    HIP_OK(hipMemcpyAsync(&valid, S.count, 8, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
-    int64_t valid = m;
-    while (valid > 0 && ctx->hkeys[valid - 1] == ~0ull) --valid;
-    if (!direct) outv.resize(valid);
-    CexRec *out = direct ? direct : outv.data();
-    const uint64_t rmask = (S.kshift >= 64) ? ~0ull : ((1ull << S.kshift) - 1ull);
-    const uint64_t kmask = (1ull << (S.pshift - S.kshift)) - 1ull;
-    for (int64_t i = 0; i < valid; ++i) {
-        const uint64_t key = ctx->hkeys[i];
-        CexRec &r = out[i];
-        r.prop = (int32_t)(S.pshift >= 64 ? 0 : (key >> S.pshift));
-        r.k = (int32_t)((key >> S.kshift) & kmask);
-        r.rank = (int64_t)(key & rmask);
-        r.label = (int32_t)ctx->hvals[i];
-        r.reserved = 0;
+    *nout = valid;
+    if (direct_dev) return IBMC_OK;
+    CexRec *hout = direct;
+    if (!hout) {
+        outv.resize(valid);
+        hout = outv.data();
+    }
+    if (valid) {
+        HIP_OK(hipMemcpyAsync(hout, dout, valid * sizeof(CexRec), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
     }
     return IBMC_OK;
 }
@@ -218,7 +226,7 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
                               std::vector<unsigned long long> &slot_cex, std::vector<unsigned long long> &slot_ties,
                               std::vector<CexRec> &recs, std::vector<CexRec> &ties, int64_t &rec_total,
                               int64_t &tie_total, double &kernel_seconds, int &launches,
-                              CexRec *direct_recs = nullptr, CexRec *direct_ties = nullptr) {
+                              CexRec *direct_recs = nullptr, CexRec *direct_ties = nullptr, bool direct_dev = false) {
     (void)images_on_device;
     hipStream_t s = ctx->stream;
     std::vector<NetPlan> plans;
@@ -475,8 +483,11 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
         const int pid = J.prop;
         max_rank = std::max(max_rank, binom_small(props[pid].net->dims[0], J.k) * ipow64(props[pid].n_deltas, J.k));
     }
-    IBMC_TRY(fetch_sorted(ctx, ctx->recs.as<DevRec>(), nr, cap, n_props - 1, max_k, max_rank, recs, direct_recs));
-    IBMC_TRY(fetch_sorted(ctx, ctx->ties.as<DevRec>(), nt, tcap, n_props - 1, max_k, max_rank, ties, direct_ties));
+    int64_t nout = 0;
+    IBMC_TRY(fetch_sorted(ctx, ctx->recs.as<DevRec>(), nr, cap, n_props - 1, max_k, max_rank, recs, direct_recs,
+                          direct_dev, &nout));
+    IBMC_TRY(fetch_sorted(ctx, ctx->ties.as<DevRec>(), nt, tcap, n_props - 1, max_k, max_rank, ties, direct_ties,
+                          direct_dev, &nout));
     HIP_OK(hipMemcpyAsync(B.hprops.data(), ctx->props.p, n_props * sizeof(PropDev), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     if (ctx->flags_host[0]) return fail(IBMC_E_ABORTED, "check aborted");
@@ -569,7 +580,7 @@ ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props, int32_t 
         const bool direct = !o->stop_at_first;
         st = run_levels(ctx, props, n_props, &oo, B, sel, images_on_device, sc, stt, r, t, rt, tt, ks, nl,
                         direct ? reinterpret_cast<CexRec *>(cex_buf) : nullptr,
-                        direct ? reinterpret_cast<CexRec *>(tie_buf) : nullptr);
+                        direct ? reinterpret_cast<CexRec *>(tie_buf) : nullptr, o->records_on_device != 0);
         rounds++;
         if (st < 0 && st != IBMC_E_ABORTED) return st;
         ksec += ks;
@@ -600,8 +611,11 @@ ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props, int32_t 
         std::sort(all_ties.begin(), all_ties.end(), rec_less);
     }
     if (o->stop_at_first) {
-        if (cex_buf && !all_recs.empty()) memcpy(cex_buf, all_recs.data(), all_recs.size() * sizeof(CexRec));
-        if (tie_buf && !all_ties.empty()) memcpy(tie_buf, all_ties.data(), all_ties.size() * sizeof(CexRec));
+        const hipMemcpyKind kind = o->records_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
+        if (cex_buf && !all_recs.empty())
+            HIP_OK(hipMemcpy(cex_buf, all_recs.data(), all_recs.size() * sizeof(CexRec), kind));
+        if (tie_buf && !all_ties.empty())
+            HIP_OK(hipMemcpy(tie_buf, all_ties.data(), all_ties.size() * sizeof(CexRec), kind));
     }
     for (int i = 0; i < n_props; ++i) {
         ibmc_check_summary &S = outs[i];
@@ -853,8 +867,9 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
     for (int li = 0; li < n_slots; ++li) rec_total += (int64_t)h[8 + li];
     const int64_t nr = std::min((int64_t)h[1], rec_slots);
     std::vector<CexRec> recs;
-    IBMC_TRY(fetch_sorted(ctx, ctx->recs.as<DevRec>(), nr, cap, 0, o->k_max, binom_small(n, 2) * m * m, recs));
-    const int64_t nkept = (int64_t)recs.size();
+    int64_t nkept = 0;
+    IBMC_TRY(fetch_sorted(ctx, ctx->recs.as<DevRec>(), nr, cap, 0, o->k_max, binom_small(n, 2) * m * m, recs, nullptr,
+                          false, &nkept));
     if (p) {
         order.resize(N1);
         HIP_OK(hipMemcpy(order.data(), ctx->order.p, N1 * 4, hipMemcpyDeviceToHost));
@@ -863,7 +878,9 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
     HIP_OK(hipEventSynchronize(ctx->ev1));
     float ms = 0.f;
     HIP_OK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    if (cex_buf && nkept) memcpy(cex_buf, recs.data(), nkept * sizeof(CexRec));
+    if (cex_buf && nkept)
+        HIP_OK(hipMemcpy(cex_buf, recs.data(), nkept * sizeof(CexRec),
+                         o->records_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
 
     // position of every record in the visiting order (hardware independent)
     int64_t first_pos = -1;

@@ -64,8 +64,7 @@ struct ibmc_ctx {
     // scratch of the check driver (grow-only)
     ibmc::DevBuf images, props, jobs, qcum, u0, u0_index, prop_ids, counters, recs, ties, order;
     ibmc::DevBuf u0f, sortbuf;
-    std::vector<uint64_t> hkeys;
-    std::vector<uint32_t> hvals;
+    ibmc::DevBuf recout;  // sorted records in the public layout, on their way to a host buffer
     ibmc::DevBuf cov_img, cov_pots, cov_bits, cov_sums, cov_out;
     // tuned kernel variant per network shape key
     std::map<std::string, std::string> tuned;

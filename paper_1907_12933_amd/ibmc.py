@@ -48,7 +48,7 @@ class ibmc_mlp_desc(C.Structure):
 class ibmc_check_opts(C.Structure):
     _fields_ = [("k_min", C.c_int32), ("k_max", C.c_int32), ("k_step", C.c_int32),
                 ("stop_at_first", C.c_int32), ("cex_capacity", C.c_int64),
-                ("near_tie_capacity", C.c_int64), ("near_tie_rel", C.c_float), ("reserved", C.c_int32)]
+                ("near_tie_capacity", C.c_int64), ("near_tie_rel", C.c_float), ("records_on_device", C.c_int32)]
 
 
 class ibmc_cex(C.Structure):
@@ -264,9 +264,9 @@ def ibmc_decode_point(n_pixels, n_deltas, k, rank):
 # check
 # ---------------------------------------------------------------------------
 
-def _opts(k_min, k_max, k_step, stop_at_first, cap, tie_cap, tie_rel):
+def _opts(k_min, k_max, k_step, stop_at_first, cap, tie_cap, tie_rel, on_device=False):
     return ibmc_check_opts(int(k_min), int(k_max), int(k_step), int(bool(stop_at_first)), int(cap), int(tie_cap),
-                           float(tie_rel), 0)
+                           float(tie_rel), int(bool(on_device)))
 
 
 def summary_dict(s: ibmc_check_summary):
@@ -316,26 +316,38 @@ def _props(props, on_device):
 
 
 def ibmc_check_batch(ctx, props, stop_at_first=False, cex_capacity=1 << 20, near_tie_capacity=0,
-                     near_tie_rel=0.0, on_device=False, cex_buf=None):
+                     near_tie_rel=0.0, on_device=False, cex_buf=None, records_on_device=False):
     """props: list of (net, image, deltas, k_min, k_max[, k_step]); with on_device the images are
-    torch device tensors (uint8).  cex_buf: optional preallocated CEX_DTYPE array of at least
-    cex_capacity records (reused across calls).  Returns (list of summary dicts, cex records
-    (a view into cex_buf when given), near-tie records, status)."""
+    torch device tensors (uint8).  cex_buf: optional preallocated buffer of at least cex_capacity
+    records, reused across calls: a CEX_DTYPE array, or with records_on_device a torch uint8
+    device tensor of CEX_DTYPE.itemsize bytes per record (the records then stay on the device).
+    Returns (list of summary dicts, cex records (a view into cex_buf when given; with
+    records_on_device a uint8 device tensor), near-tie records, status)."""
     arr, keep = _props(props, on_device)
     n = len(props)
     outs = (ibmc_check_summary * n)()
-    if cex_buf is None or len(cex_buf) < cex_capacity:
-        cex_buf = np.empty(max(cex_capacity, 1), CEX_DTYPE)
-    cex = cex_buf
-    ties = np.empty(max(near_tie_capacity, 1), CEX_DTYPE)
-    o = _opts(0, 0, 1, stop_at_first, cex_capacity, near_tie_capacity, near_tie_rel)
+    rsz = CEX_DTYPE.itemsize
+    if records_on_device:
+        import torch
+        if cex_buf is None or cex_buf.numel() < cex_capacity * rsz:
+            cex_buf = torch.empty(max(cex_capacity, 1) * rsz, dtype=torch.uint8, device="cuda")
+        tie_dev = torch.empty(max(near_tie_capacity, 1) * rsz, dtype=torch.uint8, device="cuda")
+        cex_ptr, tie_ptr = C.cast(cex_buf.data_ptr(), P_CEX), C.cast(tie_dev.data_ptr(), P_CEX)
+    else:
+        if cex_buf is None or len(cex_buf) < cex_capacity:
+            cex_buf = np.empty(max(cex_capacity, 1), CEX_DTYPE)
+        ties = np.empty(max(near_tie_capacity, 1), CEX_DTYPE)
+        cex_ptr, tie_ptr = cex_buf.ctypes.data_as(P_CEX), ties.ctypes.data_as(P_CEX)
+    o = _opts(0, 0, 1, stop_at_first, cex_capacity, near_tie_capacity, near_tie_rel, records_on_device)
     fn = lib().ibmc_check_batch_dev if on_device else lib().ibmc_check_batch
-    rc = _ck(fn(ctx.handle, arr, n, C.byref(o), outs, cex.ctypes.data_as(P_CEX), ties.ctypes.data_as(P_CEX)))
+    rc = _ck(fn(ctx.handle, arr, n, C.byref(o), outs, cex_ptr, tie_ptr))
     sums = [summary_dict(outs[i]) for i in range(n)]
-    tot = sum(s["cex_total"] for s in sums)
-    ttot = sum(s["near_ties_total"] for s in sums)
+    tot = min(sum(s["cex_total"] for s in sums), cex_capacity)
+    ttot = min(sum(s["near_ties_total"] for s in sums), near_tie_capacity)
     del keep
-    return sums, cex[:min(tot, cex_capacity)], ties[:min(ttot, near_tie_capacity)].copy(), rc
+    if records_on_device:
+        return sums, cex_buf[:tot * rsz], tie_dev[:ttot * rsz], rc
+    return sums, cex_buf[:tot], ties[:ttot].copy(), rc
 
 
 def ibmc_check_batch_dev(ctx, props, **kw):

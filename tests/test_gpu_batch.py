@@ -91,3 +91,23 @@ def test_autotune_picks_a_working_variant(ctx, orc):
         s, cex, _ = ibmc.ibmc_check_property(ctx, m, x, D, 1, 2)
         assert np.array_equal(cex["rank"], r["cex_rank"]) and np.array_equal(cex["new_label"], r["cex_label"]), v
     ibmc.ibmc_set_variant(ctx, m, None)
+
+
+def test_records_on_device_match_host(ctx, small_batch):
+    """Device-resident record output (images and records in HBM) hands out
+    the same sorted records and totals as the host-buffer path, with and
+    without truncation."""
+    import torch
+    from paper_1907_12933_amd import ibmc
+    nets, props = small_batch
+    ms = [ibmc.Mlp(ctx, n) for n in nets]
+    imgs = [torch.from_numpy(np.ascontiguousarray(p.image)).cuda() for p in props]
+    P = [(ms[p.net_index], imgs[i], p.deltas, 1, p.k) for i, p in enumerate(props)]
+    for cap in (1 << 20, 5):
+        s1, c1, _, rc1 = ibmc.ibmc_check_batch_dev(ctx, P, cex_capacity=cap)
+        s2, c2, _, rc2 = ibmc.ibmc_check_batch_dev(ctx, P, cex_capacity=cap, records_on_device=True)
+        assert rc1 == rc2 and [s["cex"] for s in s1] == [s["cex"] for s in s2]
+        host = np.frombuffer(c2.cpu().numpy().tobytes(), dtype=ibmc.CEX_DTYPE)
+        assert len(host) == len(c1) == min(cap, sum(s["cex_total"] for s in s1))
+        if cap > 5:
+            assert np.array_equal(host, c1)
