@@ -18,6 +18,27 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 MI355X_INT8_PEAK_TOPS = 5000.0     # dense int8 MFMA, TOP/s
+HERE = os.path.dirname(os.path.abspath(__file__))
+# enumeration kernel sources whose hash keys the measured HBM traffic
+KERNEL_SOURCES = ["paper_1907_12933_amd/csrc/enum_q8_impl.h", "paper_1907_12933_amd/csrc/enum_common.h",
+                  "paper_1907_12933_amd/csrc/ibmc_internal.h"]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the enumeration kernel on this workload, from the
+    FETCH_SIZE / WRITE_SIZE counter runs recorded in profiles/ (scaled by a
+    plain copy's counters); None once the kernel sources differ from the ones
+    measured."""
+    import hashlib
+    path = os.path.join(HERE, "profiles", "enum_q8_blob784_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    return rec["hbm_bytes_per_launch"] if rec.get("kernel_source_sha256") == h.hexdigest() else None
 MI355X_HBM_PEAK_GBS = 8000.0
 
 
@@ -205,7 +226,8 @@ def main():
     k_avg = float(np.mean(ksec))
     achieved_tops = 2.0 * macs_per_point * points / k_avg / 1e12
     roof = dict(bound="mfma", achieved=round(achieved_tops, 2), peak=MI355X_INT8_PEAK_TOPS, unit="TOP/s",
-                frac=round(achieved_tops / MI355X_INT8_PEAK_TOPS, 4), traffic=None,
+                frac=round(achieved_tops / MI355X_INT8_PEAK_TOPS, 4),
+                traffic=measured_traffic() if args.images == 64 else None,
                 kernel="enum_q8", kernel_ms=round(k_avg * 1e3, 3))
     out = {
         "metric": "perturbation points verified/sec + time-to-first-counterexample, plain vs learned",
