@@ -27,16 +27,17 @@ __device__ __forceinline__ int requant4_clamp(v4i acc, int s, int lo, int hi) {
 
 __device__ __forceinline__ int requant4_offset(v4i acc, int s) { return requant4_clamp(acc, s, -64, 63); }
 
-// Fast hidden epilogue: the accumulator is alpha * u with alpha * 2^s = 256,
-// so a = clamp(floor(u / 2^s), 0, 127) is byte 1 of clamp(acc, 0, 32767):
-// one med3 per value and no shift.
-__device__ __forceinline__ int requant4_byte1(v4i acc) {
-    int m[4];
-#pragma unroll
-    for (int z = 0; z < 4; ++z) m[z] = min(max(acc[z], 0), 32767);
-    const unsigned l2 = __builtin_amdgcn_perm((unsigned)m[1], (unsigned)m[0], 0x0c0c0501u);
-    const unsigned h2 = __builtin_amdgcn_perm((unsigned)m[3], (unsigned)m[2], 0x05010c0cu);
-    return (int)(l2 | h2);
+// Fast hidden epilogue: the accumulator is alpha * u - 32768 with
+// alpha * 2^s = 256.  Saturated to int16 (two values per conversion) and
+// capped at -1, byte 1 of each half is a - 128 for a = clamp(floor(u / 2^s),
+// 0, 127): below u = 0 the conversion saturates to -32768 (byte -128), from
+// a = 128 on the cap gives byte -1.
+__device__ __forceinline__ int requant4_sat(v4i acc) {
+    const short2_t m1 = {(short)-1, (short)-1};
+    const short2_t p0 = __builtin_elementwise_min(__builtin_amdgcn_cvt_pk_i16(acc[0], acc[1]), m1);
+    const short2_t p1 = __builtin_elementwise_min(__builtin_amdgcn_cvt_pk_i16(acc[2], acc[3]), m1);
+    return (int)__builtin_amdgcn_perm(__builtin_bit_cast(unsigned, p1), __builtin_bit_cast(unsigned, p0),
+                                      0x07050301u);
 }
 
 // a - 64 bytes -> 2 (a - 64) bytes (still int8: [-128, 126]); the bit that
@@ -303,7 +304,10 @@ __device__ __forceinline__ void layer1_issue(const Cursor &c, const QNetDev &net
 // First layer, packed int16 path: u = base + e W1[:, p] as v = f u - 16384
 // in 16-bit halves, clamped to [-16384, 16383], whose byte 1 is a - 64.  The
 // base of this lane group's 16 positions per K-block comes from LDS.
-template <int KB1, int NT>
+// DBL: bytes 2 (a - 64) instead, from the saturated sum v + v (its byte 1 is
+// floor(v / 128), 2 (a - 64) plus a low bit that is masked off); the
+// pre-clamped base keeps v itself inside int16.
+template <int KB1, int NT, bool DBL>
 __device__ __forceinline__ void layer1_packed(const L1Loads<KB1, NT> &ld, const int (&ev)[NT], const int16_t *base16,
                                               int g, v4i (&a1)[NT][KB1]) {
     const short2_t vlo = {(short)-16384, (short)-16384};
@@ -326,14 +330,19 @@ __device__ __forceinline__ void layer1_packed(const L1Loads<KB1, NT> &ld, const 
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 short2_t u = as_s2(bv[t]) + e2 * as_s2(wv[t]);
-                u = __builtin_elementwise_max(u, vlo);
-                u = __builtin_elementwise_min(u, vhi);
+                if constexpr (DBL) {
+                    u = __builtin_elementwise_add_sat(u, u);
+                } else {
+                    u = __builtin_elementwise_max(u, vlo);
+                    u = __builtin_elementwise_min(u, vhi);
+                }
                 pr2[t] = as_int(u);
             }
-            a1[nt][kb] = v4i{(int)__builtin_amdgcn_perm(pr2[1], pr2[0], 0x07050301u),
-                             (int)__builtin_amdgcn_perm(pr2[3], pr2[2], 0x07050301u),
-                             (int)__builtin_amdgcn_perm(pr2[5], pr2[4], 0x07050301u),
-                             (int)__builtin_amdgcn_perm(pr2[7], pr2[6], 0x07050301u)};
+            const unsigned msk = DBL ? 0xfefefefeu : 0xffffffffu;
+            a1[nt][kb] = v4i{(int)(__builtin_amdgcn_perm(pr2[1], pr2[0], 0x07050301u) & msk),
+                             (int)(__builtin_amdgcn_perm(pr2[3], pr2[2], 0x07050301u) & msk),
+                             (int)(__builtin_amdgcn_perm(pr2[5], pr2[4], 0x07050301u) & msk),
+                             (int)(__builtin_amdgcn_perm(pr2[7], pr2[6], 0x07050301u) & msk)};
         }
     }
 }
@@ -380,7 +389,8 @@ __device__ __forceinline__ void layer1_int32(const L1Loads<KB1, NT> &ld, const i
 // its M-tiles and every point takes the full argmax).
 //
 // Activations travel between layers in the offset form a - 64 (int8 in
-// [-64, 63]); the offsets are folded into the next layer's bias (bo).
+// [-64, 63]; the fast epilogue's second hidden layer: a - 128); the offsets
+// are folded into the next layer's bias.
 template <int L, int KB1, int KB2, int NT, bool WLDS, int EPI, bool OUT16>
 __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int32_t *u0_store,
                                                       int64_t u0_stride, const int32_t *u0_index) {
@@ -397,7 +407,7 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
     const int8_t *w2s = net.Wt[2];
     const int8_t *wls = net.Wt[L];
     // fast hidden epilogue (3-layer nets, shift[1] in {7, 8}): layer 1 emits
-    // fast2 * (a1 - 64) (doubled bytes when fast2 == 2), layer 2 emits plain a2
+    // fast2 * (a1 - 64) (doubled bytes when fast2 == 2), layer 2 emits a2 - 128
     constexpr bool fast = (L == 3) && EPI == 1;
     const bool dbl1 = fast && net.fast2 == 2;
     // LDS: [weight tiles of layers >= 2 (WLDS)] [layer-2 init] [output init] [per-wave base]
@@ -420,7 +430,7 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
             const int32_t *src2 = fast ? net.bf2 : net.bo[2];
             for (int t = threadIdx.x; t < nb2; t += blockDim.x) bdst[t] = src2[t];
         }
-        const int32_t *srcl = fast ? net.bn[L] : net.bo[L];
+        const int32_t *srcl = fast ? net.bf3 : net.bo[L];
         for (int t = threadIdx.x; t < nbl; t += blockDim.x) bdst[nb2 + t] = srcl[t];
         __syncthreads();
     }
@@ -567,12 +577,14 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
 
         // ---- layer 1: incremental update, requantisation, B operands
         v4i a1[NT][KB1];
-        if (P.packed)
-            layer1_packed<KB1, NT>(ld, ev, base16 + w * H1, g, a1);
-        else
+        if (P.packed) {
+            if (dbl1)  // uniform: one branch per segment
+                layer1_packed<KB1, NT, true>(ld, ev, base16 + w * H1, g, a1);
+            else
+                layer1_packed<KB1, NT, false>(ld, ev, base16 + w * H1, g, a1);
+        } else {
             layer1_int32<KB1, NT>(ld, ev, base32, s1, g, a1);
-        if constexpr (L == 3) {
-            if (dbl1) {  // uniform: one branch per chunk
+            if (dbl1) {
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
@@ -631,7 +643,7 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
                     const int pm = mt - 1;
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt) {
-                        int q = fast ? requant4_byte1(accp[nt]) : requant4_clamp(accp[nt], s2, lo2, hi2);
+                        int q = fast ? requant4_sat(accp[nt]) : requant4_clamp(accp[nt], s2, lo2, hi2);
                         // pin the epilogue here: otherwise it is sunk towards the
                         // output layer, keeping every raw accumulator live
                         asm volatile("" : "+v"(q));
@@ -653,7 +665,7 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
 #pragma unroll
                         for (int i = 0; i < KB1 * NT; ++i) {
                             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                            __builtin_amdgcn_sched_group_barrier(0x002, ((fast ? 7 : 11) * NT + KB1 * NT - 1) / (KB1 * NT), 0);
+                            __builtin_amdgcn_sched_group_barrier(0x002, ((fast ? 5 : 11) * NT + KB1 * NT - 1) / (KB1 * NT), 0);
                         }
                     }
                 }

@@ -236,6 +236,19 @@ static ibmc_status build_q8(ibmc_ctx *ctx, ibmc_mlp *m) {
         IBMC_TRY(m->buf.emplace_back().upload(t.data(), t.size(), s));
         q.W1tile = (const int8_t *)m->buf.back().p;
     }
+    // fast hidden epilogue of 3-layer nets (shift[1] in {7, 8}), where every
+    // partial sum of its offset accumulators stays inside int32
+    bool fast_ok = L == 3 && (m->shift[1] == 7 || m->shift[1] == 8);
+    for (int l = 2; l <= L && fast_ok; ++l) {
+        const int nin = m->dims[l - 1], nout = m->dims[l];
+        const int64_t alpha = (l == 2) ? (1 << (8 - m->shift[1])) : 1;
+        for (int j = 0; j < nout && fast_ok; ++j) {
+            int64_t sa = 0;
+            for (int i = 0; i < nin; ++i) sa += std::llabs((long long)m->Wq[l - 1][(size_t)j * nin + i]);
+            const int64_t bound = alpha * (std::llabs((long long)m->bq[l - 1][j]) + 256 * sa) + 32768;
+            if (bound >= (1LL << 31)) fast_ok = false;
+        }
+    }
     // layers >= 2: A-operand tiles with sigma-permuted K, natural-order bias
     for (int l = 2; l <= L; ++l) {
         const int Hin = q.H[l - 1], Hout = q.H[l], nin = m->dims[l - 1], nout = m->dims[l];
@@ -267,19 +280,31 @@ static ibmc_status build_q8(ibmc_ctx *ctx, ibmc_mlp *m) {
         q.bn[l] = (const int32_t *)m->buf.back().p;
         IBMC_TRY(m->buf.emplace_back().upload(bo.data(), bo.size() * 4, s));
         q.bo[l] = (const int32_t *)m->buf.back().p;
-        if (l == 2 && L == 3 && (m->shift[1] == 7 || m->shift[1] == 8)) {
-            // layer 2 fed with alpha (a1 - 64), alpha = 2^(8 - s2): its accumulator is alpha * u2,
-            // so byte 1 of clamp(acc, 0, 32767) is the requantised activation
+        if (l == 2 && fast_ok) {
+            // layer 2 fed with alpha (a1 - 64), alpha = 2^(8 - s2): its accumulator is
+            // alpha * u2 - 32768, whose saturation to int16 has byte 1 = a2 - 128 once
+            // clamped to at most -1
             const int alpha = 1 << (8 - m->shift[1]);
             std::vector<int32_t> bf(Hout, 0);
             for (int j = 0; j < nout; ++j) {
                 int64_t rs = 0;
                 for (int i = 0; i < nin; ++i) rs += m->Wq[l - 1][(size_t)j * nin + i];
-                bf[j] = (int32_t)(alpha * ((int64_t)m->bq[l - 1][j] + 64 * rs));
+                bf[j] = (int32_t)(alpha * ((int64_t)m->bq[l - 1][j] + 64 * rs) - 32768);
             }
             IBMC_TRY(m->buf.emplace_back().upload(bf.data(), bf.size() * 4, s));
             q.bf2 = (const int32_t *)m->buf.back().p;
             q.fast2 = alpha;
+        }
+        if (l == L && q.fast2 != 0) {
+            // output layer fed with a2 - 128
+            std::vector<int32_t> bf(Hout, 0);
+            for (int j = 0; j < nout; ++j) {
+                int64_t rs = 0;
+                for (int i = 0; i < nin; ++i) rs += m->Wq[l - 1][(size_t)j * nin + i];
+                bf[j] = (int32_t)((int64_t)m->bq[l - 1][j] + 128 * rs);
+            }
+            IBMC_TRY(m->buf.emplace_back().upload(bf.data(), bf.size() * 4, s));
+            q.bf3 = (const int32_t *)m->buf.back().p;
         }
     }
     // batched forward: natural-K tiles of layers >= 2 and accumulator inits

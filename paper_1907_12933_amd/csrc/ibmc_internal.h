@@ -57,8 +57,11 @@ struct QNetDev {
     int maxw1;                         // max |W1|
     const int32_t *bo[kMaxLayers + 1]; // l >= 2: bias with the a - 64 input offset (and the
                                        // hidden requantiser offset) folded in, natural order
-    int fast2;                         // 3-layer nets with shift[1] in {7, 8}: alpha = 2^(8 - shift[1]), else 0
-    const int32_t *bf2;                // alpha * (b2 + 64 rowsum(W2)): layer-2 init for inputs alpha (a1 - 64)
+    int fast2;                         // 3-layer nets with shift[1] in {7, 8} and int32 room for the
+                                       // offset accumulators: alpha = 2^(8 - shift[1]), else 0
+    const int32_t *bf2;                // alpha * (b2 + 64 rowsum(W2)) - 32768: layer-2 init for inputs
+                                       // alpha (a1 - 64) (fast2 != 0)
+    const int32_t *bf3;                // b3 + 128 rowsum(W3): output-layer init for inputs a2 - 128 (fast2 != 0)
     const int32_t *b1s;                // [H1], sigma order
     const int8_t *Wt[kMaxLayers + 1];  // l >= 2: A-operand tiles
     const int32_t *bn[kMaxLayers + 1]; // l >= 2: bias, natural order, padded to H[l]
