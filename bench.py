@@ -7,6 +7,7 @@ counterexamples returned to the host.  Images are resident in device memory
 before the timed region.  Prints one JSON line.
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -205,6 +206,10 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # objects alive now (torch's among them) leave the cyclic collector's
+    # scans: a full collection over them stalls the host for tens of ms
+    gc.collect()
+    gc.freeze()
     ksec = []
     t0 = time.perf_counter()
     for _ in range(args.steps):

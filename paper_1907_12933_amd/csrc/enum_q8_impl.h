@@ -155,6 +155,55 @@ __device__ __forceinline__ int64_t rank_of(const EmitInfo &e, int p, int i) {
     return (c2n - 1 - x * (x - 1) / 2 - (e.n - 1 - b)) * e.mk + (int64_t)da * e.m + db;
 }
 
+// Emission state of a chunk as lanes of one VGPR (wave-uniform values, read
+// back only when a tile records violations): lanes w and 4 + w hold the low
+// and high half of segment w's rank offset, the others the fields below.
+enum : int {
+    EI_PROP = 8, EI_K, EI_SLOT, EI_MODE, EI_N, EI_M, EI_PH, EI_IH, EI_MKLO, EI_MKHI, EI_GCLO, EI_GCHI
+};
+static_assert(kSegGroup <= 4, "rank offsets take lanes 0..7");
+
+__device__ __forceinline__ int lane_put(int v, int idx, int x) { return (int)__lane_id() == idx ? x : v; }
+__device__ __forceinline__ int lane_get(int v, int idx) { return __builtin_amdgcn_readlane(v, idx); }
+
+// Segment w's emission info into v (the group's common fields with w == 0).
+__device__ __forceinline__ int einfo_pack(const EmitInfo &e, int w, int v) {
+    v = lane_put(v, w, (int)(uint32_t)e.r0);
+    v = lane_put(v, 4 + w, (int)(e.r0 >> 32));
+    if (w == 0) {
+        v = lane_put(v, EI_PROP, e.prop);
+        v = lane_put(v, EI_K, e.k);
+        v = lane_put(v, EI_SLOT, e.slot);
+        v = lane_put(v, EI_MODE, e.mode);
+        v = lane_put(v, EI_N, e.n);
+        v = lane_put(v, EI_M, e.m);
+        v = lane_put(v, EI_PH, e.ph);
+        v = lane_put(v, EI_IH, e.ih);
+        v = lane_put(v, EI_MKLO, (int)(uint32_t)e.mk);
+        v = lane_put(v, EI_MKHI, (int)(e.mk >> 32));
+    }
+    return v;
+}
+
+__device__ __forceinline__ int64_t lane_get64(int v, int lo, int hi) {
+    return (int64_t)(((uint64_t)(uint32_t)lane_get(v, hi) << 32) | (uint32_t)lane_get(v, lo));
+}
+
+__device__ __forceinline__ EmitInfo einfo_unpack(int v, int w) {
+    EmitInfo e;
+    e.prop = lane_get(v, EI_PROP);
+    e.k = lane_get(v, EI_K);
+    e.slot = lane_get(v, EI_SLOT);
+    e.mode = lane_get(v, EI_MODE);
+    e.n = lane_get(v, EI_N);
+    e.m = lane_get(v, EI_M);
+    e.ph = lane_get(v, EI_PH);
+    e.ih = lane_get(v, EI_IH);
+    e.mk = lane_get64(v, EI_MKLO, EI_MKHI);
+    e.r0 = lane_get64(v, w, 4 + w);
+    return e;
+}
+
 // Lowest-index maximum over one 16-row tile of logits (this lane's four
 // rows, classes 16 mt + 4 g + t), combined into (value, index, count).
 // CHECK: skip classes >= ncls (else their logits are INT32_MIN, below any
@@ -227,12 +276,15 @@ __device__ __forceinline__ void rec_finish(const EnumParams &P, RecOut &o, int l
 }
 
 // Record the violations of one 16-point tile (lanes of group 0 carry the
-// points) in the wave's current block, continuing in a new block when it
-// runs out (a tile holds at most 16 records, a block 64).
-__device__ __forceinline__ void emit_tile(const EnumParams &P, RecOut &o, const EmitInfo &e, int64_t gchunk,
-                                          bool viol, int p, int i, int label, int lane) {
+// points) of segment w in the wave's current block, continuing in a new block
+// when it runs out (a tile holds at most 16 records, a block 64).  einfo:
+// the chunk's packed emission info.
+__device__ __forceinline__ void emit_tile(const EnumParams &P, RecOut &o, int einfo, int w, bool viol, int p, int i,
+                                          int label, int lane) {
     const unsigned long long vm = __ballot(viol);
     if (!vm) return;
+    const EmitInfo e = einfo_unpack(einfo, w);
+    const int64_t gchunk = lane_get64(einfo, EI_GCLO, EI_GCHI);
     const int n = __popcll(vm);
     const int64_t room = o.end - o.next;
     int64_t nb = 0;
@@ -443,6 +495,8 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
     char *wslot = smem + wbytes + 4 * (nb2 + nbl) + wave * SLOT;
     int32_t *base32 = reinterpret_cast<int32_t *>(wslot);
     int16_t *base16 = reinterpret_cast<int16_t *>(wslot);
+    // per wave: the cursor record, after the four waves' slots
+    Cursor *const cs = reinterpret_cast<Cursor *>(smem + wbytes + 4 * (nb2 + nbl) + 4 * SLOT) + wave_uniform(wave);
 
     // output layer of at most 16 classes: one M-tile, its weight tiles read
     // when needed, its init held in registers
@@ -475,14 +529,15 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
     }
 
     // ---- work distribution: batches of chunks from the global queue; the
-    // cursor always describes the chunk whose first-layer loads are in flight
-    Cursor c;
-    c.job = -1;
+    // cursor always describes the chunk whose first-layer loads are in
+    // flight.  Between chunks it rests in the wave's LDS record (read back
+    // and written once per chunk), so that none of its fields holds
+    // registers across the layers.
     int64_t cur_chunk = 0, end_chunk = 0;
     int fetches = 0;
     // next chunk of this wave; false when the queue is exhausted or a stop
     // or abort was requested.  seg: the segment (hence the base) changed.
-    auto advance = [&](bool first, bool &seg) __attribute__((always_inline)) -> bool {
+    auto advance = [&](Cursor &c, bool first, bool &seg) __attribute__((always_inline)) -> bool {
         if (!first && ++cur_chunk < end_chunk) {
             seg = cursor_next<CH, EnumParams>(c, P);
             return true;
@@ -502,25 +557,20 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
     };
 
     // state of the chunk at the cursor (prepared a chunk ahead)
-    EmitInfo ein;
-    int64_t gchunk_n = 0;
     int label_n = -1, lowbits_n = 0, prop_n = -1;
     bool valid_n[NT];
     int plast_n[NT], ilast_n[NT];
     L1Loads<KB1, NT> ld;
-    // segment set-up when needed, then positions and first-layer loads
-    // segments of the group: their bases in LDS slots, their rank offsets
-    // in lane w of r0lo / r0hi
-    int nw_n = 1, r0lo_n = 0, r0hi_n = 0;
-    auto prepare = [&](bool seg) __attribute__((always_inline)) {
+    // segment set-up when needed (the group's bases in LDS slots, its
+    // emission info in einfo_n), then positions and first-layer loads
+    int nw_n = 1, einfo_n = 0;
+    auto prepare = [&](const Cursor &c, bool seg) __attribute__((always_inline)) {
         if (seg) {
             const int32_t *u0s = u0_store + (int64_t)wave_uniform(u0_index[c.prop]) * u0_stride;
             Cursor ct = c;
             for (int w = 0; w < c.nw; ++w) {
                 build_base<KB1>(ct, P, u0s, base32, base16 + w * H1, lane, ulo, uhi);
-                const EmitInfo e = make_emit_info<EnumParams>(ct, P);
-                if (w == 0) ein = e;
-                if (lane == w) { r0lo_n = (int)(uint32_t)e.r0; r0hi_n = (int)(e.r0 >> 32); }
+                einfo_n = einfo_pack(make_emit_info<EnumParams>(ct, P), w, einfo_n);
                 if (w + 1 < c.nw) seg_step(ct);
             }
             nw_n = c.nw;
@@ -535,7 +585,8 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
 #pragma unroll
             for (int t = 0; t < 4; ++t) lowbits_n |= (4 * g + t < label_n ? 1 : 0) << t;
         }
-        gchunk_n = c.chunk;
+        einfo_n = lane_put(einfo_n, EI_GCLO, (int)(uint32_t)c.chunk);
+        einfo_n = lane_put(einfo_n, EI_GCHI, (int)(c.chunk >> 32));
         const int obase = (int)c.ch * CH;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
@@ -543,9 +594,26 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
         layer1_issue<KB1, NT>(c, net, P.packed != 0, plast_n, ilast_n, g, ld);
     };
 
+    // back to the LDS record: everything after a segment change, else the
+    // chunk position; the clobber makes the next chunk read it back
+    auto store_cursor = [&](const Cursor &c, bool full) __attribute__((always_inline)) {
+        if (full) {
+            *cs = c;
+        } else {
+            cs->chunk = c.chunk;
+            cs->ch = c.ch;
+        }
+        asm volatile("" ::: "memory");
+    };
+
     bool seg = false;
-    if (!advance(true, seg)) return;
-    prepare(seg);
+    {
+        Cursor c;
+        c.job = -1;
+        if (!advance(c, true, seg)) return;
+        prepare(c, seg);
+        store_cursor(c, true);
+    }
     RecOut ro;
     ro.next = 0;
     ro.end = 0;
@@ -556,10 +624,9 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
     while (true) {
         // ---- the current chunk is the prepared one: the same last-element
         // positions for each of the group's nw segments
-        const EmitInfo ei = ein;
-        const int64_t gchunk = gchunk_n;
+        const int einfo = einfo_n;
         const int label0 = label_n, lowbits = lowbits_n;
-        const int nw = nw_n, r0lo = r0lo_n, r0hi = r0hi_n;
+        const int nw = nw_n;
         bool valid[NT];
         int plast[NT], ilast[NT], ev[NT];
 #pragma unroll
@@ -571,9 +638,6 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
         }
         bool more = true;
         for (int w = 0; w < nw; ++w) {
-        EmitInfo ew = ei;
-        ew.r0 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(r0hi, w) << 32) |
-                          (uint32_t)__builtin_amdgcn_readlane(r0lo, w));
 
         // ---- layer 1: incremental update, requantisation, B operands
         v4i a1[NT][KB1];
@@ -597,8 +661,12 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
         // ---- after the group's last segment has used them, the next chunk's
         // loads fly while this one goes through the MFMAs
         if (w == nw - 1) {
-            more = advance(false, seg);
-            if (more) prepare(seg);
+            Cursor c = *cs;
+            more = advance(c, false, seg);
+            if (more) {
+                prepare(c, seg);
+                store_cursor(c, seg);
+            }
         }
 
         // ---- hidden layer 2 (L == 3): int8 MFMA, requantise into B operands;
@@ -715,9 +783,9 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
                     argmax_combine(bv, bi, bc);
                     const bool mine = g == 0 && ((viol16 >> j16) & 1u);
                     ties += (unsigned)__popcll(__ballot(mine && bc > 1));
-                    emit_tile(P, ro, ew, gchunk, mine, plast[nt], ilast[nt], bi, lane);
+                    emit_tile(P, ro, einfo, w, mine, plast[nt], ilast[nt], bi, lane);
                 }
-                if (ties) rec_tally(P, ro, ei.slot, 0u, ties, lane);
+                if (ties) rec_tally(P, ro, lane_get(einfo, EI_SLOT), 0u, ties, lane);
             }
         } else {
             // ---- general output layer: M-tiles in turn, full lowest-index argmax
@@ -748,8 +816,8 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
                 argmax_combine(bestv[nt], besti[nt], bestc[nt]);
                 const bool mine = valid[nt] && g == 0;
                 const unsigned long long tm = __ballot(mine && bestc[nt] > 1);
-                if (tm) rec_tally(P, ro, ei.slot, 0u, (unsigned)__popcll(tm), lane);
-                emit_tile(P, ro, ew, gchunk, mine && besti[nt] != label0, plast[nt], ilast[nt], besti[nt], lane);
+                if (tm) rec_tally(P, ro, lane_get(einfo, EI_SLOT), 0u, (unsigned)__popcll(tm), lane);
+                emit_tile(P, ro, einfo, w, mine && besti[nt] != label0, plast[nt], ilast[nt], besti[nt], lane);
             }
         }
 

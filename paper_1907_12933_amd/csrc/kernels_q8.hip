@@ -226,9 +226,10 @@ int64_t enum_lds_bytes(const EnumVariant &v, const QNetDev &net) {
         w += (int64_t)(net.H[v.L] / 16) * kbl * 1024;
     }
     const int64_t biases = 4LL * ((v.L == 3 ? (int64_t)v.kb2 * 64 : 0) + net.H[v.L]);
-    // per wave (4 per workgroup): one int32 or kSegGroup int16 first-layer bases
+    // per wave (4 per workgroup): one int32 or kSegGroup int16 first-layer
+    // bases, and the cursor record
     const int64_t h1 = (int64_t)v.kb1 * 64;
-    return w + biases + 4LL * std::max<int64_t>(h1 * 4, (int64_t)kSegGroup * h1 * 2);
+    return w + biases + 4LL * std::max<int64_t>(h1 * 4, (int64_t)kSegGroup * h1 * 2) + 4LL * (int64_t)sizeof(Cursor);
 }
 
 hipError_t launch_enum_q8(const EnumVariant &v, int grid, const EnumParams &P,

@@ -278,6 +278,24 @@ def summary_dict(s: ibmc_check_summary):
                 points_before_first=s.points_before_first)
 
 
+def summary_dicts(outs, n):
+    """summary_dict of each of the first n entries of a ctypes summary array, read in one pass."""
+    if n == 0:
+        return []
+    a = np.ctypeslib.as_array(outs)[:n]
+    keys = a.dtype.names
+    res = []
+    for row in a.tolist():
+        d = dict(zip(keys, row))
+        m = d["n_levels"]
+        res.append(dict(clean_label=d["clean_label"], first_unsafe_k=d["first_unsafe_k"],
+                        safe_up_to_k=d["safe_up_to_k"], levels=d["level_k"][:m].tolist(), points=d["points"][:m].tolist(),
+                        cex=d["cex"][:m].tolist(), ties=d["ties"][:m].tolist(), points_total=d["points_total"],
+                        cex_total=d["cex_total"], near_ties_total=d["near_ties_total"], seconds=d["seconds"],
+                        ttfc_seconds=d["ttfc_seconds"], points_before_first=d["points_before_first"]))
+    return res
+
+
 def ibmc_check_property(ctx, net, image, deltas, k_min=1, k_max=2, k_step=1, stop_at_first=False,
                         cex_capacity=1 << 20, near_tie_capacity=0, near_tie_rel=0.0):
     """Returns (summary dict, cex records, near-tie records) as numpy structured arrays."""
@@ -341,7 +359,7 @@ def ibmc_check_batch(ctx, props, stop_at_first=False, cex_capacity=1 << 20, near
     o = _opts(0, 0, 1, stop_at_first, cex_capacity, near_tie_capacity, near_tie_rel, records_on_device)
     fn = lib().ibmc_check_batch_dev if on_device else lib().ibmc_check_batch
     rc = _ck(fn(ctx.handle, arr, n, C.byref(o), outs, cex_ptr, tie_ptr))
-    sums = [summary_dict(outs[i]) for i in range(n)]
+    sums = summary_dicts(outs, n)
     tot = min(sum(s["cex_total"] for s in sums), cex_capacity)
     ttot = min(sum(s["near_ties_total"] for s in sums), near_tie_capacity)
     del keep
