@@ -27,6 +27,19 @@ __device__ __forceinline__ unsigned long long wave_uniform(unsigned long long v)
     return ((unsigned long long)hi << 32) | lo;
 }
 
+// The kernel's parameter block (its first argument) through a pointer that
+// the compiler cannot see through: each call site re-reads the fields it
+// needs with scalar loads, instead of the kernel holding them in registers
+// from start to end.  For the rarely taken paths (queue, segment set-up,
+// records).
+template <class PT>
+__device__ __forceinline__ const PT &cold_params() {
+    typedef const __attribute__((address_space(4))) PT *cptr;
+    cptr p = (cptr)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    return *(const PT *)p;
+}
+
 // Segment cursor: position of a wave in the global chunk order
 // (job, last-prefix pixel q, prefix subset, prefix deltas, chunk).  All its
 // fields are wave-uniform.

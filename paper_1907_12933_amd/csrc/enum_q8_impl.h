@@ -204,6 +204,29 @@ __device__ __forceinline__ EmitInfo einfo_unpack(int v, int w) {
     return e;
 }
 
+// Cross-row exchange without LDS: v_permlane32_swap / v_permlane16_swap of
+// a value with itself give, in every lane, the pair (lower-half value,
+// upper-half value) of lanes l and l ^ 32, resp. (even-row value, odd-row
+// value) of lanes l and l ^ 16 (rows: 16 lanes).
+struct LanePair {
+    int lo, hi;
+};
+__device__ __forceinline__ LanePair swap32(int x) {
+    const auto p = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return LanePair{(int)p[0], (int)p[1]};
+}
+__device__ __forceinline__ LanePair swap16(int x) {
+    const auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return LanePair{(int)p[0], (int)p[1]};
+}
+
+// Row G's value (lane 16 G + l % 16) in every lane; G wave-uniform.
+__device__ __forceinline__ int row_bcast(int x, int G) {
+    const LanePair a = swap32(x);
+    const LanePair b = swap16(G >= 2 ? a.hi : a.lo);
+    return (G & 1) ? b.hi : b.lo;
+}
+
 // Lowest-index maximum over one 16-row tile of logits (this lane's four
 // rows, classes 16 mt + 4 g + t), combined into (value, index, count).
 // CHECK: skip classes >= ncls (else their logits are INT32_MIN, below any
@@ -221,16 +244,17 @@ __device__ __forceinline__ void argmax_tile(v4i acc, int mt, int g, int ncls, in
     }
 }
 
-// Combine the four lane groups holding the same point.
+// Combine the four lane groups holding the same point (both lanes of a
+// pair reach the same, symmetric, result).
+__device__ __forceinline__ void argmax_pair(const LanePair &v, const LanePair &i, const LanePair &c, int &bv, int &bi,
+                                            int &bc) {
+    if (v.lo > v.hi) { bv = v.lo; bi = i.lo; bc = c.lo; }
+    else if (v.hi > v.lo) { bv = v.hi; bi = i.hi; bc = c.hi; }
+    else { bv = v.lo; bi = min(i.lo, i.hi); bc = c.lo + c.hi; }
+}
 __device__ __forceinline__ void argmax_combine(int &bv, int &bi, int &bc) {
-#pragma unroll
-    for (int sh = 16; sh <= 32; sh <<= 1) {
-        const int ov = __shfl_xor(bv, sh);
-        const int oi = __shfl_xor(bi, sh);
-        const int oc = __shfl_xor(bc, sh);
-        if (ov > bv) { bv = ov; bi = oi; bc = oc; }
-        else if (ov == bv) { bi = min(bi, oi); bc += oc; }
-    }
+    argmax_pair(swap16(bv), swap16(bi), swap16(bc), bv, bi, bc);
+    argmax_pair(swap32(bv), swap32(bi), swap32(bc), bv, bi, bc);
 }
 
 // Per-wave record output: slots come in blocks of kRecBlock from one atomic
@@ -243,8 +267,9 @@ struct RecOut {
     unsigned long long cex, ties;
 };
 
-__device__ __forceinline__ void rec_flush_counts(const EnumParams &P, RecOut &o, int lane) {
+__device__ __forceinline__ void rec_flush_counts(RecOut &o, int lane) {
     if (o.slot >= 0 && lane == 0) {
+        const EnumParams &P = cold_params<EnumParams>();
         if (o.cex) atomicAdd(P.slot_cex + o.slot, o.cex);
         if (o.ties) atomicAdd(P.slot_ties + o.slot, o.ties);
     }
@@ -252,10 +277,9 @@ __device__ __forceinline__ void rec_flush_counts(const EnumParams &P, RecOut &o,
     o.ties = 0;
 }
 
-__device__ __forceinline__ void rec_tally(const EnumParams &P, RecOut &o, int slot, unsigned ncex, unsigned nties,
-                                          int lane) {
+__device__ __forceinline__ void rec_tally(RecOut &o, int slot, unsigned ncex, unsigned nties, int lane) {
     if (slot != o.slot) {
-        rec_flush_counts(P, o, lane);
+        rec_flush_counts(o, lane);
         o.slot = slot;
     }
     o.cex += ncex;
@@ -263,8 +287,9 @@ __device__ __forceinline__ void rec_tally(const EnumParams &P, RecOut &o, int sl
 }
 
 // At the wave's end: counts out, sentinels into the block's unused slots.
-__device__ __forceinline__ void rec_finish(const EnumParams &P, RecOut &o, int lane) {
-    rec_flush_counts(P, o, lane);
+__device__ __forceinline__ void rec_finish(RecOut &o, int lane) {
+    rec_flush_counts(o, lane);
+    const EnumParams &P = cold_params<EnumParams>();
     const int64_t idx = o.next + lane;
     if (lane < kRecBlock && idx < o.end && idx < P.rec_cap) {
         DevRec r;
@@ -279,12 +304,11 @@ __device__ __forceinline__ void rec_finish(const EnumParams &P, RecOut &o, int l
 // points) of segment w in the wave's current block, continuing in a new block
 // when it runs out (a tile holds at most 16 records, a block 64).  einfo:
 // the chunk's packed emission info.
-__device__ __forceinline__ void emit_tile(const EnumParams &P, RecOut &o, int einfo, int w, bool viol, int p, int i,
-                                          int label, int lane) {
+__device__ __forceinline__ void emit_tile(RecOut &o, int einfo, int w, bool viol, int p, int i, int label, int lane) {
     const unsigned long long vm = __ballot(viol);
     if (!vm) return;
+    const EnumParams &P = cold_params<EnumParams>();
     const EmitInfo e = einfo_unpack(einfo, w);
-    const int64_t gchunk = lane_get64(einfo, EI_GCLO, EI_GCHI);
     const int n = __popcll(vm);
     const int64_t room = o.end - o.next;
     int64_t nb = 0;
@@ -293,12 +317,15 @@ __device__ __forceinline__ void emit_tile(const EnumParams &P, RecOut &o, int ei
         if (lane == 0) start = atomicAdd(P.rec_count, (unsigned long long)kRecBlock);
         nb = (int64_t)wave_uniform(start);  // lane 0's value
     }
-    if (lane == 0) {
-        if (P.track_first) atomicMin(P.first_chunk, (unsigned long long)gchunk);
-        if (P.hit_host) *P.hit_host = 1;
-        if (P.stop_on_first) *P.stop_flag = 1;
+    if (P.notify) {
+        const int64_t gchunk = lane_get64(einfo, EI_GCLO, EI_GCHI);
+        if (lane == 0) {
+            if (P.track_first) atomicMin(P.first_chunk, (unsigned long long)gchunk);
+            if (P.hit_host) *P.hit_host = 1;
+            if (P.stop_on_first) *P.stop_flag = 1;
+        }
     }
-    rec_tally(P, o, e.slot, (unsigned)n, 0u, lane);
+    rec_tally(o, e.slot, (unsigned)n, 0u, lane);
     if (viol) {
         const int t = __popcll(vm & ((1ull << lane) - 1ull));
         const int64_t idx = t < room ? o.next + t : nb + (t - room);
@@ -538,20 +565,21 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
     // next chunk of this wave; false when the queue is exhausted or a stop
     // or abort was requested.  seg: the segment (hence the base) changed.
     auto advance = [&](Cursor &c, bool first, bool &seg) __attribute__((always_inline)) -> bool {
+        const EnumParams &Q = cold_params<EnumParams>();
         if (!first && ++cur_chunk < end_chunk) {
-            seg = cursor_next<CH, EnumParams>(c, P);
+            seg = cursor_next<CH, EnumParams>(c, Q);
             return true;
         }
         unsigned long long start = 0;
-        if (lane == 0) start = atomicAdd(P.queue, (unsigned long long)P.batch);
+        if (lane == 0) start = atomicAdd(Q.queue, (unsigned long long)Q.batch);
         start = wave_uniform(start);  // lane 0's value
-        if ((int64_t)start >= P.total_chunks) return false;
-        if (wave_uniform(*P.stop_flag)) return false;
+        if ((int64_t)start >= Q.total_chunks) return false;
+        if (wave_uniform(*Q.stop_flag)) return false;
         // host-mapped: poll sparsely
-        if (P.abort_host && (fetches++ & 15) == 0 && wave_uniform(*P.abort_host)) return false;
+        if (Q.abort_host && (fetches++ & 15) == 0 && wave_uniform(*Q.abort_host)) return false;
         cur_chunk = (int64_t)start;
-        end_chunk = min((int64_t)start + P.batch, P.total_chunks);
-        cursor_decode<CH, EnumParams>(c, P, cur_chunk);
+        end_chunk = min((int64_t)start + Q.batch, Q.total_chunks);
+        cursor_decode<CH, EnumParams>(c, Q, cur_chunk);
         seg = true;
         return true;
     };
@@ -565,12 +593,13 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
     // emission info in einfo_n), then positions and first-layer loads
     int nw_n = 1, einfo_n = 0;
     auto prepare = [&](const Cursor &c, bool seg) __attribute__((always_inline)) {
+        const EnumParams &Q = cold_params<EnumParams>();
         if (seg) {
             const int32_t *u0s = u0_store + (int64_t)wave_uniform(u0_index[c.prop]) * u0_stride;
             Cursor ct = c;
             for (int w = 0; w < c.nw; ++w) {
-                build_base<KB1>(ct, P, u0s, base32, base16 + w * H1, lane, ulo, uhi);
-                einfo_n = einfo_pack(make_emit_info<EnumParams>(ct, P), w, einfo_n);
+                build_base<KB1>(ct, Q, u0s, base32, base16 + w * H1, lane, ulo, uhi);
+                einfo_n = einfo_pack(make_emit_info<EnumParams>(ct, Q), w, einfo_n);
                 if (w + 1 < c.nw) seg_step(ct);
             }
             nw_n = c.nw;
@@ -579,7 +608,7 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
         }
         if (c.prop != prop_n) {
             prop_n = c.prop;
-            label_n = wave_uniform(P.props[c.prop].label0);
+            label_n = wave_uniform(Q.props[c.prop].label0);
             // bit t: this lane's class 4 g + t has a lower index than the label
             lowbits_n = 0;
 #pragma unroll
@@ -590,8 +619,8 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
         const int obase = (int)c.ch * CH;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
-            valid_n[nt] = last_element32(c, P, obase + nt * 16 + j16, plast_n[nt], ilast_n[nt]);
-        layer1_issue<KB1, NT>(c, net, P.packed != 0, plast_n, ilast_n, g, ld);
+            valid_n[nt] = last_element32(c, Q, obase + nt * 16 + j16, plast_n[nt], ilast_n[nt]);
+        layer1_issue<KB1, NT>(c, Q.net, Q.packed != 0, plast_n, ilast_n, g, ld);
     };
 
     // back to the LDS record: everything after a segment change, else the
@@ -677,72 +706,133 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
         for (int nt = 0; nt < NT; ++nt) acco[nt] = bo4;
         v4i a2[NT][(L == 3 && !OUT16) ? KB2 : 1];
         if constexpr (L == 3) {
-            // Software pipeline over the M-tiles: the weight tiles and init of
-            // tile mt + 1 are read from LDS while tile mt computes, and the
-            // requantisation of tile mt - 1 (VALU) is interleaved with the MFMAs
-            // of tile mt, so that the two pipes overlap within one wave.
             const v4i *wt2 = reinterpret_cast<const v4i *>(w2s) + lane;
-            v4i Acur[KB1], Anext[KB1];
-#pragma unroll
-            for (int kb = 0; kb < KB1; ++kb) Acur[kb] = wt2[kb * 64];
             const int4 *bias2 = reinterpret_cast<const int4 *>(b2s + g * 4);
-            int4 bias = bias2[0], bnext = bias;
-            v4i accp[NT];
             v4i blk[NT];  // the a2 block being filled (OUT16)
+            // requantisation of the finished tile pm into B operands; with
+            // OUT16 every fourth tile completes a block for the output layer
+            auto epilogue = [&](int pm, const v4i (&accf)[NT]) __attribute__((always_inline)) {
 #pragma unroll
-            for (int mt = 0; mt <= MT2; ++mt) {
-                if (mt + 1 < MT2) {
-#pragma unroll
-                    for (int kb = 0; kb < KB1; ++kb) Anext[kb] = wt2[((mt + 1) * KB1 + kb) * 64];
-                    bnext = bias2[(mt + 1) * 4];
+                for (int nt = 0; nt < NT; ++nt) {
+                    int q = fast ? requant4_sat(accf[nt]) : requant4_clamp(accf[nt], s2, lo2, hi2);
+                    // pin the epilogue here: otherwise it is sunk towards the
+                    // output layer, keeping every raw accumulator live
+                    asm volatile("" : "+v"(q));
+                    if constexpr (OUT16) blk[nt][pm & 3] = q;
+                    else a2[nt][pm >> 2][pm & 3] = q;
                 }
-                v4i acc[NT];
-                if (mt < MT2) {
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) acc[nt] = v4i{bias.x, bias.y, bias.z, bias.w};
-#pragma unroll
-                    for (int kb = 0; kb < KB1; ++kb) {
+                if constexpr (OUT16) {
+                    if ((pm & 3) == 3) {
+                        const v4i w = wo[(pm >> 2) * 64];
 #pragma unroll
                         for (int nt = 0; nt < NT; ++nt)
-                            acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Acur[kb], a1[nt][kb], acc[nt], 0, 0, 0);
+                            acco[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(w, blk[nt], acco[nt], 0, 0, 0);
                     }
                 }
-                if (mt > 0) {
-                    const int pm = mt - 1;
+            };
+            constexpr int EPI_V = (fast ? 5 : 11) * NT;  // VALU ops of one epilogue
+            if constexpr (KB1 >= 2) {
+                // Skewed software pipeline over the M-tiles.  Step mt runs the
+                // first half of tile mt's K-blocks interleaved with the second
+                // half of tile mt - 1's (2 NT independent accumulation chains,
+                // enough to keep the matrix pipe busy), requantises tile mt - 2
+                // (VALU between the MFMAs), and reads the next step's weight
+                // tiles and init from LDS.
+                constexpr int KH = KB1 / 2;
+                v4i Alo[KH], Ahi[KH], Alo_n[KH], Ahi_n[KH];
 #pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) {
-                        int q = fast ? requant4_sat(accp[nt]) : requant4_clamp(accp[nt], s2, lo2, hi2);
-                        // pin the epilogue here: otherwise it is sunk towards the
-                        // output layer, keeping every raw accumulator live
-                        asm volatile("" : "+v"(q));
-                        if constexpr (OUT16) blk[nt][pm & 3] = q;
-                        else a2[nt][pm >> 2][pm & 3] = q;
-                    }
-                    if constexpr (OUT16) {
-                        if ((pm & 3) == 3) {
-                            const v4i w = wo[(pm >> 2) * 64];
+                for (int kb = 0; kb < KH; ++kb) { Alo[kb] = wt2[kb * 64]; Ahi[kb] = Alo[kb]; }
+                int4 bias = bias2[0], bnext = bias;
+                v4i accA[NT], accE[NT];  // tile mt - 1 (finishing), tile mt - 2 (done)
 #pragma unroll
-                            for (int nt = 0; nt < NT; ++nt)
-                                acco[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(w, blk[nt], acco[nt], 0, 0, 0);
-                        }
+                for (int mt = 0; mt <= MT2 + 1; ++mt) {
+                    if (mt + 1 < MT2) {
+#pragma unroll
+                        for (int kb = 0; kb < KH; ++kb) Alo_n[kb] = wt2[((mt + 1) * KB1 + kb) * 64];
+                        bnext = bias2[(mt + 1) * 4];
                     }
                     if (mt < MT2) {
-                        // the next tile's LDS reads first, then one MFMA and a share of
-                        // the epilogue's VALU work, and so on
-                        __builtin_amdgcn_sched_group_barrier(0x100, KB1 + 1, 0);
 #pragma unroll
-                        for (int i = 0; i < KB1 * NT; ++i) {
-                            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                            __builtin_amdgcn_sched_group_barrier(0x002, ((fast ? 5 : 11) * NT + KB1 * NT - 1) / (KB1 * NT), 0);
+                        for (int kb = 0; kb < KH; ++kb) Ahi_n[kb] = wt2[(mt * KB1 + KH + kb) * 64];
+                    }
+                    v4i accB[NT];
+                    if (mt < MT2) {
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt) accB[nt] = v4i{bias.x, bias.y, bias.z, bias.w};
+                    }
+#pragma unroll
+                    for (int kb = 0; kb < KH; ++kb) {
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt) {
+                            if (mt >= 1 && mt <= MT2)
+                                accA[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Ahi[kb], a1[nt][KH + kb], accA[nt], 0, 0, 0);
+                            if (mt < MT2)
+                                accB[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Alo[kb], a1[nt][kb], accB[nt], 0, 0, 0);
                         }
                     }
+                    if (mt >= 2) {
+                        epilogue(mt - 2, accE);
+                        if (mt < MT2) {
+                            // the next step's LDS reads first, then one MFMA and a
+                            // share of the epilogue's VALU work, and so on
+                            __builtin_amdgcn_sched_group_barrier(0x100, 2 * KH + 1, 0);
+#pragma unroll
+                            for (int i = 0; i < KB1 * NT; ++i) {
+                                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                                __builtin_amdgcn_sched_group_barrier(0x002, (EPI_V + KB1 * NT - 1) / (KB1 * NT), 0);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        accE[nt] = accA[nt];
+                        accA[nt] = accB[nt];
+                    }
+#pragma unroll
+                    for (int kb = 0; kb < KH; ++kb) {
+                        Alo[kb] = Alo_n[kb];
+                        Ahi[kb] = Ahi_n[kb];
+                    }
+                    bias = bnext;
+                    __builtin_amdgcn_sched_barrier(0);
                 }
+            } else {
+                // one K-block: the weight tile and init of tile mt + 1 are read
+                // from LDS while tile mt computes, and the requantisation of
+                // tile mt - 1 is interleaved with the MFMAs of tile mt
+                v4i Acur = wt2[0], Anext = Acur;
+                int4 bias = bias2[0], bnext = bias;
+                v4i accp[NT];
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) accp[nt] = acc[nt];
+                for (int mt = 0; mt <= MT2; ++mt) {
+                    if (mt + 1 < MT2) {
+                        Anext = wt2[(mt + 1) * 64];
+                        bnext = bias2[(mt + 1) * 4];
+                    }
+                    v4i acc[NT];
+                    if (mt < MT2) {
 #pragma unroll
-                for (int kb = 0; kb < KB1; ++kb) Acur[kb] = Anext[kb];
-                bias = bnext;
-                __builtin_amdgcn_sched_barrier(0);
+                        for (int nt = 0; nt < NT; ++nt)
+                            acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Acur, a1[nt][0],
+                                                                           v4i{bias.x, bias.y, bias.z, bias.w}, 0, 0, 0);
+                    }
+                    if (mt > 0) {
+                        epilogue(mt - 1, accp);
+                        if (mt < MT2) {
+                            __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+#pragma unroll
+                            for (int i = 0; i < NT; ++i) {
+                                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                                __builtin_amdgcn_sched_group_barrier(0x002, (EPI_V + NT - 1) / NT, 0);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) accp[nt] = acc[nt];
+                    Acur = Anext;
+                    bias = bnext;
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             }
         } else if constexpr (OUT16) {
 #pragma unroll
@@ -764,7 +854,7 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
             for (int nt = 0; nt < NT; ++nt) {
                 const v4i z = acco[nt];
                 const int zs = tL == 0 ? z[0] : tL == 1 ? z[1] : tL == 2 ? z[2] : z[3];
-                const int zL = __shfl(zs, j16 + 16 * (label0 >> 2));
+                const int zL = row_bcast(zs, label0 >> 2);
                 unsigned long long beat = 0, eqm = 0;
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
@@ -783,9 +873,9 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
                     argmax_combine(bv, bi, bc);
                     const bool mine = g == 0 && ((viol16 >> j16) & 1u);
                     ties += (unsigned)__popcll(__ballot(mine && bc > 1));
-                    emit_tile(P, ro, einfo, w, mine, plast[nt], ilast[nt], bi, lane);
+                    emit_tile(ro, einfo, w, mine, plast[nt], ilast[nt], bi, lane);
                 }
-                if (ties) rec_tally(P, ro, lane_get(einfo, EI_SLOT), 0u, ties, lane);
+                if (ties) rec_tally(ro, lane_get(einfo, EI_SLOT), 0u, ties, lane);
             }
         } else {
             // ---- general output layer: M-tiles in turn, full lowest-index argmax
@@ -816,15 +906,15 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
                 argmax_combine(bestv[nt], besti[nt], bestc[nt]);
                 const bool mine = valid[nt] && g == 0;
                 const unsigned long long tm = __ballot(mine && bestc[nt] > 1);
-                if (tm) rec_tally(P, ro, lane_get(einfo, EI_SLOT), 0u, (unsigned)__popcll(tm), lane);
-                emit_tile(P, ro, einfo, w, mine && besti[nt] != label0, plast[nt], ilast[nt], besti[nt], lane);
+                if (tm) rec_tally(ro, lane_get(einfo, EI_SLOT), 0u, (unsigned)__popcll(tm), lane);
+                emit_tile(ro, einfo, w, mine && besti[nt] != label0, plast[nt], ilast[nt], besti[nt], lane);
             }
         }
 
         }  // segments of the group
         if (!more) break;
     }
-    rec_finish(P, ro, lane);
+    rec_finish(ro, lane);
 }
 
 #define IBMC_ENUM_VARIANT(L_, KB1_, KB2_, NT_, WLDS_, EPI_, O16_, TAG_)                                      \

@@ -159,7 +159,7 @@ struct EnumParams {
     int32_t packed;                    // packed int16 first layer (bound checked by the host)
     int32_t vb_lo, vb_hi;              // pre-clamp of the scaled base for the packed path
     int32_t track_first;               // maintain first_chunk (ordered searches)
-    int32_t pad_;
+    int32_t notify;                    // any of stop_on_first, track_first, hit_host (set at launch)
 };
 
 // Record slots a wave of the integer kernel reserves at a time.

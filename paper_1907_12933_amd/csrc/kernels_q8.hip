@@ -236,7 +236,9 @@ hipError_t launch_enum_q8(const EnumVariant &v, int grid, const EnumParams &P,
                           const int32_t *u0_store, int64_t u0_stride, const int32_t *u0_index,
                           hipStream_t s) {
     const int64_t lds = enum_lds_bytes(v, P.net);
-    void *args[] = {const_cast<EnumParams *>(&P), &u0_store, &u0_stride, &u0_index};
+    EnumParams Q = P;
+    Q.notify = (P.stop_on_first || P.track_first || P.hit_host) ? 1 : 0;
+    void *args[] = {&Q, &u0_store, &u0_stride, &u0_index};
     return hipLaunchKernel(v.fn, dim3(grid), dim3(256), args, (size_t)lds, s);
 }
 
