@@ -121,6 +121,11 @@ def proposer_leg(ctx, ibmc, inputs, w, net, recs, args):
     if unsafe:
         out["ttfc_speedup_median"] = med([r[2] / r[3] for r in unsafe if r[3] > 0])
         out["points_before_first_ratio_median"] = med([(r[4] + 1) / (r[5] + 1) for r in unsafe])
+        # totals over the unsafe held-out images (the tail of late first hits counts)
+        out["ttfc_plain_total_s"] = float(sum(r[2] for r in unsafe))
+        out["ttfc_learned_total_s"] = float(sum(r[3] for r in unsafe))
+        out["points_before_first_plain_total"] = int(sum(r[4] for r in unsafe))
+        out["points_before_first_learned_total"] = int(sum(r[5] for r in unsafe))
     return out
 
 

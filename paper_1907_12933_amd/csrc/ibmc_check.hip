@@ -737,25 +737,7 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
     IBMC_TRY(ctx->prop_ids.upload(&zero, 4, s));
     IBMC_TRY(ctx->u0_index.upload(&zero, 4, s));
     IBMC_TRY(ctx->u0.reserve((size_t)net->qd.H[1] * 4));
-    HIP_OK(launch_clean_q8(net->qd, ctx->props.as<PropDev>(), ctx->prop_ids.as<int32_t>(), 1, ctx->u0.as<int32_t>(),
-                           net->qd.H[1], s));
-    // order of the candidates
     std::vector<int32_t> order;
-    if (p) {
-        PropCand pc;
-        pc.m = m;
-        pc.dmax = 0;
-        for (int i = 0; i < m; ++i) { pc.deltas[i] = deltas[i]; pc.dmax = std::max(pc.dmax, std::abs((int)deltas[i])); }
-        DevBuf feat, sc;
-        const PropParams PP = prop_views(p);
-        IBMC_TRY(feat.reserve((size_t)N1 * kPropF * 4));
-        IBMC_TRY(sc.reserve((size_t)N1 * 4));
-        HIP_OK(launch_prop_features(net->qd, pd.image, rows, cols, pc, feat.as<float>(), s));
-        HIP_OK(launch_prop_score(PP, feat.as<float>(), N1, sc.as<float>(), s));
-        IBMC_TRY(ctx->order.reserve((size_t)N1 * 4));
-        HIP_OK(launch_prop_sort(sc.as<float>(), (int)N1, ctx->order.as<int32_t>(), s));
-        HIP_OK(hipStreamSynchronize(s));  // feat / sc are released here
-    }
     // jobs: one per level >= 1
     std::vector<int> lv;
     for (int k = o->k_min; k <= o->k_max; ++k) lv.push_back(k);
@@ -780,9 +762,15 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
             ch = ceil_div(N1, CH);
         } else {
             J.mode = SEG_SHELL;
-            scum.assign(N1, 0);
-            for (int64_t t = 1; t < N1; ++t) scum[t] = (t >= 2 ? scum[t - 1] + ceil_div(t - 1, CH) : 0);
-            ch = scum[N1 - 1] + ceil_div(N1 - 1, CH);
+            // chunks before shell t (shells t >= 1 have t candidates); the
+            // table depends on (N1, CH) only and stays on the device
+            if (ctx->shell_cum_n != N1 || ctx->shell_cum_ch != CH) {
+                scum.assign(N1, 0);
+                for (int64_t t = 1; t < N1; ++t) scum[t] = (t >= 2 ? scum[t - 1] + ceil_div(t - 1, CH) : 0);
+            }
+            int64_t last = 0;  // scum[N1 - 1]
+            for (int64_t t = 2; t < N1; ++t) last += ceil_div(t - 1, CH);
+            ch = last + ceil_div(N1 - 1, CH);
         }
         J.chunk_end = total + ch;
         total += ch;
@@ -804,18 +792,44 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
     const int64_t rec_slots = cap + grid * 4 * kRecBlock;
     IBMC_TRY(ctx->recs.reserve((size_t)std::max<int64_t>(rec_slots, 1) * sizeof(DevRec)));
     if (!qc.empty()) IBMC_TRY(ctx->qcum.upload(qc.data(), qc.size() * 8, s));
-    DevBuf dscum;
-    if (!scum.empty()) IBMC_TRY(dscum.upload(scum.data(), scum.size() * 8, s));
+    if (!scum.empty()) {
+        IBMC_TRY(ctx->shell_cum.upload(scum.data(), scum.size() * 8, s));
+        ctx->shell_cum_n = N1;
+        ctx->shell_cum_ch = CH;
+    }
+    if (p) IBMC_TRY(ctx->order.reserve((size_t)N1 * 4));
     for (auto &J : jobs) {
         J.qcum = (J.mode == SEG_PLAIN && J.k >= 2) ? ctx->qcum.as<int64_t>() : nullptr;
         J.order = p ? ctx->order.as<int32_t>() : nullptr;
-        J.shell_cum = (J.mode == SEG_SHELL) ? dscum.as<int64_t>() : nullptr;
+        J.shell_cum = (J.mode == SEG_SHELL) ? ctx->shell_cum.as<int64_t>() : nullptr;
+    }
+    if (!jobs.empty()) IBMC_TRY(ctx->jobs.upload(jobs.data(), jobs.size() * sizeof(EnumJob), s));
+    // every upload is done: the clean pass, the proposer's ordering and the
+    // enumeration are queued back to back, with no host wait in between
+    HIP_OK(launch_clean_q8(net->qd, ctx->props.as<PropDev>(), ctx->prop_ids.as<int32_t>(), 1, ctx->u0.as<int32_t>(),
+                           net->qd.H[1], s));
+    // order of the candidates
+    if (p) {
+        PropCand pc;
+        pc.m = m;
+        pc.dmax = 0;
+        for (int i = 0; i < m; ++i) { pc.deltas[i] = deltas[i]; pc.dmax = std::max(pc.dmax, std::abs((int)deltas[i])); }
+        const PropParams PP = prop_views(p);
+        // the context's buffers (no allocation once sized); the clean pass
+        // above has left the first-layer potentials in u0
+        IBMC_TRY(ctx->prop_feat.reserve((size_t)N1 * kPropF * 4));
+        IBMC_TRY(ctx->prop_scores.reserve((size_t)N1 * 4));
+        IBMC_TRY(ctx->prop_scratch.reserve((size_t)(net->qd.H[1] + n) * 4));
+        HIP_OK(launch_prop_features(net->qd, pd.image, ctx->u0.as<int32_t>(), rows, cols, pc,
+                                    ctx->prop_scratch.as<int32_t>(), ctx->prop_scratch.as<float>() + net->qd.H[1],
+                                    ctx->prop_feat.as<float>(), s));
+        HIP_OK(launch_prop_score(PP, ctx->prop_feat.as<float>(), N1, ctx->prop_scores.as<float>(), s));
+        HIP_OK(launch_prop_sort(ctx->prop_scores.as<float>(), (int)N1, ctx->order.as<int32_t>(), s));
     }
     double ttfc = -1.0;
     int64_t rec_total = 0;
     std::vector<unsigned long long> h(n_ctr);
     if (!jobs.empty() && total > 0) {
-        IBMC_TRY(ctx->jobs.upload(jobs.data(), jobs.size() * sizeof(EnumJob), s));
         EnumParams P{};
         P.net = net->qd;
         P.jobs = ctx->jobs.as<EnumJob>();
@@ -903,15 +917,36 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
         }
         std::vector<int64_t> rowstart(n + 1, 0);   // plain level 2: points before first pixel q
         for (int q = 0; q < n; ++q) rowstart[q + 1] = rowstart[q] + (int64_t)(n - 1 - q) * m * m;
+        // pairs with first pixel below a: the lex index of pair (a, b) is
+        // pairs_before[a] + b - a - 1
+        std::vector<int64_t> pairs_before(n + 1, 0);
+        for (int a = 0; a < n; ++a) pairs_before[a + 1] = pairs_before[a] + (n - 1 - a);
+        int first_p0 = -1;
         for (const CexRec &r : recs) {
             int64_t pos = -1;
             int px[2] = {0, 0}, dg[2] = {0, 0};
             int64_t mk = (r.k == 1) ? m : (int64_t)m * m;
-            int tmp[kMaxK];
-            lex_unrank_subset(r.rank / mk, r.k, n, tmp);
+            const int64_t sidx = r.rank / mk;  // lex index of the pixel subset
+            if (r.k == 1) {
+                px[0] = (int)sidx;
+            } else {
+                px[0] = (int)(std::upper_bound(pairs_before.begin(), pairs_before.end(), sidx) - pairs_before.begin()) - 1;
+                px[1] = (int)(sidx - pairs_before[px[0]]) + px[0] + 1;
+            }
             int64_t d = r.rank % mk;
             for (int j = r.k - 1; j >= 0; --j) { dg[j] = (int)(d % m); d /= m; }
-            for (int j = 0; j < r.k; ++j) px[j] = tmp[j];
+            // plain order: records come in rank order, level 1 (visited first)
+            // before level 2, and within level 2 the visiting order starts with
+            // the first pixel, so only the records sharing the first record's
+            // first pixel can hold the earliest position
+            if (!p) {
+                if (first_pos >= 0 && r.k == 1) continue;
+                if (r.k == 2) {
+                    if (first_pos >= 0 && first_p0 < 0) break;  // a level-1 record came first
+                    if (first_p0 < 0) first_p0 = px[0];
+                    else if (px[0] != first_p0) break;
+                }
+            }
             if (r.k == 1) {
                 const int cand = px[0] * m + dg[0];
                 pos = p ? pos_of[cand] : cand;

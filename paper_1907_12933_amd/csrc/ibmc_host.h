@@ -65,6 +65,8 @@ struct ibmc_ctx {
     ibmc::DevBuf images, props, jobs, qcum, u0, u0_index, prop_ids, counters, recs, ties, order;
     ibmc::DevBuf u0f, sortbuf;
     ibmc::DevBuf recout;  // sorted records in the public layout, on their way to a host buffer
+    ibmc::DevBuf prop_scratch, prop_feat, prop_scores, shell_cum;  // ranked search
+    int64_t shell_cum_n = -1, shell_cum_ch = -1;                   // shell_cum holds this plan
     ibmc::DevBuf cov_img, cov_pots, cov_bits, cov_sums, cov_out;
     // tuned kernel variant per network shape key
     std::map<std::string, std::string> tuned;

@@ -215,6 +215,27 @@ static ibmc_status build_q8(ibmc_ctx *ctx, ibmc_mlp *m) {
     }
     IBMC_TRY(m->buf.emplace_back().upload(b1s.data(), b1s.size() * 4, s));
     q.b1s = (const int32_t *)m->buf.back().p;
+    // column norms of the first layer for the proposer's features
+    {
+        std::vector<float> pn((size_t)2 * n + 2, 0.f);
+        float M1 = 0.f, M2 = 0.f;
+        for (int p = 0; p < n; ++p) {
+            int64_t s1 = 0, s2 = 0;
+            for (int j = 0; j < m->dims[1]; ++j) {
+                const int w = m->Wq[0][(size_t)j * n + p];
+                s1 += std::abs(w);
+                s2 += (int64_t)w * w;
+            }
+            pn[p] = (float)s1;
+            pn[n + p] = std::sqrt((float)s2);
+            M1 = std::max(M1, pn[p]);
+            M2 = std::max(M2, pn[n + p]);
+        }
+        pn[2 * n] = std::max(M1, 1.f);
+        pn[2 * n + 1] = std::max(M2, 1.f);
+        IBMC_TRY(m->buf.emplace_back().upload(pn.data(), pn.size() * 4, s));
+        q.pnorm = (const float *)m->buf.back().p;
+    }
     IBMC_TRY(m->buf.emplace_back().upload(b1n.data(), b1n.size() * 4, s));
     q.b1n = (const int32_t *)m->buf.back().p;
     IBMC_TRY(m->buf.emplace_back().upload(rs.data(), rs.size() * 4, s));

@@ -70,6 +70,7 @@ struct QNetDev {
     const int32_t *rowsum1;            // 128 * sum_i W1[j][i], natural order, padded (x - 128 trick)
     const int8_t *Wd[kMaxLayers + 1];  // l >= 1: dense row-major [dims[l]][dims[l-1]]
     const int32_t *bd[kMaxLayers + 1]; // l >= 1: dense bias [dims[l]]
+    const float *pnorm;                // proposer features: sum |W1[:, p]| [n], ||W1[:, p]||_2 [n], their maxima
 };
 
 // Float network (sigmoid variant).

@@ -65,7 +65,9 @@ static ibmc_status score_image(ibmc_ctx *ctx, const ibmc_proposer *p, const ibmc
     hipStream_t s = ctx->stream;
     const int64_t N = (int64_t)net->dims[0] * pc.m;
     IBMC_TRY(feat.reserve((size_t)N * kPropF * 4));
-    HIP_OK(launch_prop_features(net->qd, dimage, rows, cols, pc, feat.as<float>(), s));
+    IBMC_TRY(ctx->prop_scratch.reserve((size_t)(net->qd.H[1] + net->dims[0]) * 4));
+    HIP_OK(launch_prop_features(net->qd, dimage, nullptr, rows, cols, pc, ctx->prop_scratch.as<int32_t>(),
+                                ctx->prop_scratch.as<float>() + net->qd.H[1], feat.as<float>(), s));
     if (want_scores) {
         IBMC_TRY(scores.reserve((size_t)N * 4));
         HIP_OK(launch_prop_score(prop_views(p), feat.as<float>(), N, scores.as<float>(), s));

@@ -29,8 +29,12 @@ struct PropCand {
     int16_t deltas[kMaxDeltas];
 };
 
-hipError_t launch_prop_features(const QNetDev &net, const uint8_t *image, int rows, int cols, const PropCand &pc,
-                                float *feat, hipStream_t s);
+// Feature rows [n m][32] of one image's candidates.  u0: its clean
+// first-layer potentials in sigma order (computed into u0_scratch, H[1]
+// ints, when null); nl_scratch: n floats.
+hipError_t launch_prop_features(const QNetDev &net, const uint8_t *image, const int32_t *u0, int rows, int cols,
+                                const PropCand &pc, int32_t *u0_scratch, float *nl_scratch, float *feat,
+                                hipStream_t s);
 hipError_t launch_prop_score(const PropParams &P, const float *feat, int64_t N, float *scores, hipStream_t s);
 hipError_t launch_prop_train(const PropParams &P, const float *feat, const float *labels, const int32_t *index,
                              int64_t begin, int64_t count, float inv_b, float pw, const PropGrads &G, int n_cu,

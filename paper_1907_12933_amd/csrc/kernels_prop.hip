@@ -1,7 +1,7 @@
 // Learned proposal network: candidate features, bf16 MFMA forward (scoring),
 // fused forward/backward with the weight gradient on bf16 MFMA, Adam, a
-// single-workgroup bitonic sort of the scores, and candidate labels from
-// counterexample records.
+// single-workgroup sort of the scores (radix, or bitonic above 8192
+// candidates), and candidate labels from counterexample records.
 //
 // Network: s = w2 . relu(W1 f + b1) + c with f in R^32, hidden 128.
 // v_mfma_f32_16x16x32_bf16, orientation out[hidden x samples] = W1 x F^T:
@@ -9,6 +9,8 @@
 // samples; the accumulator leaves lane (j + 16 g) with hidden 4g..4g+3 of
 // sample j.
 #include "kernels_prop.h"
+
+#include <rocprim/block/block_radix_sort.hpp>
 
 namespace ibmc {
 
@@ -18,61 +20,68 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }  // round to nearest even
 
 // ---------------------------------------------------------------------------
-// features (one workgroup per image)
+// features: clean first-layer potentials (when not given), the live-weighted
+// column norm of every pixel, then the candidates' feature rows
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) prop_features_kernel(QNetDev net, const uint8_t *image, int rows, int cols,
-                                                            PropCand pc, float *feat) {
-    __shared__ int xs[kMaxWidth];
-    __shared__ unsigned char live[kMaxWidth];
-    __shared__ float n1[kMaxWidth], n2[kMaxWidth], nl[kMaxWidth];
-    __shared__ float red[3][256];
-    const int tid = threadIdx.x;
+// Clean first-layer potentials of one image in sigma order: 64 neurons per
+// workgroup, the inputs split over its four waves.
+__global__ void __launch_bounds__(256) prop_u0_kernel(QNetDev net, const uint8_t *image, int32_t *u0) {
+    __shared__ int part[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int n = net.dims[0], H1 = net.H[1];
-    for (int i = tid; i < n; i += blockDim.x) xs[i] = image[i];
+    const int q = blockIdx.x * 64 + lane;
+    const int seg = (n + 3) / 4, i0 = wv * seg, i1 = min(n, i0 + seg);
+    int u = 0;
+    if (q < H1)
+        for (int i = i0; i < i1; ++i) u += (int)net.W1T[(int64_t)i * H1 + q] * (int)image[i];
+    part[wv][lane] = u;
     __syncthreads();
-    // clean first-layer potentials (sigma order) and the requantiser's linear window
+    if (wv == 0 && q < H1) u0[q] = net.b1s[q] + part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+}
+
+// Sum of |W1[:, p]| over the neurons whose clean potential lies in the
+// requantiser's linear window [0, 128 2^s): one wave per pixel.
+__global__ void __launch_bounds__(256) prop_live_norm_kernel(QNetDev net, const int32_t *u0, float *nl) {
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int n = net.dims[0], H1 = net.H[1];
+    if (p >= n) return;  // whole waves
     const int top = 128 << net.shift[0];
-    for (int q = tid; q < H1; q += blockDim.x) {
-        int u = net.b1s[q];
-        for (int i = 0; i < n; ++i) u += (int)net.W1T[(int64_t)i * H1 + q] * xs[i];
-        live[q] = (sigma64(q) < net.dims[1]) && u >= 0 && u < top;
+    int sl = 0;
+    for (int q = lane; q < H1; q += 64) {
+        const int u = u0[q];
+        const int w = net.W1T[(int64_t)p * H1 + q];
+        if (sigma64(q) < net.dims[1] && u >= 0 && u < top) sl += w < 0 ? -w : w;
     }
-    __syncthreads();
-    float m1 = 0.f, m2 = 0.f, ml = 0.f;
-    for (int p = tid; p < n; p += blockDim.x) {
-        int s1 = 0, sl = 0;
-        long long s2 = 0;
-        const int8_t *col = net.W1T + (int64_t)p * H1;
-        for (int q = 0; q < H1; ++q) {
-            const int w = col[q];
-            const int aw = w < 0 ? -w : w;
-            s1 += aw;
-            s2 += (long long)w * w;
-            if (live[q]) sl += aw;
-        }
-        n1[p] = (float)s1;
-        n2[p] = sqrtf((float)s2);
-        nl[p] = (float)sl;
-        m1 = fmaxf(m1, n1[p]);
-        m2 = fmaxf(m2, n2[p]);
-        ml = fmaxf(ml, nl[p]);
-    }
-    red[0][tid] = m1; red[1][tid] = m2; red[2][tid] = ml;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sl += __shfl_xor(sl, off);
+    if (lane == 0) nl[p] = (float)sl;
+}
+
+// Feature rows of the candidates (p, i): position, clean value, delta and its
+// clamped effect, the three column norms (each over its maximum), a constant.
+__global__ void __launch_bounds__(256) prop_feat_kernel(QNetDev net, const uint8_t *image, int rows, int cols,
+                                                        PropCand pc, const float *nl, float *feat) {
+    __shared__ float red[256];
+    const int tid = threadIdx.x, n = net.dims[0];
+    float ml = 0.f;
+    for (int p = tid; p < n; p += blockDim.x) ml = fmaxf(ml, nl[p]);
+    red[tid] = ml;
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
-        if (tid < st)
-            for (int z = 0; z < 3; ++z) red[z][tid] = fmaxf(red[z][tid], red[z][tid + st]);
+        if (tid < st) red[tid] = fmaxf(red[tid], red[tid + st]);
         __syncthreads();
     }
-    const float M1 = fmaxf(red[0][0], 1.f), M2 = fmaxf(red[1][0], 1.f), ML = fmaxf(red[2][0], 1.f);
+    const float *n1 = net.pnorm, *n2 = net.pnorm + n;
+    const float M1 = net.pnorm[2 * n], M2 = net.pnorm[2 * n + 1], ML = fmaxf(red[0], 1.f);
     const float rden = rows > 1 ? (float)(rows - 1) : 1.f, cden = cols > 1 ? (float)(cols - 1) : 1.f;
     const int m = pc.m;
     const float dmax = fmaxf((float)pc.dmax, 1.f);
-    for (int t = tid; t < n * m; t += blockDim.x) {
+    for (int t = blockIdx.x * blockDim.x + tid; t < n * m; t += gridDim.x * blockDim.x) {
         const int p = t / m, i = t - p * m;
         const int r = p / cols, c = p - r * cols;
-        const int x = xs[p];
+        const int x = image[p];
         const int d = pc.deltas[i];
         const int e = min(max(x + d, 0), 255) - x;
         float *f = feat + (int64_t)t * 32;
@@ -322,6 +331,29 @@ __global__ void __launch_bounds__(1024) prop_sort_kernel(const float *scores, in
     for (int t = threadIdx.x; t < N; t += blockDim.x) order[t] = (int32_t)(keys[t] & 0xffffffffu);
 }
 
+// Up to 1024 * ITEMS scores in one workgroup: a stable block radix sort of
+// the inverted order keys with the candidate index as value, so that ties
+// keep index order (the same order as the bitonic sort of key:index).
+template <int ITEMS>
+__global__ void __launch_bounds__(1024) prop_rsort_kernel(const float *scores, int N, int32_t *order) {
+    using Sort = rocprim::block_radix_sort<unsigned, 1024, ITEMS, int>;
+    __shared__ typename Sort::storage_type st;
+    unsigned k[ITEMS];
+    int v[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int t = threadIdx.x * ITEMS + j;  // blocked arrangement: index order
+        k[j] = t < N ? order_key(scores[t]) : 0xffffffffu;
+        v[j] = t;
+    }
+    Sort().sort(k, v, st);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int t = threadIdx.x * ITEMS + j;
+        if (t < N) order[t] = v[j];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // candidate labels: every (pixel, delta) that occurs in a counterexample
 // ---------------------------------------------------------------------------
@@ -348,9 +380,17 @@ __global__ void __launch_bounds__(256) label_candidates_kernel(int n, int m, con
 // launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_prop_features(const QNetDev &net, const uint8_t *image, int rows, int cols, const PropCand &pc,
-                                float *feat, hipStream_t s) {
-    hipLaunchKernelGGL(prop_features_kernel, dim3(1), dim3(256), 0, s, net, image, rows, cols, pc, feat);
+hipError_t launch_prop_features(const QNetDev &net, const uint8_t *image, const int32_t *u0, int rows, int cols,
+                                const PropCand &pc, int32_t *u0_scratch, float *nl_scratch, float *feat,
+                                hipStream_t s) {
+    const int n = net.dims[0];
+    if (!u0) {
+        hipLaunchKernelGGL(prop_u0_kernel, dim3((net.H[1] + 63) / 64), dim3(256), 0, s, net, image, u0_scratch);
+        u0 = u0_scratch;
+    }
+    hipLaunchKernelGGL(prop_live_norm_kernel, dim3((n + 3) / 4), dim3(256), 0, s, net, u0, nl_scratch);
+    const int grid = (int)std::min<int64_t>(((int64_t)n * pc.m + 255) / 256, 1024);
+    hipLaunchKernelGGL(prop_feat_kernel, dim3(grid), dim3(256), 0, s, net, image, rows, cols, pc, nl_scratch, feat);
     return hipGetLastError();
 }
 
@@ -381,6 +421,10 @@ hipError_t launch_prop_adam(float *theta, float *grad, float *mom, float *vel, i
 int prop_sort_max() { return 16384; }
 
 hipError_t launch_prop_sort(const float *scores, int N, int32_t *order, hipStream_t s) {
+    if (N <= 1024 * 8) {
+        hipLaunchKernelGGL(prop_rsort_kernel<8>, dim3(1), dim3(1024), 0, s, scores, N, order);
+        return hipGetLastError();
+    }
     int P2 = 1;
     while (P2 < N) P2 <<= 1;
     hipLaunchKernelGGL(prop_sort_kernel, dim3(1), dim3(1024), (size_t)P2 * 8, s, scores, N, order);

@@ -23,21 +23,39 @@ __device__ __forceinline__ int pack4(int a0, int a1, int a2, int a3) {
 
 
 // ---------------------------------------------------------------------------
-// plain dense forward of one image held in LDS (one workgroup of 256 threads)
+// plain dense forward of one image held in LDS (one workgroup of kFwdThreads)
 // ---------------------------------------------------------------------------
 
-// xs: n pixel values; act0/act1: scratch of kMaxWidth ints each.
+constexpr int kFwdThreads = 1024;
+constexpr int kFwdSplit = 4;  // every dot product is split over this many threads
+
+// xs: n pixel values; act0/act1: scratch of kMaxWidth ints each; part:
+// kFwdSplit x kMaxWidth ints of partial sums.  Every layer's dot products are
+// split kFwdSplit ways over the inputs (short dependent chains, coalesced
+// weight reads: the transposed first layer by consecutive neurons, the
+// row-major later layers by consecutive input segments of one row).
 // Writes potentials (natural order, layers concatenated) if pot != nullptr,
 // layer-1 potentials in sigma order if u0s != nullptr; returns the label
 // (thread 0 holds the valid value) and the exact-tie flag.
 __device__ void dense_forward_block(const QNetDev &net, const int *xs, int *act0, int *act1,
-                                    int32_t *pot, int32_t *u0s, int *label_out, int *tie_out) {
-    const int tid = threadIdx.x;
+                                    int (*part)[kMaxWidth], int32_t *pot, int32_t *u0s, int *label_out,
+                                    int *tie_out) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
     const int n = net.dims[0], H1 = net.H[1];
-    // layer 1 through the transposed first layer (coalesced), sigma order
-    for (int q = tid; q < H1; q += blockDim.x) {
+    const int seg1 = (n + kFwdSplit - 1) / kFwdSplit;
+    // layer 1 through the transposed first layer, sigma order
+    for (int t = tid; t < H1 * kFwdSplit; t += nthr) {
+        const int q = t % H1, sp = t / H1;
+        const int i0 = sp * seg1, i1 = min(n, i0 + seg1);
+        int u = 0;
+        for (int i = i0; i < i1; ++i) u += (int)net.W1T[(int64_t)i * H1 + q] * xs[i];
+        part[sp][q] = u;
+    }
+    __syncthreads();
+    for (int q = tid; q < H1; q += nthr) {
         int u = net.b1s[q];
-        for (int i = 0; i < n; ++i) u += (int)net.W1T[(int64_t)i * H1 + q] * xs[i];
+#pragma unroll
+        for (int sp = 0; sp < kFwdSplit; ++sp) u += part[sp][q];
         const int neuron = sigma64(q);
         if (u0s) u0s[q] = u;
         if (neuron < net.dims[1]) {
@@ -50,11 +68,21 @@ __device__ void dense_forward_block(const QNetDev &net, const int *xs, int *act0
     int po = net.dims[1];
     for (int l = 2; l <= net.L; ++l) {
         const int nin = net.dims[l - 1], nout = net.dims[l];
+        const int seg = (nin + kFwdSplit - 1) / kFwdSplit;
         const int8_t *W = net.Wd[l];
-        for (int j = tid; j < nout; j += blockDim.x) {
-            int u = net.bd[l][j];
+        for (int t = tid; t < nout * kFwdSplit; t += nthr) {
+            const int j = t / kFwdSplit, sp = t % kFwdSplit;
+            const int i0 = sp * seg, i1 = min(nin, i0 + seg);
             const int8_t *row = W + (int64_t)j * nin;
-            for (int i = 0; i < nin; ++i) u += (int)row[i] * in[i];
+            int u = 0;
+            for (int i = i0; i < i1; ++i) u += (int)row[i] * in[i];
+            part[sp][j] = u;
+        }
+        __syncthreads();
+        for (int j = tid; j < nout; j += nthr) {
+            int u = net.bd[l][j];
+#pragma unroll
+            for (int sp = 0; sp < kFwdSplit; ++sp) u += part[sp][j];
             if (pot) pot[po + j] = u;
             out[j] = (l < net.L) ? requant_relu(u, net.shift[l - 1]) : u;
         }
@@ -73,17 +101,18 @@ __device__ void dense_forward_block(const QNetDev &net, const int *xs, int *act0
     }
 }
 
-__global__ void __launch_bounds__(256) forward_q8_kernel(QNetDev net, const uint8_t *images,
-                                                         int64_t n_images, int32_t *labels,
-                                                         int32_t *pots, int64_t pot_stride) {
+__global__ void __launch_bounds__(kFwdThreads) forward_q8_kernel(QNetDev net, const uint8_t *images,
+                                                                 int64_t n_images, int32_t *labels,
+                                                                 int32_t *pots, int64_t pot_stride) {
     __shared__ int xs[kMaxWidth];
     __shared__ int a0[kMaxWidth], a1[kMaxWidth];
+    __shared__ int part[kFwdSplit][kMaxWidth];
     __shared__ int lab, tie;
     for (int64_t img = blockIdx.x; img < n_images; img += gridDim.x) {
         const uint8_t *x = images + img * net.dims[0];
         for (int i = threadIdx.x; i < net.dims[0]; i += blockDim.x) xs[i] = x[i];
         __syncthreads();
-        dense_forward_block(net, xs, a0, a1, pots ? pots + img * pot_stride : nullptr, nullptr, &lab, &tie);
+        dense_forward_block(net, xs, a0, a1, part, pots ? pots + img * pot_stride : nullptr, nullptr, &lab, &tie);
         __syncthreads();
         if (threadIdx.x == 0 && labels) labels[img] = lab;
         __syncthreads();
@@ -93,18 +122,19 @@ __global__ void __launch_bounds__(256) forward_q8_kernel(QNetDev net, const uint
 // Clean pass of the properties listed in prop_ids: first-layer potentials in
 // sigma order (the base of every incremental update, stored at the property's
 // index) and the clean label.
-__global__ void __launch_bounds__(256) clean_q8_kernel(QNetDev net, PropDev *props,
-                                                       const int32_t *prop_ids, int32_t n_ids,
-                                                       int32_t *u0_store, int64_t u0_stride) {
+__global__ void __launch_bounds__(kFwdThreads) clean_q8_kernel(QNetDev net, PropDev *props,
+                                                               const int32_t *prop_ids, int32_t n_ids,
+                                                               int32_t *u0_store, int64_t u0_stride) {
     __shared__ int xs[kMaxWidth];
     __shared__ int a0[kMaxWidth], a1[kMaxWidth];
+    __shared__ int part[kFwdSplit][kMaxWidth];
     __shared__ int lab, tie;
     for (int t = blockIdx.x; t < n_ids; t += gridDim.x) {
         const int pid = prop_ids[t];
         const uint8_t *x = props[pid].image;
         for (int i = threadIdx.x; i < net.dims[0]; i += blockDim.x) xs[i] = x[i];
         __syncthreads();
-        dense_forward_block(net, xs, a0, a1, nullptr, u0_store + (int64_t)pid * u0_stride, &lab, &tie);
+        dense_forward_block(net, xs, a0, a1, part, nullptr, u0_store + (int64_t)pid * u0_stride, &lab, &tie);
         __syncthreads();
         if (threadIdx.x == 0) { props[pid].label0 = lab; props[pid].tie0 = tie; }
         __syncthreads();
@@ -113,12 +143,13 @@ __global__ void __launch_bounds__(256) clean_q8_kernel(QNetDev net, PropDev *pro
 
 // Replay: rebuild each perturbed image from its record and run the plain
 // forward pass.
-__global__ void __launch_bounds__(256) replay_q8_kernel(QNetDev net, const uint8_t *clean,
-                                                        const int16_t *deltas, int m,
-                                                        const CexRec *recs, int64_t n_recs,
-                                                        int32_t *labels) {
+__global__ void __launch_bounds__(kFwdThreads) replay_q8_kernel(QNetDev net, const uint8_t *clean,
+                                                                const int16_t *deltas, int m,
+                                                                const CexRec *recs, int64_t n_recs,
+                                                                int32_t *labels) {
     __shared__ int xs[kMaxWidth];
     __shared__ int a0[kMaxWidth], a1[kMaxWidth];
+    __shared__ int part[kFwdSplit][kMaxWidth];
     __shared__ int lab, tie;
     __shared__ int pix[kMaxK], dig[kMaxK];
     const int n = net.dims[0];
@@ -138,7 +169,7 @@ __global__ void __launch_bounds__(256) replay_q8_kernel(QNetDev net, const uint8
         if (threadIdx.x == 0)
             for (int j = 0; j < k; ++j) xs[pix[j]] = clamp_pixel(xs[pix[j]] + deltas[dig[j]]);
         __syncthreads();
-        dense_forward_block(net, xs, a0, a1, nullptr, nullptr, &lab, &tie);
+        dense_forward_block(net, xs, a0, a1, part, nullptr, nullptr, &lab, &tie);
         __syncthreads();
         if (threadIdx.x == 0) labels[r] = lab;
         __syncthreads();
@@ -188,7 +219,7 @@ hipError_t launch_forward_q8(const QNetDev &net, const uint8_t *images, int64_t 
                              int32_t *labels, int32_t *pots, int64_t pot_stride, hipStream_t s) {
     if (n_images <= 0) return hipSuccess;
     const int grid = (int)std::min<int64_t>(n_images, 4096);
-    hipLaunchKernelGGL(forward_q8_kernel, dim3(grid), dim3(256), 0, s, net, images, n_images,
+    hipLaunchKernelGGL(forward_q8_kernel, dim3(grid), dim3(kFwdThreads), 0, s, net, images, n_images,
                        labels, pots, pot_stride);
     return hipGetLastError();
 }
@@ -197,7 +228,7 @@ hipError_t launch_clean_q8(const QNetDev &net, PropDev *props, const int32_t *pr
                            int32_t n_ids, int32_t *u0_store, int64_t u0_stride, hipStream_t s) {
     if (n_ids <= 0) return hipSuccess;
     const int grid = std::min(n_ids, 4096);
-    hipLaunchKernelGGL(clean_q8_kernel, dim3(grid), dim3(256), 0, s, net, props, prop_ids, n_ids,
+    hipLaunchKernelGGL(clean_q8_kernel, dim3(grid), dim3(kFwdThreads), 0, s, net, props, prop_ids, n_ids,
                        u0_store, u0_stride);
     return hipGetLastError();
 }
@@ -206,7 +237,7 @@ hipError_t launch_replay_q8(const QNetDev &net, const uint8_t *clean, const int1
                             const CexRec *recs, int64_t n_recs, int32_t *labels, hipStream_t s) {
     if (n_recs <= 0) return hipSuccess;
     const int grid = (int)std::min<int64_t>(n_recs, 8192);
-    hipLaunchKernelGGL(replay_q8_kernel, dim3(grid), dim3(256), 0, s, net, clean, deltas, m, recs,
+    hipLaunchKernelGGL(replay_q8_kernel, dim3(grid), dim3(kFwdThreads), 0, s, net, clean, deltas, m, recs,
                        n_recs, labels);
     return hipGetLastError();
 }
