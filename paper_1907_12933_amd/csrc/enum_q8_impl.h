@@ -264,6 +264,7 @@ __device__ __forceinline__ void argmax_combine(int &bv, int &bi, int &bc) {
 struct RecOut {
     int64_t next, end;   // free slots of the current block
     int slot;            // level slot being counted
+    bool notified;       // this wave has reported its first counterexample
     unsigned long long cex, ties;
 };
 
@@ -317,7 +318,10 @@ __device__ __forceinline__ void emit_tile(RecOut &o, int einfo, int w, bool viol
         if (lane == 0) start = atomicAdd(P.rec_count, (unsigned long long)kRecBlock);
         nb = (int64_t)wave_uniform(start);  // lane 0's value
     }
-    if (P.notify) {
+    // side effects of a counterexample, once per wave: its chunks come in
+    // increasing order, so the first one holds the wave's smallest chunk
+    if (P.notify && !o.notified) {
+        o.notified = true;
         const int64_t gchunk = lane_get64(einfo, EI_GCLO, EI_GCHI);
         if (lane == 0) {
             if (P.track_first) atomicMin(P.first_chunk, (unsigned long long)gchunk);
@@ -647,6 +651,7 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
     ro.next = 0;
     ro.end = 0;
     ro.slot = -1;
+    ro.notified = false;
     ro.cex = 0;
     ro.ties = 0;
 

@@ -302,10 +302,12 @@ __global__ void __launch_bounds__(256) prop_adam_kernel(float *theta, float *gra
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ unsigned order_key(float s) {
-    // monotone float -> uint map, then inverted so that larger scores come first
+    // monotone float -> uint map, then inverted so that larger scores come
+    // first; the order keeps 16 bits (sign, exponent, 7 mantissa bits: the
+    // precision of the network's bf16 products), ties go by candidate index
     const unsigned b = __float_as_uint(s);
     const unsigned u = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-    return ~u;
+    return (~u) >> 16;
 }
 
 __global__ void __launch_bounds__(1024) prop_sort_kernel(const float *scores, int N, int32_t *order) {
@@ -332,8 +334,8 @@ __global__ void __launch_bounds__(1024) prop_sort_kernel(const float *scores, in
 }
 
 // Up to 1024 * ITEMS scores in one workgroup: a stable block radix sort of
-// the inverted order keys with the candidate index as value, so that ties
-// keep index order (the same order as the bitonic sort of key:index).
+// the 16-bit order keys with the candidate index as value, so that ties keep
+// index order (the same order as the bitonic sort of key:index).
 template <int ITEMS>
 __global__ void __launch_bounds__(1024) prop_rsort_kernel(const float *scores, int N, int32_t *order) {
     using Sort = rocprim::block_radix_sort<unsigned, 1024, ITEMS, int>;
@@ -343,10 +345,10 @@ __global__ void __launch_bounds__(1024) prop_rsort_kernel(const float *scores, i
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int t = threadIdx.x * ITEMS + j;  // blocked arrangement: index order
-        k[j] = t < N ? order_key(scores[t]) : 0xffffffffu;
+        k[j] = t < N ? order_key(scores[t]) : 0xffffu;
         v[j] = t;
     }
-    Sort().sort(k, v, st);
+    Sort().sort(k, v, st, 0, 16);
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int t = threadIdx.x * ITEMS + j;

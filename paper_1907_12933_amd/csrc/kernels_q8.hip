@@ -48,6 +48,7 @@ __device__ void dense_forward_block(const QNetDev &net, const int *xs, int *act0
         const int q = t % H1, sp = t / H1;
         const int i0 = sp * seg1, i1 = min(n, i0 + seg1);
         int u = 0;
+#pragma unroll 8
         for (int i = i0; i < i1; ++i) u += (int)net.W1T[(int64_t)i * H1 + q] * xs[i];
         part[sp][q] = u;
     }
@@ -75,6 +76,7 @@ __device__ void dense_forward_block(const QNetDev &net, const int *xs, int *act0
             const int i0 = sp * seg, i1 = min(nin, i0 + seg);
             const int8_t *row = W + (int64_t)j * nin;
             int u = 0;
+#pragma unroll 8
             for (int i = i0; i < i1; ++i) u += (int)row[i] * in[i];
             part[sp][j] = u;
         }

@@ -1,6 +1,6 @@
 """GPU parity of the learned proposal network: features against the oracle,
 bf16 MFMA gradients against the FP64 oracle gradients, training, the
-bitonic ordering, and the ordered search keeping the plain verdicts."""
+ordering by score, and the ordered search keeping the plain verdicts."""
 import numpy as np
 import pytest
 
@@ -119,3 +119,38 @@ def test_labels_from_records(ctx, orc):
         pix, dig = orc.decode(30, 4, int(k), int(r))
         exp[pix * 4 + dig] = 1.0
     assert np.array_equal(lab, exp)
+
+
+def _order_from_scores(scores):
+    """Visiting order of the candidates: 16-bit order keys (larger score first), ties by index."""
+    b = scores.astype(np.float32).view(np.uint32).astype(np.uint64)
+    u = np.where(b & 0x80000000, b ^ 0xFFFFFFFF, b | 0x80000000)
+    key = ((~u) & 0xFFFFFFFF) >> 16
+    return np.argsort(key, kind="stable")
+
+
+def test_ranked_order_follows_scores(ctx, orc):
+    """The learned search visits level 1 in score order: its first counterexample's
+    position equals the smallest position, in the order computed here from the
+    proposer's scores, of the oracle's level-1 counterexamples."""
+    from paper_1907_12933_amd import ibmc
+    g = I.rng(47)
+    net = I.random_qnet(g, [64, 64, 64, 10], shift=5, wmax=16, bmax=200)
+    m = ibmc.Mlp(ctx, net)
+    D = np.array([-64, -32, 32, 64], np.int16)
+    prop = ibmc.Proposer(ctx, seed=2)
+    checked = 0
+    for t in range(6):
+        x = g.integers(0, 255, size=64, endpoint=True).astype(np.uint8)
+        ref = orc.q8_check(net, x, D, 1, 1)
+        if not ref["cex_total"]:
+            continue
+        sc = ibmc.ibmc_proposer_score(ctx, prop, m, x, 8, 8, D)
+        order = _order_from_scores(sc)
+        pos_of = np.empty(len(order), np.int64)
+        pos_of[order] = np.arange(len(order))
+        expect = min(int(pos_of[int(r)]) for r in ref["cex_rank"])  # k = 1: rank = pixel * m + delta index
+        s, _ = ibmc.ibmc_check_property_ranked(ctx, m, prop, x, 8, 8, D, 1, 1)
+        assert s["points_before_first"] == expect
+        checked += 1
+    assert checked >= 2
