@@ -301,16 +301,25 @@ __device__ __forceinline__ void rec_finish(RecOut &o, int lane) {
     }
 }
 
-// Record the violations of one 16-point tile (lanes of group 0 carry the
-// points) of segment w in the wave's current block, continuing in a new block
-// when it runs out (a tile holds at most 16 records, a block 64).  einfo:
-// the chunk's packed emission info.
-__device__ __forceinline__ void emit_tile(RecOut &o, int einfo, int w, bool viol, int p, int i, int label, int lane) {
-    const unsigned long long vm = __ballot(viol);
-    if (!vm) return;
+// Record the violations of segment w's NT 16-point tiles (lanes of group 0
+// carry the points) in the wave's current block, continuing in a new block
+// when it runs out (the tiles hold at most 16 NT <= kRecBlock records, so one
+// new block always suffices).  The emission info and the parameter block are
+// read once for all tiles.  einfo: the chunk's packed emission info.
+template <int NT>
+__device__ __forceinline__ void emit_tiles(RecOut &o, int einfo, int w, const bool (&viol)[NT], const int (&p)[NT],
+                                           const int (&i)[NT], const int (&label)[NT], int lane) {
+    static_assert(16 * NT <= kRecBlock, "one block reservation per call");
+    unsigned long long vm[NT];
+    int n = 0;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        vm[nt] = __ballot(viol[nt]);
+        n += __popcll(vm[nt]);
+    }
+    if (!n) return;
     const EnumParams &P = cold_params<EnumParams>();
     const EmitInfo e = einfo_unpack(einfo, w);
-    const int n = __popcll(vm);
     const int64_t room = o.end - o.next;
     int64_t nb = 0;
     if (n > room) {
@@ -330,16 +339,22 @@ __device__ __forceinline__ void emit_tile(RecOut &o, int einfo, int w, bool viol
         }
     }
     rec_tally(o, e.slot, (unsigned)n, 0u, lane);
-    if (viol) {
-        const int t = __popcll(vm & ((1ull << lane) - 1ull));
-        const int64_t idx = t < room ? o.next + t : nb + (t - room);
-        if (idx < P.rec_cap) {
-            DevRec r;
-            r.rank = rank_of(e, p, i);
-            r.prop = e.prop;
-            r.klab = (e.k << 24) | (label & 0xffffff);
-            P.recs[idx] = r;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int before = 0;  // records of the earlier tiles
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        if (viol[nt]) {
+            const int t = before + __popcll(vm[nt] & below);
+            const int64_t idx = t < room ? o.next + t : nb + (t - room);
+            if (idx < P.rec_cap) {
+                DevRec r;
+                r.rank = rank_of(e, p[nt], i[nt]);
+                r.prop = e.prop;
+                r.klab = (e.k << 24) | (label[nt] & 0xffffff);
+                P.recs[idx] = r;
+            }
         }
+        before += __popcll(vm[nt]);
     }
     if (n > room) {
         o.next = nb + (n - room);
@@ -855,6 +870,10 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
             // counterexamples take the full argmax.
             const int tL = label0 & 3;
             const unsigned long long rowL = 0xffffull << (16 * (label0 >> 2));
+            bool mine[NT];
+            int lab[NT];
+            bool anyv = false;
+            unsigned ties = 0;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const v4i z = acco[nt];
@@ -871,17 +890,21 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
                 const unsigned vmask = (unsigned)(__ballot(valid[nt]) & 0xffffull);
                 const unsigned viol16 = fold_groups(beat) & vmask;
                 const unsigned tie16 = fold_groups(eqm) & vmask & ~viol16;
-                unsigned ties = __popc(tie16);
+                ties += __popc(tie16);
+                mine[nt] = false;
+                lab[nt] = 0;
                 if (viol16) {
+                    anyv = true;
                     int bv = INT32_MIN, bi = 0x7fffffff, bc = 0;
                     argmax_tile<false>(z, 0, g, ncls, bv, bi, bc);
                     argmax_combine(bv, bi, bc);
-                    const bool mine = g == 0 && ((viol16 >> j16) & 1u);
-                    ties += (unsigned)__popcll(__ballot(mine && bc > 1));
-                    emit_tile(ro, einfo, w, mine, plast[nt], ilast[nt], bi, lane);
+                    mine[nt] = g == 0 && ((viol16 >> j16) & 1u);
+                    lab[nt] = bi;
+                    ties += (unsigned)__popcll(__ballot(mine[nt] && bc > 1));
                 }
-                if (ties) rec_tally(ro, lane_get(einfo, EI_SLOT), 0u, ties, lane);
             }
+            if (anyv) emit_tiles<NT>(ro, einfo, w, mine, plast, ilast, lab, lane);
+            if (ties) rec_tally(ro, lane_get(einfo, EI_SLOT), 0u, ties, lane);
         } else {
             // ---- general output layer: M-tiles in turn, full lowest-index argmax
             int bestv[NT], besti[NT], bestc[NT];
@@ -906,14 +929,17 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) argmax_tile<true>(acc[nt], mt, g, ncls, bestv[nt], besti[nt], bestc[nt]);
             }
+            bool viol[NT];
+            unsigned ties = 0;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 argmax_combine(bestv[nt], besti[nt], bestc[nt]);
                 const bool mine = valid[nt] && g == 0;
-                const unsigned long long tm = __ballot(mine && bestc[nt] > 1);
-                if (tm) rec_tally(ro, lane_get(einfo, EI_SLOT), 0u, (unsigned)__popcll(tm), lane);
-                emit_tile(ro, einfo, w, mine && besti[nt] != label0, plast[nt], ilast[nt], besti[nt], lane);
+                ties += (unsigned)__popcll(__ballot(mine && bestc[nt] > 1));
+                viol[nt] = mine && besti[nt] != label0;
             }
+            emit_tiles<NT>(ro, einfo, w, viol, plast, ilast, besti, lane);
+            if (ties) rec_tally(ro, lane_get(einfo, EI_SLOT), 0u, ties, lane);
         }
 
         }  // segments of the group
