@@ -879,20 +879,30 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
                 const v4i z = acco[nt];
                 const int zs = tL == 0 ? z[0] : tL == 1 ? z[1] : tL == 2 ? z[2] : z[3];
                 const int zL = row_bcast(zs, label0 >> 2);
-                unsigned long long beat = 0, eqm = 0;
+                // common case first: no other class reaches zL (then the
+                // point is neither a counterexample nor a tie)
+                unsigned long long gem = 0;
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    // z_c beats zL iff z_c > zL - [c < label]
-                    beat |= __ballot(z[t] > zL - ((lowbits >> t) & 1));
-                    const unsigned long long eq = __ballot(z[t] == zL);
-                    eqm |= (t == tL) ? (eq & ~rowL) : eq;
+                    const unsigned long long ge = __ballot(z[t] >= zL);
+                    gem |= (t == tL) ? (ge & ~rowL) : ge;
                 }
                 const unsigned vmask = (unsigned)(__ballot(valid[nt]) & 0xffffull);
-                const unsigned viol16 = fold_groups(beat) & vmask;
-                const unsigned tie16 = fold_groups(eqm) & vmask & ~viol16;
-                ties += __popc(tie16);
+                unsigned viol16 = 0;
                 mine[nt] = false;
                 lab[nt] = 0;
+                if (fold_groups(gem) & vmask) {
+                    unsigned long long beat = 0, eqm = 0;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        // z_c beats zL iff z_c > zL - [c < label]
+                        beat |= __ballot(z[t] > zL - ((lowbits >> t) & 1));
+                        const unsigned long long eq = __ballot(z[t] == zL);
+                        eqm |= (t == tL) ? (eq & ~rowL) : eq;
+                    }
+                    viol16 = fold_groups(beat) & vmask;
+                    ties += __popc(fold_groups(eqm) & vmask & ~viol16);
+                }
                 if (viol16) {
                     anyv = true;
                     int bv = INT32_MIN, bi = 0x7fffffff, bc = 0;
