@@ -605,7 +605,7 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
 
     // state of the chunk at the cursor (prepared a chunk ahead)
     int label_n = -1, lowbits_n = 0, prop_n = -1;
-    bool valid_n[NT];
+    int valid_n[NT];  // 0 / 1 per lane, held in a VGPR (a lane mask would take two scalar registers)
     int plast_n[NT], ilast_n[NT];
     L1Loads<KB1, NT> ld;
     // segment set-up when needed (the group's bases in LDS slots, its
@@ -637,8 +637,10 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
         einfo_n = lane_put(einfo_n, EI_GCHI, (int)(c.chunk >> 32));
         const int obase = (int)c.ch * CH;
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-            valid_n[nt] = last_element32(c, Q, obase + nt * 16 + j16, plast_n[nt], ilast_n[nt]);
+        for (int nt = 0; nt < NT; ++nt) {
+            valid_n[nt] = last_element32(c, Q, obase + nt * 16 + j16, plast_n[nt], ilast_n[nt]) ? 1 : 0;
+            asm volatile("" : "+v"(valid_n[nt]));
+        }
         layer1_issue<KB1, NT>(c, Q.net, Q.packed != 0, plast_n, ilast_n, g, ld);
     };
 
@@ -676,7 +678,7 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
         const int einfo = einfo_n;
         const int label0 = label_n, lowbits = lowbits_n;
         const int nw = nw_n;
-        bool valid[NT];
+        int valid[NT];
         int plast[NT], ilast[NT], ev[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
@@ -868,8 +870,13 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
             // z_c == zL with c < label (padding classes sit at INT32_MIN); it is
             // an exact tie iff another class reaches zL.  Tiles with
             // counterexamples take the full argmax.
-            const int tL = label0 & 3;
-            const unsigned long long rowL = 0xffffull << (16 * (label0 >> 2));
+            // label-derived masks recomputed here with scalar ops (an opaque
+            // copy of the label keeps the compiler from hoisting them out of
+            // the loop, where they would only add to the scalar spills)
+            int labv = label0;
+            asm volatile("" : "+s"(labv));
+            const int tL = labv & 3;
+            const unsigned long long rowL = 0xffffull << (16 * (labv >> 2));
             bool mine[NT];
             int lab[NT];
             bool anyv = false;
@@ -878,7 +885,7 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
             for (int nt = 0; nt < NT; ++nt) {
                 const v4i z = acco[nt];
                 const int zs = tL == 0 ? z[0] : tL == 1 ? z[1] : tL == 2 ? z[2] : z[3];
-                const int zL = row_bcast(zs, label0 >> 2);
+                const int zL = row_bcast(zs, labv >> 2);
                 // common case first: no other class reaches zL (then the
                 // point is neither a counterexample nor a tie)
                 unsigned long long gem = 0;
@@ -887,7 +894,7 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
                     const unsigned long long ge = __ballot(z[t] >= zL);
                     gem |= (t == tL) ? (ge & ~rowL) : ge;
                 }
-                const unsigned vmask = (unsigned)(__ballot(valid[nt]) & 0xffffull);
+                const unsigned vmask = (unsigned)(__ballot(valid[nt] != 0) & 0xffffull);
                 unsigned viol16 = 0;
                 mine[nt] = false;
                 lab[nt] = 0;
@@ -944,7 +951,7 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 argmax_combine(bestv[nt], besti[nt], bestc[nt]);
-                const bool mine = valid[nt] && g == 0;
+                const bool mine = valid[nt] != 0 && g == 0;
                 ties += (unsigned)__popcll(__ballot(mine && bestc[nt] > 1));
                 viol[nt] = mine && besti[nt] != label0;
             }
