@@ -3,6 +3,8 @@
 Integer work is compared bit for bit: clean label, per-level point /
 counterexample / exact-tie counts, and the sorted (k, rank, new label)
 records."""
+import json
+
 import numpy as np
 import pytest
 
@@ -202,3 +204,28 @@ def test_general_first_layer_path(orc, monkeypatch):
         x2 = g.integers(0, 255, size=40, endpoint=True).astype(np.uint8)
         s, cex, _ = ibmc.ibmc_check_property(ctx, m2, x2, D2, 1, 2)
         assert_same(s, cex, orc.q8_check(net2, x2, D2, 1, 2))
+
+
+def test_fast_epilogue_headroom_gate(ctx, orc):
+    """Layer-2 shift 7 selects the fast hidden epilogue only while every
+    partial sum of its offset accumulators fits int32: a net whose layer-2
+    bias is too large for it takes the general epilogue, with the same
+    records as the oracle."""
+    from paper_1907_12933_amd import ibmc
+    g = I.rng(161)
+    net = I.random_qnet(g, [40, 64, 64, 6], shift=7, wmax=40, bmax=300)
+    fast = ibmc.Mlp(ctx, net)
+    big = I.random_qnet(I.rng(161), [40, 64, 64, 6], shift=7, wmax=40, bmax=300)
+    big.b[1] = big.b[1].copy()
+    big.b[1][3] = np.int32(1_100_000_000)    # alpha * (b + 256 sum|W|) + 32768 >= 2^31
+    big.b[1][5] = np.int32(-1_100_000_000)
+    slow = ibmc.Mlp(ctx, big)
+    shape_fast = json.loads(ibmc.ibmc_autotune(ctx, fast, k=1, n_deltas=2))["shape"]
+    shape_slow = json.loads(ibmc.ibmc_autotune(ctx, slow, k=1, n_deltas=2))["shape"]
+    assert shape_fast.endswith("_f") and not shape_slow.endswith("_f")
+    D = np.array([-60, -30, 30, 60], np.int16)
+    for t in range(2):
+        x = g.integers(0, 255, size=40, endpoint=True).astype(np.uint8)
+        for net_, m in ((net, fast), (big, slow)):
+            s, cex, _ = ibmc.ibmc_check_property(ctx, m, x, D, 0, 2)
+            assert_same(s, cex, orc.q8_check(net_, x, D, 0, 2))
