@@ -1,6 +1,7 @@
 // Coverage kernels (the SS / DS / SV / DV neuron-pair covers):
 //  1. fwd_pots_q8_kernel: every layer's exact potentials of a batch of
-//     images on int8 MFMA (natural K order; activations staged in LDS);
+//     images on int8 MFMA (natural K order; activations staged in LDS, the
+//     output tiles split over a workgroup's waves);
 //  2. cov_pred_kernel: per input pair, sign / value change masks of every
 //     layer as wavefront ballots, sign-change counts by popcount, the layer
 //     distance, then the covered rows OR-ed into device bitmasks;
@@ -14,7 +15,9 @@ namespace ibmc {
 // 1. forward potentials
 // ---------------------------------------------------------------------------
 
-constexpr int kFwdTile = 16;                  // images per wave (one MFMA N-tile)
+constexpr int kFwdTile = 16;                  // images per workgroup (one MFMA N-tile)
+constexpr int kFwdWaves = 16;                 // waves per workgroup: they split every layer's output tiles
+constexpr int kFwdAB = 4;                     // weight tiles loaded ahead of their MFMAs
 
 __device__ __forceinline__ int fwd_requant_byte(int acc_minus_off, int s) {
     // acc - 64 * 2^s -> a - 64 with a = clamp(floor(u / 2^s), 0, 127)
@@ -23,20 +26,25 @@ __device__ __forceinline__ int fwd_requant_byte(int acc_minus_off, int s) {
     return (v >> s) & 0xff;
 }
 
-// One wave (64 threads) per 16 images.  LDS: two activation buffers of
-// 16 x 1024 int8 (the offset form a - 64; the input layer holds x - 128).
-__global__ void __launch_bounds__(64) fwd_pots_q8_kernel(QNetDev net, FwdExtra fx, const uint8_t *images,
-                                                         int64_t n_images, int32_t *pots, int64_t pot_stride,
-                                                         int32_t *labels) {
+// One workgroup of kFwdWaves waves per 16 images; wave w computes the
+// 16-row output tiles w, w + kFwdWaves, ... of every layer (K-blocks in
+// groups of kFwdAB: the group's weight tiles are loaded first, then chained
+// through the MFMAs).  LDS: two activation buffers of 16 x 1024 int8 (the
+// offset form a - 64; the input layer holds x - 128), and the per-wave label
+// candidates.
+__global__ void __launch_bounds__(64 * kFwdWaves) fwd_pots_q8_kernel(QNetDev net, FwdExtra fx, const uint8_t *images,
+                                                                     int64_t n_images, int32_t *pots,
+                                                                     int64_t pot_stride, int32_t *labels) {
     __shared__ __attribute__((aligned(16))) int8_t act[2][kFwdTile][kMaxWidth];
-    const int lane = threadIdx.x;
+    __shared__ int candv[kFwdWaves][kFwdTile], candi[kFwdWaves][kFwdTile];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int j16 = lane & 15, g = lane >> 4;
     const int n = net.dims[0];
     const int K0 = fx.K0;                      // pixels padded to 64
     for (int64_t tile = blockIdx.x; tile * kFwdTile < n_images; tile += gridDim.x) {
         const int64_t img0 = tile * kFwdTile;
         // stage x - 128 (zero padding beyond n and beyond the last image)
-        for (int t = lane; t < kFwdTile * K0; t += 64) {
+        for (int t = threadIdx.x; t < kFwdTile * K0; t += blockDim.x) {
             const int jj = t / K0, pix = t - jj * K0;
             const int64_t img = img0 + jj;
             int8_t v = 0;
@@ -57,14 +65,22 @@ __global__ void __launch_bounds__(64) fwd_pots_q8_kernel(QNetDev net, FwdExtra f
             const int s = hidden ? net.shift[l - 1] : 0;
             const int off = hidden ? (64 << s) : 0;
             const int nout = net.dims[l];
-            for (int mt = 0; mt < MT; ++mt) {
+            for (int mt = wave; mt < MT; mt += kFwdWaves) {
                 const int4 b = *reinterpret_cast<const int4 *>(init + mt * 16 + g * 4);
                 v4i acc = {b.x, b.y, b.z, b.w};
                 const v4i *Ap = reinterpret_cast<const v4i *>(tiles) + (int64_t)mt * KB * 64 + lane;
-                for (int kb = 0; kb < KB; ++kb) {
-                    const v4i A = Ap[kb * 64];
-                    const v4i B = *reinterpret_cast<const v4i *>(&act[cur][j16][kb * 64 + g * 16]);
-                    acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A, B, acc, 0, 0, 0);
+                for (int k0 = 0; k0 < KB; k0 += kFwdAB) {
+                    v4i A[kFwdAB];
+#pragma unroll
+                    for (int z = 0; z < kFwdAB; ++z)
+                        if (k0 + z < KB) A[z] = Ap[(k0 + z) * 64];
+#pragma unroll
+                    for (int z = 0; z < kFwdAB; ++z) {
+                        if (k0 + z < KB) {
+                            const v4i B = *reinterpret_cast<const v4i *>(&act[cur][j16][(k0 + z) * 64 + g * 16]);
+                            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[z], B, acc, 0, 0, 0);
+                        }
+                    }
                 }
                 // potentials of neurons 16 mt + 4 g + t for image j16
 #pragma unroll
@@ -90,14 +106,26 @@ __global__ void __launch_bounds__(64) fwd_pots_q8_kernel(QNetDev net, FwdExtra f
             __syncthreads();
             cur ^= 1;
         }
-        // label: combine the four lane groups of each image
+        // label: the four lane groups of each image, then the waves
 #pragma unroll
         for (int sh = 16; sh <= 32; sh <<= 1) {
             const int ov = __shfl_xor(bestv, sh), oi = __shfl_xor(besti, sh);
             if (ov > bestv) { bestv = ov; besti = oi; }
             else if (ov == bestv) besti = min(besti, oi);
         }
-        if (labels && g == 0 && myimg < n_images) labels[myimg] = besti;
+        if (g == 0) {
+            candv[wave][j16] = bestv;
+            candi[wave][j16] = besti;
+        }
+        __syncthreads();
+        if (wave == 0 && g == 0) {
+            for (int w = 1; w < kFwdWaves; ++w) {
+                const int ov = candv[w][j16], oi = candi[w][j16];
+                if (ov > bestv) { bestv = ov; besti = oi; }
+                else if (ov == bestv) besti = min(besti, oi);
+            }
+            if (labels && myimg < n_images) labels[myimg] = besti;
+        }
         __syncthreads();
     }
 }
@@ -110,6 +138,8 @@ __device__ __forceinline__ unsigned long long sat_add_u64(unsigned long long a, 
     const unsigned long long s = a + b;
     return s < a ? ~0ull : s;
 }
+
+constexpr int kPredAB = 4;   // 64-neuron chunks whose potentials are loaded ahead of their tests
 
 template <class T>
 __global__ void __launch_bounds__(64) cov_pred_kernel(const T *pots1, const T *pots2, int64_t n_pairs,
@@ -124,38 +154,50 @@ __global__ void __launch_bounds__(64) cov_pred_kernel(const T *pots1, const T *p
             const int w = lay.width[l];
             const T *x = a1 + lay.uoff[l], *y = a2 + lay.uoff[l];
             int count = 0, first = -1;
-            unsigned long long dist = 0;
-            for (int c0 = 0; c0 < w; c0 += 64) {
-                const int i = c0 + lane;
-                bool sc = false, vc = false;
-                unsigned long long d2 = 0;
-                if (i < w) {
-                    const int64_t a = (int64_t)x[i], b = (int64_t)y[i];
-                    const bool sa = a >= 0, sb = b >= 0;   // sign(0) = 1
-                    sc = sa != sb;
-                    const int64_t aa = a < 0 ? -a : a, bb = b < 0 ? -b : b;
-                    const int64_t mx = aa > bb ? aa : bb, mn = aa > bb ? bb : aa;
-                    vc = !sc && mx > 0 && (int64_t)cp.ratio_den * mx >= (int64_t)cp.ratio_num * mn;
-                    const int64_t d = a - b;
-                    const unsigned long long ad = (unsigned long long)(d < 0 ? -d : d);
-                    // |d| < 2^32 for int32 potentials; larger (int64 input) saturates
-                    d2 = (ad >> 32) ? ~0ull : ad * ad;
-                }
-                const unsigned long long sm = __ballot(sc), vm = __ballot(vc);
-                if (lane == 0) {
-                    scm[l][c0 / 32] = (uint32_t)sm;
-                    vcm[l][c0 / 32] = (uint32_t)vm;
-                    if (c0 + 32 < kMaxWidth) {
-                        scm[l][c0 / 32 + 1] = (uint32_t)(sm >> 32);
-                        vcm[l][c0 / 32 + 1] = (uint32_t)(vm >> 32);
-                    }
-                }
-                if (sm && first < 0) first = c0 + __ffsll((long long)sm) - 1;
-                count += __popcll(sm);
+            unsigned long long dist = 0;           // this lane's share (saturating sums are associative)
+            for (int c1 = 0; c1 < w; c1 += 64 * kPredAB) {
+                T xv[kPredAB], yv[kPredAB];
 #pragma unroll
-                for (int sh = 32; sh >= 1; sh >>= 1) d2 = sat_add_u64(d2, __shfl_xor(d2, sh));
-                dist = sat_add_u64(dist, d2);
+                for (int z = 0; z < kPredAB; ++z) {
+                    const int i = c1 + 64 * z + lane;
+                    xv[z] = i < w ? x[i] : T(0);
+                    yv[z] = i < w ? y[i] : T(0);
+                }
+#pragma unroll
+                for (int z = 0; z < kPredAB; ++z) {
+                    const int c0 = c1 + 64 * z;
+                    if (c0 >= w) break;
+                    const int i = c0 + lane;
+                    bool sc = false, vc = false;
+                    unsigned long long d2 = 0;
+                    if (i < w) {
+                        const int64_t a = (int64_t)xv[z], b = (int64_t)yv[z];
+                        const bool sa = a >= 0, sb = b >= 0;   // sign(0) = 1
+                        sc = sa != sb;
+                        const int64_t aa = a < 0 ? -a : a, bb = b < 0 ? -b : b;
+                        const int64_t mx = aa > bb ? aa : bb, mn = aa > bb ? bb : aa;
+                        vc = !sc && mx > 0 && (int64_t)cp.ratio_den * mx >= (int64_t)cp.ratio_num * mn;
+                        const int64_t d = a - b;
+                        const unsigned long long ad = (unsigned long long)(d < 0 ? -d : d);
+                        // |d| < 2^32 for int32 potentials; larger (int64 input) saturates
+                        d2 = (ad >> 32) ? ~0ull : ad * ad;
+                    }
+                    const unsigned long long sm = __ballot(sc), vm = __ballot(vc);
+                    if (lane == 0) {
+                        scm[l][c0 / 32] = (uint32_t)sm;
+                        vcm[l][c0 / 32] = (uint32_t)vm;
+                        if (c0 + 32 < kMaxWidth) {
+                            scm[l][c0 / 32 + 1] = (uint32_t)(sm >> 32);
+                            vcm[l][c0 / 32 + 1] = (uint32_t)(vm >> 32);
+                        }
+                    }
+                    if (sm && first < 0) first = c0 + __ffsll((long long)sm) - 1;
+                    count += __popcll(sm);
+                    dist = sat_add_u64(dist, d2);
+                }
             }
+#pragma unroll
+            for (int sh = 32; sh >= 1; sh >>= 1) dist = sat_add_u64(dist, __shfl_xor(dist, sh));
             nsc[l] = count;
             istar[l] = first;
             dc[l] = count == 0 && dist >= (unsigned long long)cp.dist_sq_min;
@@ -189,30 +231,37 @@ __global__ void __launch_bounds__(64) cov_pred_kernel(const T *pots1, const T *p
 // 3. summaries and the caller's bit layout
 // ---------------------------------------------------------------------------
 
-// grid: (rows of block l, criterion).  For SS / SV: per row, any bit ->
-// condition neuron covered, OR into the column mask, count bits.  For DS /
-// DV the block is "all rows x allrows-mask".
+// grid: (groups of kSumRows rows of block l, criterion).  For SS / SV: per
+// row, any bit -> condition neuron covered, OR into the column mask, count
+// bits.  For DS / DV the block is "all rows x allrows-mask".  A row holds at
+// most kMaxWidth / 32 words, one per lane; each lane ORs its column over the
+// group's rows and touches the shared column mask once.
+constexpr int kSumRows = 8;
+static_assert(kMaxWidth / 32 <= 64, "one mask word per lane");
+
 __global__ void __launch_bounds__(64) cov_sum_kernel(CovLayout lay, CovBits bits, int l, CovSums sums) {
-    const int row = blockIdx.x, crit = blockIdx.y;   // crit: 0 SS, 1 DS, 2 SV, 3 DV
+    const int crit = blockIdx.y;   // 0 SS, 1 DS, 2 SV, 3 DV
+    const bool per_row = crit == 0 || crit == 2;
     const int W = lay.words[l + 1];
+    const int rows = lay.width[l];
     const int lane = threadIdx.x;
-    const uint32_t *src;
-    if (crit == 0 || crit == 2) src = (crit == 0 ? bits.rows_ss : bits.rows_sv) + lay.rowoff[l] + (int64_t)row * W;
-    else src = (crit == 1 ? bits.all_ds : bits.all_dv) + lay.alloff[l];
+    const int r0 = blockIdx.x * kSumRows;
     int cnt = 0;
-    bool any = false;
-    for (int t = lane; t < W; t += 64) {
-        const uint32_t v = src[t];
+    uint32_t col = 0;
+    for (int rr = 0; rr < kSumRows && r0 + rr < rows; ++rr) {
+        const int row = r0 + rr;
+        const uint32_t *src = per_row
+                                  ? (crit == 0 ? bits.rows_ss : bits.rows_sv) + lay.rowoff[l] + (int64_t)row * W
+                                  : (crit == 1 ? bits.all_ds : bits.all_dv) + lay.alloff[l];
+        const uint32_t v = lane < W ? src[lane] : 0u;
         cnt += __popc(v);
-        any |= v != 0;
-        if (v && (crit == 0 || crit == 2 || row == 0)) atomicOr(sums.colmask + (int64_t)crit * sums.colmask_stride + lay.alloff[l] + t, v);
+        col |= v;
+        if (__ballot(v != 0) && lane == 0) sums.condflag[(int64_t)crit * sums.flag_stride + lay.uoff[l] + row] = 1;
     }
+    if (col && (per_row || blockIdx.x == 0))
+        atomicOr(sums.colmask + (int64_t)crit * sums.colmask_stride + lay.alloff[l] + lane, col);
     for (int sh = 32; sh >= 1; sh >>= 1) cnt += __shfl_xor(cnt, sh);
-    const bool anyw = __ballot(any) != 0;
-    if (lane == 0) {
-        if (cnt) atomicAdd(sums.pairs + crit, (unsigned long long)cnt);
-        if (anyw) sums.condflag[(int64_t)crit * sums.flag_stride + lay.uoff[l] + row] = 1;
-    }
+    if (lane == 0 && cnt) atomicAdd(sums.pairs + crit, (unsigned long long)cnt);
 }
 
 // Neuron count per criterion: condition flags OR decision bits of the
@@ -269,8 +318,8 @@ hipError_t launch_fwd_pots_q8(const QNetDev &net, const FwdExtra &fx, const uint
     if (n_images <= 0) return hipSuccess;
     const int64_t tiles = (n_images + kFwdTile - 1) / kFwdTile;
     const int grid = (int)std::min<int64_t>(tiles, 8192);
-    hipLaunchKernelGGL(fwd_pots_q8_kernel, dim3(grid), dim3(64), 0, s, net, fx, images, n_images, pots, pot_stride,
-                       labels);
+    hipLaunchKernelGGL(fwd_pots_q8_kernel, dim3(grid), dim3(64 * kFwdWaves), 0, s, net, fx, images, n_images, pots,
+                       pot_stride, labels);
     return hipGetLastError();
 }
 
@@ -292,7 +341,8 @@ hipError_t launch_cov_pred_i64(const int64_t *p1, const int64_t *p2, int64_t n_p
 
 hipError_t launch_cov_summary(const CovLayout &lay, const CovBits &bits, const CovSums &sums, hipStream_t s) {
     for (int l = 0; l + 1 < lay.nl; ++l) {
-        hipLaunchKernelGGL(cov_sum_kernel, dim3(lay.width[l], 4), dim3(64), 0, s, lay, bits, l, sums);
+        hipLaunchKernelGGL(cov_sum_kernel, dim3((lay.width[l] + kSumRows - 1) / kSumRows, 4), dim3(64), 0, s, lay,
+                           bits, l, sums);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
