@@ -126,6 +126,18 @@ def proposer_leg(ctx, ibmc, inputs, w, net, recs, args):
         out["ttfc_learned_total_s"] = float(sum(r[3] for r in unsafe))
         out["points_before_first_plain_total"] = int(sum(r[4] for r in unsafe))
         out["points_before_first_learned_total"] = int(sum(r[5] for r in unsafe))
+        # The first round of the persistent grid (two workgroups of four waves
+        # per CU, one 64-point chunk each) is visited at once, so the order
+        # only decides the time of first hits that lie beyond it.
+        n_cu = ctx.device_info()[0]
+        round_pts = n_cu * 2 * 4 * 64
+        late = [r for r in unsafe if r[4] >= round_pts]
+        out["first_round_points"] = int(round_pts)
+        out["late_images"] = len(late)
+        if late:
+            out["ttfc_plain_late_median_s"] = med([r[2] for r in late])
+            out["ttfc_learned_late_median_s"] = med([r[3] for r in late])
+            out["ttfc_late_speedup_median"] = med([r[2] / r[3] for r in late if r[3] > 0])
     return out
 
 

@@ -574,7 +574,10 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
         uhi = a1v >= 0 ? (a1v + f - 1) / f : -((-a1v) / f);  // ceil(a1v / f)
     }
 
-    // ---- work distribution: batches of chunks from the global queue; the
+    // ---- work distribution: tickets from the global queue, each a single
+    // chunk at first (the visiting order stays fine where an ordered search
+    // meets its first counterexample), then batches of contiguous chunks
+    // (one queue atomic, one cursor decode and one base per batch); the
     // cursor always describes the chunk whose first-layer loads are in
     // flight.  Between chunks it rests in the wave's LDS record (read back
     // and written once per chunk), so that none of its fields holds
@@ -589,15 +592,16 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
             seg = cursor_next<CH, EnumParams>(c, Q);
             return true;
         }
-        unsigned long long start = 0;
-        if (lane == 0) start = atomicAdd(Q.queue, (unsigned long long)Q.batch);
-        start = wave_uniform(start);  // lane 0's value
-        if ((int64_t)start >= Q.total_chunks) return false;
+        unsigned long long ticket = 0;
+        if (lane == 0) ticket = atomicAdd(Q.queue, 1ull);
+        const int64_t t = (int64_t)wave_uniform(ticket);  // lane 0's value
+        const int64_t start = t < Q.single ? t : Q.single + (t - Q.single) * Q.batch;
+        if (start >= Q.total_chunks) return false;
         if (wave_uniform(*Q.stop_flag)) return false;
         // host-mapped: poll sparsely
         if (Q.abort_host && (fetches++ & 15) == 0 && wave_uniform(*Q.abort_host)) return false;
-        cur_chunk = (int64_t)start;
-        end_chunk = min((int64_t)start + Q.batch, Q.total_chunks);
+        cur_chunk = start;
+        end_chunk = min(start + (t < Q.single ? 1 : (int64_t)Q.batch), Q.total_chunks);
         cursor_decode<CH, EnumParams>(c, Q, cur_chunk);
         seg = true;
         return true;

@@ -727,15 +727,9 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
     // property
     PropDev pd;
     memset(&pd, 0, sizeof(pd));
-    IBMC_TRY(ctx->images.upload(image, n, s));
-    pd.image = ctx->images.as<uint8_t>();
     pd.m = m;
     pd.n = n;
     for (int i = 0; i < m; ++i) pd.deltas[i] = deltas[i];
-    IBMC_TRY(ctx->props.upload(&pd, sizeof(pd), s));
-    const int32_t zero = 0;
-    IBMC_TRY(ctx->prop_ids.upload(&zero, 4, s));
-    IBMC_TRY(ctx->u0_index.upload(&zero, 4, s));
     IBMC_TRY(ctx->u0.reserve((size_t)net->qd.H[1] * 4));
     std::vector<int32_t> order;
     // jobs: one per level >= 1
@@ -791,22 +785,53 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
     const int64_t grid = std::min<int64_t>((int64_t)ctx->n_cu * occ, std::max<int64_t>(1, total));
     const int64_t rec_slots = cap + grid * 4 * kRecBlock;
     IBMC_TRY(ctx->recs.reserve((size_t)std::max<int64_t>(rec_slots, 1) * sizeof(DevRec)));
-    if (!qc.empty()) IBMC_TRY(ctx->qcum.upload(qc.data(), qc.size() * 8, s));
     if (!scum.empty()) {
         IBMC_TRY(ctx->shell_cum.upload(scum.data(), scum.size() * 8, s));
         ctx->shell_cum_n = N1;
         ctx->shell_cum_ch = CH;
     }
     if (p) IBMC_TRY(ctx->order.reserve((size_t)N1 * 4));
+    // the per-call inputs in one copy from pinned memory:
+    // image | property | property id 0 | u0 index 0 | jobs | plain prefix table
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t o_pd = al((size_t)n), o_ids = o_pd + al(sizeof(PropDev)), o_u0i = o_ids + 256, o_jobs = o_u0i + 256;
+    const size_t o_qc = o_jobs + al(jobs.size() * sizeof(EnumJob)), stage_n = o_qc + qc.size() * 8;
+    if (ctx->stage_pending) HIP_OK(hipEventSynchronize(ctx->stage_ev));  // the previous copy has read the staging
+    ctx->stage_pending = false;
+    if (ctx->stage_host_bytes < stage_n) {
+        if (ctx->stage_host) HIP_OK(hipHostFree(ctx->stage_host));
+        ctx->stage_host = nullptr;
+        ctx->stage_host_bytes = 0;
+        const size_t want = std::max<size_t>(stage_n, 64 << 10);
+        void *hp = nullptr;
+        HIP_OK(hipHostMalloc(&hp, want, hipHostMallocDefault));
+        ctx->stage_host = reinterpret_cast<char *>(hp);
+        ctx->stage_host_bytes = want;
+    }
+    IBMC_TRY(ctx->stage_dev.reserve(stage_n));
+    char *const SH = ctx->stage_host;
+    char *const SD = ctx->stage_dev.as<char>();
+    PropDev *const d_props = reinterpret_cast<PropDev *>(SD + o_pd);
+    const int32_t *const d_ids = reinterpret_cast<const int32_t *>(SD + o_ids);
+    const int32_t *const d_u0i = reinterpret_cast<const int32_t *>(SD + o_u0i);
+    pd.image = reinterpret_cast<const uint8_t *>(SD);
     for (auto &J : jobs) {
-        J.qcum = (J.mode == SEG_PLAIN && J.k >= 2) ? ctx->qcum.as<int64_t>() : nullptr;
+        J.qcum = (J.mode == SEG_PLAIN && J.k >= 2) ? reinterpret_cast<const int64_t *>(SD + o_qc) : nullptr;
         J.order = p ? ctx->order.as<int32_t>() : nullptr;
         J.shell_cum = (J.mode == SEG_SHELL) ? ctx->shell_cum.as<int64_t>() : nullptr;
     }
-    if (!jobs.empty()) IBMC_TRY(ctx->jobs.upload(jobs.data(), jobs.size() * sizeof(EnumJob), s));
+    memcpy(SH, image, (size_t)n);
+    memcpy(SH + o_pd, &pd, sizeof(pd));
+    memset(SH + o_ids, 0, 4);
+    memset(SH + o_u0i, 0, 4);
+    if (!jobs.empty()) memcpy(SH + o_jobs, jobs.data(), jobs.size() * sizeof(EnumJob));
+    if (!qc.empty()) memcpy(SH + o_qc, qc.data(), qc.size() * 8);
+    HIP_OK(hipMemcpyAsync(SD, SH, stage_n, hipMemcpyHostToDevice, s));
+    HIP_OK(hipEventRecord(ctx->stage_ev, s));
+    ctx->stage_pending = true;
     // every upload is done: the clean pass, the proposer's ordering and the
     // enumeration are queued back to back, with no host wait in between
-    HIP_OK(launch_clean_q8(net->qd, ctx->props.as<PropDev>(), ctx->prop_ids.as<int32_t>(), 1, ctx->u0.as<int32_t>(),
+    HIP_OK(launch_clean_q8(net->qd, d_props, d_ids, 1, ctx->u0.as<int32_t>(),
                            net->qd.H[1], s));
     // order of the candidates
     if (p) {
@@ -832,11 +857,16 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
     if (!jobs.empty() && total > 0) {
         EnumParams P{};
         P.net = net->qd;
-        P.jobs = ctx->jobs.as<EnumJob>();
+        P.jobs = reinterpret_cast<const EnumJob *>(SD + o_jobs);
         P.n_jobs = (int32_t)jobs.size();
         P.total_chunks = total;
-        P.batch = 1;                                   // visit in order
-        P.props = ctx->props.as<PropDev>();
+        // visit in order: the first four tickets of every wave are single
+        // chunks (the early positions, where a first counterexample usually
+        // sits, are visited one chunk at a time), later tickets contiguous
+        // batches (the same size rule as the unordered search)
+        P.single = std::min<int64_t>(total, grid * 4 * 4);
+        P.batch = (int32_t)std::max<int64_t>(1, std::min<int64_t>(16, (total - P.single) / (grid * 32)));
+        P.props = d_props;
         P.queue = ctr + 0;
         P.rec_count = ctr + 1;
         P.first_chunk = ctr + 2;
@@ -856,7 +886,7 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
         P.vb_lo = (int32_t)(-16385 - M2);
         P.vb_hi = (int32_t)(16384 + M2);
         HIP_OK(hipEventRecord(ctx->ek0, s));
-        HIP_OK(launch_enum_q8(*v, (int)grid, P, ctx->u0.as<int32_t>(), net->qd.H[1], ctx->u0_index.as<int32_t>(), s));
+        HIP_OK(launch_enum_q8(*v, (int)grid, P, ctx->u0.as<int32_t>(), net->qd.H[1], d_u0i, s));
         HIP_OK(hipEventRecord(ctx->ek1, s));
         // watch the host-mapped first-hit flag while the kernel runs
         while (true) {
@@ -875,7 +905,7 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
     }
     HIP_OK(hipMemcpyAsync(h.data(), ctr, n_ctr * 8, hipMemcpyDeviceToHost, s));
     PropDev back;
-    HIP_OK(hipMemcpyAsync(&back, ctx->props.p, sizeof(back), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(&back, d_props, sizeof(back), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     rec_total = 0;
     for (int li = 0; li < n_slots; ++li) rec_total += (int64_t)h[8 + li];

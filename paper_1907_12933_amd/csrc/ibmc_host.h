@@ -67,6 +67,13 @@ struct ibmc_ctx {
     ibmc::DevBuf recout;  // sorted records in the public layout, on their way to a host buffer
     ibmc::DevBuf prop_scratch, prop_feat, prop_scores, shell_cum;  // ranked search
     int64_t shell_cum_n = -1, shell_cum_ch = -1;                   // shell_cum holds this plan
+    // a ranked search's per-call inputs, packed in pinned host memory and sent
+    // to stage_dev in one copy; stage_ev marks that copy's completion
+    char *stage_host = nullptr;
+    size_t stage_host_bytes = 0;
+    ibmc::DevBuf stage_dev;
+    hipEvent_t stage_ev = nullptr;
+    bool stage_pending = false;
     ibmc::DevBuf cov_img, cov_pots, cov_bits, cov_sums, cov_out;
     // tuned kernel variant per network shape key
     std::map<std::string, std::string> tuned;

@@ -108,6 +108,7 @@ extern "C" ibmc_status ibmc_ctx_create(int32_t device, void *hip_stream, ibmc_ct
     HIP_OK(hipEventCreate(&c->ev1));
     HIP_OK(hipEventCreate(&c->ek0));
     HIP_OK(hipEventCreate(&c->ek1));
+    HIP_OK(hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming));
     void *hm = nullptr;
     HIP_OK(hipHostMalloc(&hm, 64, hipHostMallocMapped));
     c->flags_host = reinterpret_cast<int32_t *>(hm);
@@ -128,6 +129,8 @@ ibmc_ctx::~ibmc_ctx() {
     if (ek0) (void)hipEventDestroy(ek0);
     if (ek1) (void)hipEventDestroy(ek1);
     if (flags_host) (void)hipHostFree(flags_host);
+    if (stage_host) (void)hipHostFree(stage_host);
+    if (stage_ev) (void)hipEventDestroy(stage_ev);
     for (hipStream_t st : side) (void)hipStreamDestroy(st);
     for (hipEvent_t ev : side_ev) (void)hipEventDestroy(ev);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
