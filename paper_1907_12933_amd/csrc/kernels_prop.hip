@@ -1,7 +1,7 @@
 // Learned proposal network: candidate features, bf16 MFMA forward (scoring),
-// fused forward/backward with the weight gradient on bf16 MFMA, Adam, a
-// single-workgroup sort of the scores (radix, or bitonic above 8192
-// candidates), and candidate labels from counterexample records.
+// fused forward/backward with the weight gradient on bf16 MFMA, Adam, the
+// candidates' order by score (a stable counting rank over the whole chip),
+// and candidate labels from counterexample records.
 //
 // Network: s = w2 . relu(W1 f + b1) + c with f in R^32, hidden 128.
 // v_mfma_f32_16x16x32_bf16, orientation out[hidden x samples] = W1 x F^T:
@@ -9,8 +9,6 @@
 // samples; the accumulator leaves lane (j + 16 g) with hidden 4g..4g+3 of
 // sample j.
 #include "kernels_prop.h"
-
-#include <rocprim/block/block_radix_sort.hpp>
 
 namespace ibmc {
 
@@ -298,7 +296,7 @@ __global__ void __launch_bounds__(256) prop_adam_kernel(float *theta, float *gra
 }
 
 // ---------------------------------------------------------------------------
-// ordering: bitonic sort of (score desc, id asc) in one workgroup's LDS
+// ordering: score descending, ties by candidate index
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ unsigned order_key(float s) {
@@ -310,49 +308,56 @@ __device__ __forceinline__ unsigned order_key(float s) {
     return (~u) >> 16;
 }
 
-__global__ void __launch_bounds__(1024) prop_sort_kernel(const float *scores, int N, int32_t *order) {
-    extern __shared__ unsigned long long keys[];
-    int P2 = 1;
-    while (P2 < N) P2 <<= 1;
-    for (int t = threadIdx.x; t < P2; t += blockDim.x)
-        keys[t] = t < N ? ((unsigned long long)order_key(scores[t]) << 32) | (unsigned)t : ~0ull;
-    __syncthreads();
-    for (int k = 2; k <= P2; k <<= 1) {
-        for (int jj = k >> 1; jj > 0; jj >>= 1) {
-            for (int t = threadIdx.x; t < P2; t += blockDim.x) {
-                const int partner = t ^ jj;
-                if (partner > t) {
-                    const bool up = (t & k) == 0;
-                    const unsigned long long a = keys[t], b = keys[partner];
-                    if ((a > b) == up) { keys[t] = b; keys[partner] = a; }
-                }
-            }
-            __syncthreads();
+// Stable ordering by counting: a candidate's place is the number of
+// candidates whose (order key, index) pair is smaller.  The pair is packed as
+// key << 14 | index (N <= 16384), so one unsigned compare decides it; every
+// workgroup stages all packed keys in LDS (each thread's scores loaded
+// kRankLoads at a time, all in flight together: they were just written
+// through other XCDs' caches) and places 64 candidates, one per lane, its
+// waves splitting the comparisons.  Padding keys (all ones) are larger than
+// every packed pair and never counted.
+constexpr int kRankWaves = 16;
+constexpr int kRankLoads = 8;
+constexpr int kRankMax = 16384;
+
+__global__ void __launch_bounds__(64 * kRankWaves) prop_rank_kernel(const float *scores, int N, int32_t *order) {
+    extern __shared__ __attribute__((aligned(16))) unsigned pk[];   // N rounded up to 4
+    __shared__ int part[kRankWaves][64];
+    const int Np = (N + 3) & ~3;
+    for (int t0 = threadIdx.x; t0 < Np; t0 += blockDim.x * kRankLoads) {
+        float sv[kRankLoads];
+#pragma unroll
+        for (int u = 0; u < kRankLoads; ++u) {
+            const int t = t0 + u * (int)blockDim.x;
+            sv[u] = t < N ? scores[t] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < kRankLoads; ++u) {
+            const int t = t0 + u * (int)blockDim.x;
+            if (t < Np) pk[t] = t < N ? (order_key(sv[u]) << 14) | (unsigned)t : 0xffffffffu;
         }
     }
-    for (int t = threadIdx.x; t < N; t += blockDim.x) order[t] = (int32_t)(keys[t] & 0xffffffffu);
-}
-
-// Up to 1024 * ITEMS scores in one workgroup: a stable block radix sort of
-// the 16-bit order keys with the candidate index as value, so that ties keep
-// index order (the same order as the bitonic sort of key:index).
-template <int ITEMS>
-__global__ void __launch_bounds__(1024) prop_rsort_kernel(const float *scores, int N, int32_t *order) {
-    using Sort = rocprim::block_radix_sort<unsigned, 1024, ITEMS, int>;
-    __shared__ typename Sort::storage_type st;
-    unsigned k[ITEMS];
-    int v[ITEMS];
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const int t = threadIdx.x * ITEMS + j;  // blocked arrangement: index order
-        k[j] = t < N ? order_key(scores[t]) : 0xffffu;
-        v[j] = t;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
+    const unsigned ci = i < N ? pk[i] : 0u;
+    const int q = Np / 4;
+    const int per = (q + kRankWaves - 1) / kRankWaves;
+    const int q0 = wave * per, q1 = min(q, q0 + per);
+    const uint4 *p4 = reinterpret_cast<const uint4 *>(pk);
+    int cnt = 0;
+#pragma unroll 4
+    for (int j = q0; j < q1; ++j) {
+        const uint4 v = p4[j];
+        cnt += (v.x < ci) + (v.y < ci) + (v.z < ci) + (v.w < ci);
     }
-    Sort().sort(k, v, st, 0, 16);
+    part[wave][lane] = cnt;
+    __syncthreads();
+    if (wave == 0 && i < N) {
+        int r = 0;
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const int t = threadIdx.x * ITEMS + j;
-        if (t < N) order[t] = v[j];
+        for (int w = 0; w < kRankWaves; ++w) r += part[w][lane];
+        order[r] = i;
     }
 }
 
@@ -420,16 +425,13 @@ hipError_t launch_prop_adam(float *theta, float *grad, float *mom, float *vel, i
     return hipGetLastError();
 }
 
-int prop_sort_max() { return 16384; }
+int prop_sort_max() { return kRankMax; }
 
 hipError_t launch_prop_sort(const float *scores, int N, int32_t *order, hipStream_t s) {
-    if (N <= 1024 * 8) {
-        hipLaunchKernelGGL(prop_rsort_kernel<8>, dim3(1), dim3(1024), 0, s, scores, N, order);
-        return hipGetLastError();
-    }
-    int P2 = 1;
-    while (P2 < N) P2 <<= 1;
-    hipLaunchKernelGGL(prop_sort_kernel, dim3(1), dim3(1024), (size_t)P2 * 8, s, scores, N, order);
+    if (N <= 0) return hipSuccess;
+    if (N > kRankMax) return hipErrorInvalidValue;
+    const size_t lds = (size_t)((N + 3) & ~3) * 4;
+    hipLaunchKernelGGL(prop_rank_kernel, dim3((N + 63) / 64), dim3(64 * kRankWaves), lds, s, scores, N, order);
     return hipGetLastError();
 }
 

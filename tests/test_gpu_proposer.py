@@ -105,6 +105,27 @@ def test_ranked_search_keeps_the_plain_verdicts(ctx, orc):
             assert plain["points_before_first"] == ref["cex_rank"][0]
 
 
+def test_ranked_search_full_image_matches_oracle(ctx, orc):
+    """A 784-pixel property large enough that the ordered search's queue runs
+    past its single-chunk tickets into batched ones (4.9 M points, ~77 K
+    chunks): both orders return exactly the oracle's records."""
+    from paper_1907_12933_amd import ibmc
+    g = I.rng(61)
+    net = I.random_qnet(g, [784, 64, 64, 10], shift=6, wmax=24, bmax=400)
+    m = ibmc.Mlp(ctx, net)
+    x = I.workload_blob784(count=1).images[0]
+    D = np.array([-32, -16, 16, 32], np.int16)
+    ref = orc.q8_check(net, x, D, 1, 2)
+    assert ref["cex_total"] > 0
+    prop = ibmc.Proposer(ctx, seed=2)
+    for p in (None, prop):
+        s, cx = ibmc.ibmc_check_property_ranked(ctx, m, p, x, 28, 28, D, 1, 2, cex_capacity=1 << 20)
+        assert list(s["cex"]) == [int(v) for v in ref["cex"]]
+        assert np.array_equal(cx["rank"], ref["cex_rank"]) and np.array_equal(cx["k"], ref["cex_k"])
+        assert np.array_equal(cx["new_label"], ref["cex_label"])
+        assert 0 <= s["points_before_first"] < s["points_total"]
+
+
 def test_labels_from_records(ctx, orc):
     from paper_1907_12933_amd import ibmc
     g = I.rng(43)
@@ -121,12 +142,16 @@ def test_labels_from_records(ctx, orc):
     assert np.array_equal(lab, exp)
 
 
-def _order_from_scores(scores):
-    """Visiting order of the candidates: 16-bit order keys (larger score first), ties by index."""
+def _order_keys(scores):
+    """16-bit order keys: smaller key = larger score."""
     b = scores.astype(np.float32).view(np.uint32).astype(np.uint64)
     u = np.where(b & 0x80000000, b ^ 0xFFFFFFFF, b | 0x80000000)
-    key = ((~u) & 0xFFFFFFFF) >> 16
-    return np.argsort(key, kind="stable")
+    return ((~u) & 0xFFFFFFFF) >> 16
+
+
+def _order_from_scores(scores):
+    """Visiting order of the candidates: 16-bit order keys (larger score first), ties by index."""
+    return np.argsort(_order_keys(scores), kind="stable")
 
 
 def test_ranked_order_follows_scores(ctx, orc):
@@ -152,5 +177,34 @@ def test_ranked_order_follows_scores(ctx, orc):
         expect = min(int(pos_of[int(r)]) for r in ref["cex_rank"])  # k = 1: rank = pixel * m + delta index
         s, _ = ibmc.ibmc_check_property_ranked(ctx, m, prop, x, 8, 8, D, 1, 1)
         assert s["points_before_first"] == expect
+        checked += 1
+    assert checked >= 2
+
+
+def test_ranked_order_many_candidates(ctx, orc):
+    """12,544 candidates (784 pixels x 16 deltas, many equal 16-bit keys): the
+    learned search's first level-1 counterexample sits where the stable order
+    of the scores puts the earliest of the oracle's level-1 counterexamples."""
+    from paper_1907_12933_amd import ibmc
+    g = I.rng(53)
+    net = I.random_qnet(g, [784, 64, 16, 10], shift=6, wmax=24, bmax=400)
+    m = ibmc.Mlp(ctx, net)
+    D = np.array([d for d in range(-64, 65, 8) if d != 0], np.int16)
+    assert len(D) == 16
+    prop = ibmc.Proposer(ctx, seed=6)
+    checked = 0
+    for t in range(4):
+        x = g.integers(0, 255, size=784, endpoint=True).astype(np.uint8)
+        ref = orc.q8_check(net, x, D, 1, 1)
+        if not ref["cex_total"]:
+            continue
+        sc = ibmc.ibmc_proposer_score(ctx, prop, m, x, 28, 28, D)
+        order = _order_from_scores(sc)
+        key_ties = len(order) - len(np.unique(_order_keys(sc)))
+        pos_of = np.empty(len(order), np.int64)
+        pos_of[order] = np.arange(len(order))
+        expect = min(int(pos_of[int(r)]) for r in ref["cex_rank"])
+        s, _ = ibmc.ibmc_check_property_ranked(ctx, m, prop, x, 28, 28, D, 1, 1)
+        assert s["points_before_first"] == expect, (t, key_ties)
         checked += 1
     assert checked >= 2
