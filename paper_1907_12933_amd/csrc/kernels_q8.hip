@@ -31,9 +31,11 @@ constexpr int kFwdSplit = 4;  // every dot product is split over this many threa
 
 // xs: n pixel values; act0/act1: scratch of kMaxWidth ints each; part:
 // kFwdSplit x kMaxWidth ints of partial sums.  Every layer's dot products are
-// split kFwdSplit ways over the inputs (short dependent chains, coalesced
-// weight reads: the transposed first layer by consecutive neurons, the
-// row-major later layers by consecutive input segments of one row).
+// split over the inputs (short dependent chains, coalesced weight reads).
+// The transposed first layer is read four neurons per 32-bit load, its
+// inputs split as many ways as the partial sums allow (16 for up to 256
+// neurons); the row-major later layers are read 16 weights per load when a
+// row is a multiple of 16 bytes, split kFwdSplit ways over the row.
 // Writes potentials (natural order, layers concatenated) if pot != nullptr,
 // layer-1 potentials in sigma order if u0s != nullptr; returns the label
 // (thread 0 holds the valid value) and the exact-tie flag.
@@ -42,21 +44,35 @@ __device__ void dense_forward_block(const QNetDev &net, const int *xs, int *act0
                                     int *tie_out) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int n = net.dims[0], H1 = net.H[1];
-    const int seg1 = (n + kFwdSplit - 1) / kFwdSplit;
+    int *const pf = &part[0][0];                     // [S1][H1] for the first layer
     // layer 1 through the transposed first layer, sigma order
-    for (int t = tid; t < H1 * kFwdSplit; t += nthr) {
-        const int q = t % H1, sp = t / H1;
+    const int G1 = H1 / 4;                           // groups of four neurons
+    const int S1 = max(1, min(16, kFwdSplit * kMaxWidth / H1));
+    const int seg1 = (n + S1 - 1) / S1;
+    for (int t = tid; t < G1 * S1; t += nthr) {
+        const int grp = t % G1, sp = t / G1;
         const int i0 = sp * seg1, i1 = min(n, i0 + seg1);
-        int u = 0;
+        const int *w4 = reinterpret_cast<const int *>(net.W1T) + grp;   // row stride H1 / 4 words
+        int u0 = 0, u1 = 0, u2 = 0, u3 = 0;
 #pragma unroll 8
-        for (int i = i0; i < i1; ++i) u += (int)net.W1T[(int64_t)i * H1 + q] * xs[i];
-        part[sp][q] = u;
+        for (int i = i0; i < i1; ++i) {
+            const int w = w4[(int64_t)i * G1];
+            const int x = xs[i];
+            u0 += (int)(int8_t)w * x;
+            u1 += (int)(int8_t)(w >> 8) * x;
+            u2 += (int)(int8_t)(w >> 16) * x;
+            u3 += (w >> 24) * x;
+        }
+        int *dst = pf + sp * H1 + 4 * grp;
+        dst[0] = u0;
+        dst[1] = u1;
+        dst[2] = u2;
+        dst[3] = u3;
     }
     __syncthreads();
     for (int q = tid; q < H1; q += nthr) {
         int u = net.b1s[q];
-#pragma unroll
-        for (int sp = 0; sp < kFwdSplit; ++sp) u += part[sp][q];
+        for (int sp = 0; sp < S1; ++sp) u += pf[sp * H1 + q];
         const int neuron = sigma64(q);
         if (u0s) u0s[q] = u;
         if (neuron < net.dims[1]) {
@@ -69,15 +85,29 @@ __device__ void dense_forward_block(const QNetDev &net, const int *xs, int *act0
     int po = net.dims[1];
     for (int l = 2; l <= net.L; ++l) {
         const int nin = net.dims[l - 1], nout = net.dims[l];
-        const int seg = (nin + kFwdSplit - 1) / kFwdSplit;
         const int8_t *W = net.Wd[l];
+        const bool wide = (nin % 16) == 0 && (reinterpret_cast<uintptr_t>(W) % 16) == 0;
+        // split points on 16-weight boundaries when the rows are read 16 at a time
+        const int seg = wide ? (nin / 16 + kFwdSplit - 1) / kFwdSplit * 16 : (nin + kFwdSplit - 1) / kFwdSplit;
         for (int t = tid; t < nout * kFwdSplit; t += nthr) {
             const int j = t / kFwdSplit, sp = t % kFwdSplit;
             const int i0 = sp * seg, i1 = min(nin, i0 + seg);
             const int8_t *row = W + (int64_t)j * nin;
             int u = 0;
+            if (wide) {
+                for (int i = i0; i < i1; i += 16) {
+                    const int4 w = *reinterpret_cast<const int4 *>(row + i);
+                    const int ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        u += (int)(int8_t)ww[c] * in[i + 4 * c] + (int)(int8_t)(ww[c] >> 8) * in[i + 4 * c + 1] +
+                             (int)(int8_t)(ww[c] >> 16) * in[i + 4 * c + 2] + (ww[c] >> 24) * in[i + 4 * c + 3];
+                    }
+                }
+            } else {
 #pragma unroll 8
-            for (int i = i0; i < i1; ++i) u += (int)row[i] * in[i];
+                for (int i = i0; i < i1; ++i) u += (int)row[i] * in[i];
+            }
             part[sp][j] = u;
         }
         __syncthreads();
