@@ -574,16 +574,21 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
         uhi = a1v >= 0 ? (a1v + f - 1) / f : -((-a1v) / f);  // ceil(a1v / f)
     }
 
-    // ---- work distribution: tickets from the global queue, each a single
-    // chunk at first (the visiting order stays fine where an ordered search
-    // meets its first counterexample), then batches of contiguous chunks
-    // (one queue atomic, one cursor decode and one base per batch); the
-    // cursor always describes the chunk whose first-layer loads are in
-    // flight.  Between chunks it rests in the wave's LDS record (read back
+    // ---- work distribution: first the leading single chunks, dealt out
+    // statically round by round (wave g of the grid's NW waves takes chunks
+    // g, g + NW, ...: the visiting order stays fine where an ordered search
+    // meets its first counterexample, and no wave waits on the queue atomic,
+    // which every wave of the grid hits at once when it starts), then
+    // tickets from the global queue, each a batch of contiguous chunks (one
+    // queue atomic, one cursor decode and one base per batch); the cursor
+    // always describes the chunk whose first-layer loads are in flight.  Between chunks it rests in the wave's LDS record (read back
     // and written once per chunk), so that none of its fields holds
     // registers across the layers.
     int64_t cur_chunk = 0, end_chunk = 0;
     int fetches = 0;
+    int sround = 0;  // static rounds taken
+    const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t gwave = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave_uniform(wave);
     // next chunk of this wave; false when the queue is exhausted or a stop
     // or abort was requested.  seg: the segment (hence the base) changed.
     auto advance = [&](Cursor &c, bool first, bool &seg) __attribute__((always_inline)) -> bool {
@@ -592,16 +597,21 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
             seg = cursor_next<CH, EnumParams>(c, Q);
             return true;
         }
-        unsigned long long ticket = 0;
-        if (lane == 0) ticket = atomicAdd(Q.queue, 1ull);
-        const int64_t t = (int64_t)wave_uniform(ticket);  // lane 0's value
-        const int64_t start = t < Q.single ? t : Q.single + (t - Q.single) * Q.batch;
+        int64_t start = (int64_t)sround * n_waves + gwave, len = 1;
+        if (start < Q.single) {
+            ++sround;
+        } else {
+            unsigned long long ticket = 0;
+            if (lane == 0) ticket = atomicAdd(Q.queue, 1ull);
+            start = Q.single + (int64_t)wave_uniform(ticket) * Q.batch;  // lane 0's ticket
+            len = Q.batch;
+        }
         if (start >= Q.total_chunks) return false;
         if (wave_uniform(*Q.stop_flag)) return false;
         // host-mapped: poll sparsely
         if (Q.abort_host && (fetches++ & 15) == 0 && wave_uniform(*Q.abort_host)) return false;
         cur_chunk = start;
-        end_chunk = min(start + (t < Q.single ? 1 : (int64_t)Q.batch), Q.total_chunks);
+        end_chunk = min(start + len, Q.total_chunks);
         cursor_decode<CH, EnumParams>(c, Q, cur_chunk);
         seg = true;
         return true;

@@ -860,10 +860,11 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
         P.jobs = reinterpret_cast<const EnumJob *>(SD + o_jobs);
         P.n_jobs = (int32_t)jobs.size();
         P.total_chunks = total;
-        // visit in order: the first four tickets of every wave are single
-        // chunks (the early positions, where a first counterexample usually
-        // sits, are visited one chunk at a time), later tickets contiguous
-        // batches (the same size rule as the unordered search)
+        // visit in order: the first four rounds of the grid are single
+        // chunks dealt out statically, one per wave and round (the early
+        // positions, where a first counterexample usually sits, are visited
+        // one chunk at a time without a queue atomic), later queue tickets
+        // contiguous batches (the same size rule as the unordered search)
         P.single = std::min<int64_t>(total, grid * 4 * 4);
         P.batch = (int32_t)std::max<int64_t>(1, std::min<int64_t>(16, (total - P.single) / (grid * 32)));
         P.props = d_props;

@@ -109,8 +109,11 @@ extern "C" ibmc_status ibmc_ctx_create(int32_t device, void *hip_stream, ibmc_ct
     HIP_OK(hipEventCreate(&c->ek0));
     HIP_OK(hipEventCreate(&c->ek1));
     HIP_OK(hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming));
+    // coherent (fine-grained) host memory: the device's first-hit store and
+    // the host's abort request bypass the GPU caches, so each side sees the
+    // other's write while the kernel runs
     void *hm = nullptr;
-    HIP_OK(hipHostMalloc(&hm, 64, hipHostMallocMapped));
+    HIP_OK(hipHostMalloc(&hm, 64, hipHostMallocMapped | hipHostMallocCoherent));
     c->flags_host = reinterpret_cast<int32_t *>(hm);
     memset(hm, 0, 64);
     void *dm = nullptr;

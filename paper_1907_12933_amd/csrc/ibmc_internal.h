@@ -145,10 +145,11 @@ struct EnumParams {
     int32_t n_jobs;
     int32_t batch;                     // chunks per queue ticket once the single chunks are gone
     int64_t total_chunks;
-    int64_t single;                    // leading chunks handed out one per ticket (ordered searches)
+    int64_t single;                    // leading chunks dealt out one at a time, statically: chunk c
+                                       // to wave c mod (grid waves) (ordered searches)
     const PropDev *props;
-    unsigned long long *queue;         // next queue ticket: ticket t < single is chunk t, a later
-                                       // one the batch chunks from single + (t - single) * batch
+    unsigned long long *queue;         // next queue ticket: ticket t is the batch of chunks from
+                                       // single + t * batch
     unsigned long long *rec_count;     // record slots handed out (whole blocks of kRecBlock per wave)
     int64_t rec_cap;                   // record slots in recs: capacity + kRecBlock per wave of the grid
     DevRec *recs;                      // unused slots of a wave's last block hold a sentinel (prop -1)
