@@ -607,7 +607,15 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
             len = Q.batch;
         }
         if (start >= Q.total_chunks) return false;
-        if (wave_uniform(*Q.stop_flag)) return false;
+        if (wave_uniform(*Q.stop_flag)) {
+            // an ordered search stops only past the earliest chunk known to
+            // hold a counterexample, so every chunk before it is visited (a
+            // stale read is too large: more work, never a skipped chunk)
+            if (!Q.track_first) return false;
+            const unsigned long long fc =
+                wave_uniform(*reinterpret_cast<volatile unsigned long long *>(Q.first_chunk));
+            if ((unsigned long long)start > fc) return false;
+        }
         // host-mapped: poll sparsely
         if (Q.abort_host && (fetches++ & 15) == 0 && wave_uniform(*Q.abort_host)) return false;
         cur_chunk = start;

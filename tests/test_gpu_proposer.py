@@ -118,12 +118,20 @@ def test_ranked_search_full_image_matches_oracle(ctx, orc):
     ref = orc.q8_check(net, x, D, 1, 2)
     assert ref["cex_total"] > 0
     prop = ibmc.Proposer(ctx, seed=2)
+    keys = set(zip(ref["cex_k"].tolist(), ref["cex_rank"].tolist()))
     for p in (None, prop):
         s, cx = ibmc.ibmc_check_property_ranked(ctx, m, p, x, 28, 28, D, 1, 2, cex_capacity=1 << 20)
         assert list(s["cex"]) == [int(v) for v in ref["cex"]]
         assert np.array_equal(cx["rank"], ref["cex_rank"]) and np.array_equal(cx["k"], ref["cex_k"])
         assert np.array_equal(cx["new_label"], ref["cex_label"])
         assert 0 <= s["points_before_first"] < s["points_total"]
+        # stopping at the first counterexample still visits every point
+        # before it: the same first position, and only true counterexamples
+        s1, c1 = ibmc.ibmc_check_property_ranked(ctx, m, p, x, 28, 28, D, 1, 2, stop_at_first=True,
+                                                 cex_capacity=1 << 20)
+        assert s1["points_before_first"] == s["points_before_first"]
+        assert 0 < len(c1) <= len(cx)
+        assert all((int(a), int(b)) in keys for a, b in zip(c1["k"], c1["rank"]))
 
 
 def test_labels_from_records(ctx, orc):
