@@ -970,6 +970,10 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
             // before level 2, and within level 2 the visiting order starts with
             // the first pixel, so only the records sharing the first record's
             // first pixel can hold the earliest position
+            // level 1 is visited before level 2 (its positions lie below
+            // off2) and the records come sorted by (k, rank): once a level-1
+            // record has a position, no level-2 record can come earlier
+            if (has1 && r.k >= 2 && first_pos >= 0 && first_pos < off2) break;
             if (!p) {
                 if (first_pos >= 0 && r.k == 1) continue;
                 if (r.k == 2) {
