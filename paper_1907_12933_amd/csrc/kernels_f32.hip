@@ -124,7 +124,7 @@ constexpr int kF32MaxWidth = 512;
 __global__ void __launch_bounds__(256) enum_f32_kernel(FEnumParams P, const int32_t *u0_index) {
     constexpr int CH = kF32Chunk;
     __shared__ float base[kF32MaxWidth];
-    __shared__ float act[2][CH][kF32MaxWidth];
+    __shared__ __attribute__((aligned(16))) float act[2][CH][kF32MaxWidth];
     __shared__ int s_p[CH], s_i[CH], s_valid[CH];
     __shared__ float s_e[CH];
     __shared__ unsigned long long s_start;
@@ -202,7 +202,22 @@ __global__ void __launch_bounds__(256) enum_f32_kernel(FEnumParams P, const int3
                 const float b = net.bd[l][j];
 #pragma unroll
                 for (int t = 0; t < CH; ++t) acc[t] = b;
-                for (int i = 0; i < nin; ++i) {
+                // four inputs per step: one 16-byte LDS read per point feeds four
+                // FMAs (the products still accumulate in input order)
+                int i = 0;
+                for (; i + 4 <= nin; i += 4) {
+                    const float w0 = WT[(int64_t)(i + 0) * nout + j], w1 = WT[(int64_t)(i + 1) * nout + j];
+                    const float w2 = WT[(int64_t)(i + 2) * nout + j], w3 = WT[(int64_t)(i + 3) * nout + j];
+#pragma unroll
+                    for (int t = 0; t < CH; ++t) {
+                        const float4 a = *reinterpret_cast<const float4 *>(&act[cur_buf][t][i]);
+                        acc[t] = fmaf(w0, a.x, acc[t]);
+                        acc[t] = fmaf(w1, a.y, acc[t]);
+                        acc[t] = fmaf(w2, a.z, acc[t]);
+                        acc[t] = fmaf(w3, a.w, acc[t]);
+                    }
+                }
+                for (; i < nin; ++i) {
                     const float w = WT[(int64_t)i * nout + j];
 #pragma unroll
                     for (int t = 0; t < CH; ++t) acc[t] = fmaf(w, act[cur_buf][t][i], acc[t]);
