@@ -10,11 +10,11 @@
  *   - neuron potential u = sum_j w_j * i_j + b              (Sec. II-A, Eq. (1))
  *   - sigmoid N(u) = 1 / (1 + e^-u)                          (Sec. II-A, Eq. (2))
  *   - the safety property "the classification of every image in the
- *     restricted set equals the clean classification"        (Sec. III-C, Eqs. (4)-(5))
+ *     restricted set equals the clean classification"        (Sec. III-C, Eqs. (9)-(10))
  *     checked with an incrementally growing bound k           (Sec. II-B)
  *   - sign / value / distance change and the SS, DS, SV, DV
- *     neuron-pair covers with their coverage literal          (Sec. III-B, Eqs. (6)-(9))
- *   - Euclidean distance                                     (Sec. III-C, Eq. (3))
+ *     neuron-pair covers with their coverage literal          (Sec. III-B, Eqs. (3)-(6))
+ *   - Euclidean distance                                     (Sec. III-C, Eq. (7))
  *
  * Readings where the paper is silent (the same ones the library documents):
  *   - integer networks: int8 weights, int32 bias, hidden activation
@@ -622,7 +622,7 @@ int orc_coverage(int nl, const int32_t *widths, const int64_t *pot1, const int64
     return ORC_OK;
 }
 
-/* Euclidean distance of two vectors (Eq. (3)). */
+/* Euclidean distance of two vectors (Eq. (7)). */
 double orc_euclid(const double *p, const double *q, int64_t n) {
     double s = 0.0;
     for (int64_t i = 0; i < n; ++i) s += (p[i] - q[i]) * (p[i] - q[i]);

@@ -28,11 +28,24 @@ def _compile(src):
     return obj, msgs
 
 
-def build(verbose: bool = False, jobs: int = 6) -> str:
+def _fresh(src):
+    """The object of src is newer than src and every header it could include."""
+    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    if not os.path.exists(obj):
+        return False
+    deps = [src] + glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(INCLUDE, "*.h"))
+    return os.path.getmtime(obj) > max(os.path.getmtime(d) for d in deps)
+
+
+def build(verbose: bool = False, jobs: int = 6, incremental: bool = False) -> str:
+    """Compile every source (incremental=True keeps objects newer than their
+    sources and all headers), then link libibmc.so."""
     os.makedirs(OBJDIR, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    todo = [s for s in srcs if not (incremental and _fresh(s))]
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        results = list(ex.map(_compile, srcs))
+        done = dict(zip(todo, ex.map(_compile, todo)))
+    results = [done.get(s) or (os.path.join(OBJDIR, os.path.basename(s) + ".o"), []) for s in srcs]
     for obj, msgs in results:
         if verbose and msgs:
             print("\n".join(msgs))
@@ -45,5 +58,5 @@ def build(verbose: bool = False, jobs: int = 6) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)
