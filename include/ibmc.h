@@ -9,11 +9,11 @@
  *     the sigmoid variant applies N(u) = 1 / (1 + e^-u) (Sec. II-A, Eq. (2));
  *   - safety property: every image of the restricted set keeps the clean
  *     image's classification; a violation is a counterexample
- *     (Sec. III-C, Eqs. (4)-(5));
+ *     (Sec. III-C, Eqs. (9)-(10));
  *   - incremental bound: the check is repeated for k = k_min, k_min+k_step,
  *     ... (Sec. II-B, including the increment granularity);
  *   - coverage: SS / DS / SV / DV neuron-pair covers and the covered-neuron
- *     literal (Sec. III-B, Eqs. (6)-(9)).
+ *     literal (Sec. III-B, Eqs. (3)-(6)).
  *
  * The paper restricts images to a Euclidean ball around the clean image and
  * solves for a violating one symbolically.  Here the restricted set at bound k
@@ -212,6 +212,26 @@ ibmc_status ibmc_check_property(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_
                                 int32_t n_pixels, const int16_t *delta_set, int32_t n_deltas,
                                 const ibmc_check_opts *opts, ibmc_check_summary *out,
                                 ibmc_cex *cex_buf, ibmc_cex *near_tie_buf);
+
+/* Allocation-free ibmc_check_property, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results and errors as
+ * ibmc_check_property; the call itself allocates and frees nothing: every
+ * device buffer it needs is carved from one fixed scratch array of
+ * IBMC_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs on
+ * until the process ends (its address is looked up once per device, when a
+ * context is created there).  A call whose worst-case need (record slots
+ * for cex_capacity plus one block per wave, their sort space, near-tie
+ * slots, tables) exceeds the array is rejected with IBMC_E_INVALID before
+ * any device work.  Every call on a device shares that device's array and
+ * clears what it uses, so two calls that overlap in time on one device (two
+ * threads, or two contexts on different streams) race and must not be
+ * made. */
+#define IBMC_NOALLOC_SCRATCH_BYTES (64ll << 20)
+ibmc_status ibmc_check_property_noalloc(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *image,
+                                        int32_t n_pixels, const int16_t *delta_set, int32_t n_deltas,
+                                        const ibmc_check_opts *opts, ibmc_check_summary *out,
+                                        ibmc_cex *cex_buf, ibmc_cex *near_tie_buf);
 
 /* Check many properties, possibly over different networks, as one
  * batch.  outs: one summary per property.  Records of all properties share

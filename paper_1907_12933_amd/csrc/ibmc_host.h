@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <utility>
 #include <string>
 #include <vector>
 #include <deque>
@@ -35,14 +36,35 @@ void clear_error();
         if (_s < 0) return _s;                                                                    \
     } while (0)
 
-// Grow-only device allocation.
+// A fixed region of device memory that buffers are carved from, in order,
+// instead of being allocated (the allocation-free entry point).  While one is
+// installed on the calling thread, DevBuf::reserve takes its bytes from it and
+// fails with a clear error once the region is used up.
+struct ScratchArena {
+    char *base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+};
+ScratchArena *&thread_arena();
+
+// Grow-only device allocation (or a view into the thread's arena).
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool borrowed = false;   // p points into an arena: never freed here
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), borrowed(o.borrowed) {
+        o.p = nullptr;
+        o.bytes = 0;
+        o.borrowed = false;
+    }
+    void swap(DevBuf &o) noexcept {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+        std::swap(borrowed, o.borrowed);
+    }
     ~DevBuf();
     void release();
     ibmc_status reserve(size_t n);
@@ -108,4 +130,10 @@ struct ibmc_mlp {
 namespace ibmc {
 std::string shape_key(const ibmc_mlp *m);
 PropParams prop_views(const ibmc_proposer *p);
+const EnumVariant *pick_variant(ibmc_ctx *ctx, const ibmc_mlp *net);
+ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props, int32_t n_props, const ibmc_check_opts *o,
+                             ibmc_check_summary *outs, ibmc_cex *cex_buf, ibmc_cex *tie_buf, bool images_on_device);
+// Looks up, once per device and with that device current, the address of
+// the allocation-free entry point's fixed scratch array.
+ibmc_status noalloc_setup(int device);
 }

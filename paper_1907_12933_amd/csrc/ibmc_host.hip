@@ -41,16 +41,38 @@ void clear_error() { g_err.clear(); }
 // device buffers
 // ---------------------------------------------------------------------------
 
+ScratchArena *&thread_arena() {
+    static thread_local ScratchArena *a = nullptr;
+    return a;
+}
+
 DevBuf::~DevBuf() { release(); }
 
 void DevBuf::release() {
-    if (p) (void)hipFree(p);
+    if (p && !borrowed) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    borrowed = false;
 }
 
 ibmc_status DevBuf::reserve(size_t n) {
     if (n <= bytes && p) return IBMC_OK;
+    if (ScratchArena *a = thread_arena()) {
+        // carve the next 256-byte aligned piece; an owned allocation is never
+        // held here while an arena is installed (the caller swaps them out)
+        if (p && !borrowed) return fail(IBMC_E_INVALID, "owned buffer met while carving fixed scratch");
+        const size_t off = (a->used + 255) & ~(size_t)255;
+        const size_t want = std::max<size_t>(n, 256);
+        if (off > a->cap || want > a->cap - off)
+            return fail(IBMC_E_INVALID, "the call needs more than the %zu bytes of fixed device scratch "
+                        "(at %zu, %zu more wanted); lower its capacities or use the allocating entry point",
+                        a->cap, off, want);
+        p = a->base + off;
+        bytes = want;
+        borrowed = true;
+        a->used = off + want;
+        return IBMC_OK;
+    }
     release();
     size_t want = std::max<size_t>(n, 256);
     hipError_t e = hipMalloc(&p, want);
@@ -119,6 +141,7 @@ extern "C" ibmc_status ibmc_ctx_create(int32_t device, void *hip_stream, ibmc_ct
     void *dm = nullptr;
     HIP_OK(hipHostGetDevicePointer(&dm, hm, 0));
     c->flags_dev = reinterpret_cast<int32_t *>(dm);
+    IBMC_TRY(noalloc_setup(device));
     *out = c.release();
     return IBMC_OK;
 }

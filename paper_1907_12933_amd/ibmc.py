@@ -114,6 +114,7 @@ SIGNATURES = {
     "ibmc_load_mlp": (I32, [VP, C.POINTER(ibmc_mlp_desc), C.POINTER(VP)]),
     "ibmc_free_mlp": (None, [VP]),
     "ibmc_check_property": (I32, [VP, VP, P_U8, I32, P_I16, I32, P_OPTS, P_SUM, P_CEX, P_CEX]),
+    "ibmc_check_property_noalloc": (I32, [VP, VP, P_U8, I32, P_I16, I32, P_OPTS, P_SUM, P_CEX, P_CEX]),
     "ibmc_check_batch": (I32, [VP, C.POINTER(ibmc_property), I32, P_OPTS, P_SUM, P_CEX, P_CEX]),
     "ibmc_check_batch_dev": (I32, [VP, C.POINTER(ibmc_property), I32, P_OPTS, P_SUM, P_CEX, P_CEX]),
     "ibmc_abort": (I32, [VP]),
@@ -297,7 +298,7 @@ def summary_dicts(outs, n):
 
 
 def ibmc_check_property(ctx, net, image, deltas, k_min=1, k_max=2, k_step=1, stop_at_first=False,
-                        cex_capacity=1 << 20, near_tie_capacity=0, near_tie_rel=0.0):
+                        cex_capacity=1 << 20, near_tie_capacity=0, near_tie_rel=0.0, _entry="ibmc_check_property"):
     """Returns (summary dict, cex records, near-tie records) as numpy structured arrays."""
     image = np.ascontiguousarray(image, np.uint8)
     D = np.ascontiguousarray(deltas, np.int16)
@@ -305,14 +306,22 @@ def ibmc_check_property(ctx, net, image, deltas, k_min=1, k_max=2, k_step=1, sto
     ties = np.empty(max(near_tie_capacity, 1), CEX_DTYPE)
     o = _opts(k_min, k_max, k_step, stop_at_first, cex_capacity, near_tie_capacity, near_tie_rel)
     s = ibmc_check_summary()
-    rc = _ck(lib().ibmc_check_property(ctx.handle, net.handle, _ptr(image, P_U8), image.size, _ptr(D, P_I16),
-                                       D.size, C.byref(o), C.byref(s), cex.ctypes.data_as(P_CEX),
-                                       ties.ctypes.data_as(P_CEX)))
+    rc = _ck(getattr(lib(), _entry)(ctx.handle, net.handle, _ptr(image, P_U8), image.size, _ptr(D, P_I16),
+                                    D.size, C.byref(o), C.byref(s), cex.ctypes.data_as(P_CEX),
+                                    ties.ctypes.data_as(P_CEX)))
     sd = summary_dict(s)
     sd["status"] = rc
     nrec = min(sd["cex_total"], cex_capacity)
     ntie = min(sd["near_ties_total"], near_tie_capacity)
     return sd, cex[:nrec].copy(), ties[:ntie].copy()
+
+
+def ibmc_check_property_noalloc(ctx, net, image, deltas, k_min=1, k_max=2, k_step=1, stop_at_first=False,
+                                cex_capacity=1 << 16, near_tie_capacity=0, near_tie_rel=0.0):
+    """ibmc_check_property through the entry point that allocates no device
+    memory (its buffers come from the library's fixed per-device scratch)."""
+    return ibmc_check_property(ctx, net, image, deltas, k_min, k_max, k_step, stop_at_first, cex_capacity,
+                               near_tie_capacity, near_tie_rel, _entry="ibmc_check_property_noalloc")
 
 
 def _props(props, on_device):
