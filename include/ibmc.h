@@ -31,10 +31,12 @@
  * activation = pixel value 0..255; hidden activation
  * a = min(max(floor(u / 2^s), 0), 127) with a per-layer shift s (ReLU folded
  * into the clamp); the logits are the last layer's potentials; the label is
- * the lowest index attaining the largest logit.  Every potential must fit
- * int32: ibmc_load_mlp rejects a network whose worst case
- * sum_i |W[j][i]| * max_input + |b[j]| reaches 2^31 (IBMC_E_RANGE).  The
- * integer path is exact.
+ * the lowest index attaining the largest logit.  Every accumulator must fit
+ * int32: ibmc_load_mlp rejects (IBMC_E_RANGE) a network with a neuron whose
+ * sum_i |W[j][i]| * M + |b[j]| + H reaches 2^31, with M = 256 for the first
+ * layer and 128 for later ones and H = 64 * 2^s for a hidden layer of shift
+ * s (the kernels accumulate offset forms of the potentials).  The integer
+ * path is exact.
  *
  * Float networks (IBMC_ACT_SIGMOID_F32): float32 weights and biases, input
  * activation x / 256, sigmoid on hidden layers, linear logits, lowest-index
@@ -97,7 +99,7 @@ typedef enum { IBMC_COV_SS = 0, IBMC_COV_DS = 1, IBMC_COV_SV = 2, IBMC_COV_DV = 
  * widths..., classes.  W[l] is row-major [dims[l+1]][dims[l]] (int8 for
  * IBMC_ACT_RELU_Q8, float for IBMC_ACT_SIGMOID_F32); b[l] has dims[l+1]
  * entries (int32 or float).  shift has n_layers - 1 entries (integer nets
- * only; each in 0..30).  2 <= n_layers <= IBMC_MAX_LAYERS; every width is
+ * only; each in 0..24).  2 <= n_layers <= IBMC_MAX_LAYERS; every width is
  * <= IBMC_MAX_WIDTH; the class count is <= 64. */
 typedef struct {
     int32_t n_layers;
@@ -113,7 +115,7 @@ typedef struct {
  * point, never a counterexample).  stop_at_first: stop after the first level
  * that has a counterexample (Sec. II-B stops at the first violation).
  * cex_capacity / near_tie_capacity: room in the caller's record buffers.
- * near_tie_rel: float nets only; <= 0 selects 1e-4.
+ * near_tie_rel: float nets only; <= 0 selects 4e-5.
  * records_on_device: nonzero when cex_buf / near_tie_buf are device memory
  * of the context's device (the records then never cross to the host). */
 typedef struct {
@@ -265,6 +267,20 @@ ibmc_status ibmc_decode_point(int32_t n_pixels, int32_t n_deltas, int32_t k, int
 ibmc_status ibmc_replay(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *image,
                         const int16_t *delta_set, int32_t n_deltas, const ibmc_cex *recs,
                         int64_t n, int32_t *labels_out);
+
+/* Evaluate listed points (k[t], rank[t]) of one image of a float network
+ * with the float enumeration's own FP32 arithmetic (incremental first
+ * layer from the clean potentials, blocked sums, hardware-exponential
+ * sigmoid), for checking that path against a double-precision reference
+ * (Sec. II-A, Eqs. (1)-(2)).  Outputs, each nullable: logits [n][classes],
+ * labels [n], top-2 margins [n], and the clean label (the same arithmetic on
+ * the unperturbed image).  IBMC_E_INVALID for a k outside [0, min(pixels, 8)]
+ * or a rank outside [0, C(n,k) |D|^k); IBMC_E_UNIMPL for integer networks
+ * (their enumeration is exact: ibmc_replay confirms it). */
+ibmc_status ibmc_eval_points_f32(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *image,
+                                 const int16_t *delta_set, int32_t n_deltas, const int32_t *ks,
+                                 const int64_t *ranks, int64_t n, float *logits, int32_t *labels,
+                                 float *margins, int32_t *clean_label);
 
 /* Full forward pass of n_images images (host memory, dims[0] bytes each).
  * potentials (nullable): int32 [n_images][sum of dims[1..L]] for integer

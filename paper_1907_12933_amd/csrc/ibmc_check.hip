@@ -129,7 +129,8 @@ static ibmc_status validate_props(const ibmc_property *props, int32_t n_props, c
             return fail(IBMC_E_UNIMPL, "property %d: enumeration supports 2 or 3 weight layers", i);
         if (p.net->act == IBMC_ACT_SIGMOID_F32) {
             for (int l = 1; l <= p.net->L; ++l)
-                if (p.net->dims[l] > 512) return fail(IBMC_E_UNIMPL, "property %d: float layer wider than 512", i);
+                if (p.net->dims[l] > kF32MaxWidth)
+                    return fail(IBMC_E_UNIMPL, "property %d: float layer wider than %d", i, kF32MaxWidth);
         }
     }
     return IBMC_OK;
@@ -256,7 +257,7 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
     IBMC_TRY(ctx->ties.reserve((size_t)std::max<int64_t>(tcap, 1) * sizeof(DevRec)));
     int64_t max_h1 = 64;
     for (auto &pl : plans)
-        max_h1 = std::max<int64_t>(max_h1, pl.net->act == IBMC_ACT_RELU_Q8 ? pl.net->qd.H[1] : pl.net->dims[1]);
+        max_h1 = std::max<int64_t>(max_h1, pl.net->act == IBMC_ACT_RELU_Q8 ? pl.net->qd.H[1] : pl.net->fd.HP[1]);
     IBMC_TRY(ctx->u0.reserve((size_t)n_props * max_h1 * 4));
     std::vector<int32_t> u0_index(n_props), all_ids;
     std::iota(u0_index.begin(), u0_index.end(), 0);
@@ -269,7 +270,7 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
     for (auto &pl : plans) {
         const ibmc_mlp *net = pl.net;
         const bool q8 = net->act == IBMC_ACT_RELU_Q8;
-        int CH = enum_f32_chunk();
+        int CH = q8 ? 0 : enum_f32_chunk(net->fd);
         if (q8) {
             pl.v = pick_variant(ctx, net);
             if (!pl.v) return fail(IBMC_E_UNIMPL, "no enumeration kernel for network %s", shape_key(net).c_str());
@@ -317,7 +318,9 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
             if (occ < 1) return fail(IBMC_E_UNIMPL, "variant %s does not fit", pl.v->name);
             pl.grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * occ, std::max<int64_t>(1, pl.total / 2));
         } else {
-            pl.grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * 4, std::max<int64_t>(1, pl.total));
+            const int g = f32_enum_grid(net->fd, ctx->n_cu);
+            if (g < 1) return fail(IBMC_E_UNIMPL, "no float enumeration kernel for network %s", shape_key(net).c_str());
+            pl.grid = (int)std::min<int64_t>(g, std::max<int64_t>(1, pl.total));
         }
         all_ids.insert(all_ids.end(), pl.ids.begin(), pl.ids.end());
     }
@@ -392,7 +395,7 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
             P.slot_ties = ctr + st0;
             P.stop_flag = reinterpret_cast<volatile int32_t *>(ctr + 4);
             P.abort_host = ctx->flags_dev;
-            HIP_OK(launch_enum_f32(pl.grid, P, ctx->u0_index.as<int32_t>(), st));
+            HIP_OK(launch_enum_f32(pl.grid, P, st));
         }
         return IBMC_OK;
     };
@@ -682,6 +685,71 @@ extern "C" ibmc_status ibmc_check_property(ibmc_ctx *ctx, const ibmc_mlp *net, c
     p.k_max = opts->k_max;
     p.k_step = opts->k_step;
     return check_batch_impl(ctx, &p, 1, opts, out, cex_buf, near_tie_buf, false);
+}
+
+extern "C" ibmc_status ibmc_eval_points_f32(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *image,
+                                            const int16_t *delta_set, int32_t n_deltas, const int32_t *ks,
+                                            const int64_t *ranks, int64_t n, float *logits, int32_t *labels,
+                                            float *margins, int32_t *clean_label) {
+    clear_error();
+    if (!ctx || !net || !image || !delta_set) return fail(IBMC_E_INVALID, "null ctx / net / image / deltas");
+    if (net->act != IBMC_ACT_SIGMOID_F32) return fail(IBMC_E_UNIMPL, "float networks only (integer ones: ibmc_replay)");
+    if (n_deltas < 1 || n_deltas > kMaxDeltas) return fail(IBMC_E_INVALID, "n_deltas %d", n_deltas);
+    if (n < 0 || (n > 0 && (!ks || !ranks))) return fail(IBMC_E_INVALID, "bad point list");
+    const int np = net->dims[0];
+    for (int64_t t = 0; t < n; ++t) {
+        if (ks[t] < 0 || ks[t] > std::min(np, kMaxK)) return fail(IBMC_E_INVALID, "point %lld: k = %d", (long long)t, ks[t]);
+        const int64_t pts = binom_small(np, ks[t]) * ipow64(n_deltas, ks[t]);
+        if (ranks[t] < 0 || ranks[t] >= pts)
+            return fail(IBMC_E_INVALID, "point %lld: rank %lld outside [0, %lld)", (long long)t, (long long)ranks[t],
+                        (long long)pts);
+    }
+    HIP_OK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const int hp1 = net->fd.HP[1], nc = net->dims[net->L];
+    IBMC_TRY(ctx->images.upload(image, (size_t)np, s));
+    PropDev pd;
+    memset(&pd, 0, sizeof(pd));
+    pd.image = ctx->images.as<uint8_t>();
+    pd.m = n_deltas;
+    pd.n = np;
+    for (int i = 0; i < n_deltas; ++i) pd.deltas[i] = delta_set[i];
+    IBMC_TRY(ctx->props.upload(&pd, sizeof(pd), s));
+    const int32_t zero = 0;
+    IBMC_TRY(ctx->prop_ids.upload(&zero, 4, s));
+    IBMC_TRY(ctx->u0.reserve((size_t)hp1 * 4));
+    HIP_OK(launch_clean_f32(net->fd, ctx->props.as<PropDev>(), ctx->prop_ids.as<int32_t>(), 1, ctx->u0.as<float>(), hp1,
+                            s));
+    // point list and outputs in one device buffer
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t nn = (size_t)std::max<int64_t>(n, 1);
+    const size_t o_r = al(nn * 4), o_z = o_r + al(nn * 8), o_l = o_z + al(nn * nc * 4), o_m = o_l + al(nn * 4);
+    IBMC_TRY(ctx->recout.reserve(o_m + al(nn * 4)));
+    char *B = ctx->recout.as<char>();
+    if (n > 0) {
+        HIP_OK(hipMemcpyAsync(B, ks, n * 4, hipMemcpyHostToDevice, s));
+        HIP_OK(hipMemcpyAsync(B + o_r, ranks, n * 8, hipMemcpyHostToDevice, s));
+        F32EvalParams E{};
+        E.net = net->fd;
+        E.props = ctx->props.as<PropDev>();
+        E.ks = reinterpret_cast<const int32_t *>(B);
+        E.ranks = reinterpret_cast<const int64_t *>(B + o_r);
+        E.n = n;
+        E.u0f = ctx->u0.as<float>();
+        E.u0_stride = hp1;
+        E.logits = reinterpret_cast<float *>(B + o_z);
+        E.labels = reinterpret_cast<int32_t *>(B + o_l);
+        E.margins = reinterpret_cast<float *>(B + o_m);
+        HIP_OK(launch_eval_f32(E, s));
+        if (logits) HIP_OK(hipMemcpyAsync(logits, B + o_z, (size_t)n * nc * 4, hipMemcpyDeviceToHost, s));
+        if (labels) HIP_OK(hipMemcpyAsync(labels, B + o_l, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+        if (margins) HIP_OK(hipMemcpyAsync(margins, B + o_m, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+    }
+    PropDev back;
+    HIP_OK(hipMemcpyAsync(&back, ctx->props.p, sizeof(back), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (clean_label) *clean_label = back.label0;
+    return IBMC_OK;
 }
 
 extern "C" ibmc_status ibmc_set_variant(ibmc_ctx *ctx, const ibmc_mlp *net, const char *variant) {

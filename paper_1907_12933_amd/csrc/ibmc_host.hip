@@ -434,6 +434,32 @@ static ibmc_status build_f32(ibmc_ctx *ctx, ibmc_mlp *m) {
         IBMC_TRY(m->buf.emplace_back().upload(m->bf[l - 1].data(), m->bf[l - 1].size() * 4, s));
         f.bd[l] = (const float *)m->buf.back().p;
     }
+    // enumeration layout: transposed, zero-padded to the kernel family's widths
+    const F32Layout lay = f32_layout(m->L, m->dims.data());
+    f.kind = lay.kind;
+    for (int l = 0; l <= m->L; ++l) f.HP[l] = lay.HP[l];
+    {
+        const int hp1 = f.HP[1];
+        std::vector<float> w1p((size_t)n * hp1, 0.f);
+        for (int j = 0; j < h1; ++j)
+            for (int i = 0; i < n; ++i) w1p[(size_t)i * hp1 + j] = m->Wf[0][(size_t)j * n + i];
+        IBMC_TRY(m->buf.emplace_back().upload(w1p.data(), w1p.size() * 4, s));
+        f.W1P = (const float *)m->buf.back().p;
+    }
+    for (int l = 1; l <= m->L; ++l) {
+        const int nin = m->dims[l - 1], nout = m->dims[l], hin = f.HP[l - 1], hout = f.HP[l];
+        if (l >= 2) {
+            std::vector<float> wp((size_t)hin * hout, 0.f);
+            for (int j = 0; j < nout; ++j)
+                for (int i = 0; i < nin; ++i) wp[(size_t)i * hout + j] = m->Wf[l - 1][(size_t)j * nin + i];
+            IBMC_TRY(m->buf.emplace_back().upload(wp.data(), wp.size() * 4, s));
+            f.WP[l] = (const float *)m->buf.back().p;
+        }
+        std::vector<float> bp(hout, 0.f);
+        for (int j = 0; j < nout; ++j) bp[j] = m->bf[l - 1][j];
+        IBMC_TRY(m->buf.emplace_back().upload(bp.data(), bp.size() * 4, s));
+        f.bP[l] = (const float *)m->buf.back().p;
+    }
     HIP_OK(hipStreamSynchronize(s));
     return IBMC_OK;
 }
@@ -465,7 +491,8 @@ extern "C" ibmc_status ibmc_load_mlp(ibmc_ctx *ctx, const ibmc_mlp_desc *d, ibmc
     if (d->act == IBMC_ACT_RELU_Q8) {
         if (!d->shift) return fail(IBMC_E_INVALID, "shift is null");
         for (int l = 0; l < L - 1; ++l) {
-            if (d->shift[l] < 0 || d->shift[l] > 30) return fail(IBMC_E_INVALID, "shift[%d] = %d", l, d->shift[l]);
+            if (d->shift[l] < 0 || d->shift[l] > kMaxShift)
+                return fail(IBMC_E_INVALID, "shift[%d] = %d outside [0, %d]", l, d->shift[l], kMaxShift);
             m->shift.push_back(d->shift[l]);
         }
         for (int l = 0; l < L; ++l) {
@@ -474,13 +501,18 @@ extern "C" ibmc_status ibmc_load_mlp(ibmc_ctx *ctx, const ibmc_mlp_desc *d, ibmc
             const int32_t *b = (const int32_t *)d->b[l];
             m->Wq.emplace_back(W, W + (size_t)nin * nout);
             m->bq.emplace_back(b, b + nout);
-            // int32 headroom: inputs are at most 255 (pixels) or 127 (activations)
-            const int64_t amax = (l == 0) ? 255 : 127;
+            // int32 headroom of the forms the kernels accumulate in: inputs
+            // enter as x - 128 with 128 * rowsum in the init (first layer:
+            // every partial sum within |b| + 256 sum|w|), activations as
+            // a - 64 with 64 * rowsum in the init (within |b| + 128 sum|w|),
+            // and a hidden layer's accumulator is offset by -64 * 2^s
+            const int64_t amax = (l == 0) ? 256 : 128;
+            const int64_t off = (l < L - 1) ? (64LL << d->shift[l]) : 0;
             for (int j = 0; j < nout; ++j) {
-                int64_t s = std::llabs((long long)b[j]);
+                int64_t s = std::llabs((long long)b[j]) + off;
                 for (int i = 0; i < nin; ++i) s += std::llabs((long long)W[(size_t)j * nin + i]) * amax;
                 if (s >= (1LL << 31))
-                    return fail(IBMC_E_RANGE, "layer %d neuron %d: potential bound %lld reaches 2^31", l + 1, j,
+                    return fail(IBMC_E_RANGE, "layer %d neuron %d: accumulator bound %lld reaches 2^31", l + 1, j,
                                 (long long)s);
             }
         }

@@ -33,6 +33,7 @@ namespace ibmc {
 constexpr int kMaxLayers = IBMC_MAX_LAYERS;
 constexpr int kMaxWidth = IBMC_MAX_WIDTH;
 constexpr int kMaxClasses = 64;
+constexpr int kMaxShift = 24;          // hidden-layer shifts: 64 << s stays inside int32
 constexpr int kMaxK = 8;
 constexpr int kMaxDeltas = 64;
 
@@ -81,6 +82,13 @@ struct FNetDev {
     const float *WT[kMaxLayers + 1];   // l >= 2: transposed [dims[l-1]][dims[l]]
     const float *Wd[kMaxLayers + 1];   // l >= 1: row-major [dims[l]][dims[l-1]]
     const float *bd[kMaxLayers + 1];
+    // enumeration layout: widths padded to HP (zero weights and biases in the
+    // padding, whose units therefore add exact zeros downstream)
+    int kind;                          // F32Kind
+    int HP[kMaxLayers + 1];            // HP[0] = pixels
+    const float *W1P;                  // [n][HP1] transposed first layer
+    const float *WP[kMaxLayers + 1];   // l >= 2: transposed [HP[l-1]][HP[l]]
+    const float *bP[kMaxLayers + 1];   // l >= 1: [HP[l]]
 };
 
 // One counterexample record, identical to ibmc_cex.

@@ -1,8 +1,10 @@
-// Float-network (sigmoid variant) kernels: plain forward, clean pass, replay
-// and the exhaustive enumeration with an incremental first layer on FP32
-// vector FMA.  The sigmoid 1 / (1 + e^-u) calls the device expf.
+// Float-network (sigmoid variant) kernels: plain forward and replay (the
+// dense reference path, device expf), the clean pass of the enumeration, the
+// sixteen-points-per-wave enumeration for wide networks, evaluation of
+// listed points with the enumeration arithmetic, and the launchers that pick
+// a kernel family per network.
 #include "kernels_f32.h"
-#include "enum_common.h"
+#include "f32_impl.h"
 
 namespace ibmc {
 
@@ -64,23 +66,24 @@ __global__ void __launch_bounds__(256) forward_f32_kernel(FNetDev net, const uin
     }
 }
 
-__global__ void __launch_bounds__(256) clean_f32_kernel(FNetDev net, PropDev *props, const int32_t *prop_ids,
-                                                        int32_t n_ids, float *u0_store, int64_t u0_stride) {
-    __shared__ float xs[kMaxWidth], a0[kMaxWidth], a1[kMaxWidth];
-    __shared__ int lab;
-    __shared__ float mg, top;
+// Clean first-layer potentials of listed properties, padded to HP[1] with
+// zeros (the enumeration's u0), one workgroup per property: u_j = b_j +
+// sum_i W1[j][i] x_i / 256 by fma in pixel order.
+__global__ void __launch_bounds__(256) clean_u0_f32_kernel(FNetDev net, const PropDev *props, const int32_t *prop_ids,
+                                                           int32_t n_ids, float *u0_store, int64_t u0_stride) {
+    const int n = net.dims[0], h1 = net.dims[1], hp = net.HP[1];
     for (int t = blockIdx.x; t < n_ids; t += gridDim.x) {
         const int pid = prop_ids[t];
         const uint8_t *x = props[pid].image;
-        for (int i = threadIdx.x; i < net.dims[0]; i += blockDim.x) xs[i] = (float)x[i] * (1.0f / 256.0f);
-        __syncthreads();
-        dense_forward_f32_block(net, xs, a0, a1, nullptr, u0_store + (int64_t)pid * u0_stride, &lab, &mg, &top);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            props[pid].label0 = lab;
-            props[pid].tie0 = 0;
+        float *out = u0_store + (int64_t)pid * u0_stride;
+        for (int j = threadIdx.x; j < hp; j += blockDim.x) {
+            float u = 0.0f;
+            if (j < h1) {
+                u = net.bd[1][j];
+                for (int i = 0; i < n; ++i) u = fmaf(net.W1T[(int64_t)i * h1 + j], (float)x[i] * (1.0f / 256.0f), u);
+            }
+            out[j] = u;
         }
-        __syncthreads();
     }
 }
 
@@ -116,160 +119,7 @@ __global__ void __launch_bounds__(256) replay_f32_kernel(FNetDev net, const uint
     }
 }
 
-// Enumeration, one chunk of 16 points per workgroup iteration.  LDS holds the
-// segment base (h1 floats) and two activation buffers [16][width].
-constexpr int kF32Chunk = 16;
-constexpr int kF32MaxWidth = 512;
 
-__global__ void __launch_bounds__(256) enum_f32_kernel(FEnumParams P, const int32_t *u0_index) {
-    constexpr int CH = kF32Chunk;
-    __shared__ float base[kF32MaxWidth];
-    __shared__ __attribute__((aligned(16))) float act[2][CH][kF32MaxWidth];
-    __shared__ int s_p[CH], s_i[CH], s_valid[CH];
-    __shared__ float s_e[CH];
-    __shared__ unsigned long long s_start;
-    __shared__ int s_stop;
-    const FNetDev &net = P.net;
-    const int tid = threadIdx.x;
-    const int h1 = net.dims[1];
-    Cursor c;
-    int64_t cur = 0, end = 0;
-    bool have = false;
-    while (true) {
-        if (cur >= end) {
-            if (tid == 0) {
-                s_start = atomicAdd(P.queue, (unsigned long long)P.batch);
-                s_stop = (*P.stop_flag) || (P.abort_host && *P.abort_host);
-            }
-            __syncthreads();
-            const int64_t start = (int64_t)wave_uniform(s_start);
-            const int stop = wave_uniform(s_stop);
-            __syncthreads();
-            if (start >= P.total_chunks || stop) break;
-            cur = start;
-            end = min(start + (int64_t)P.batch, P.total_chunks);
-            cursor_decode<CH, FEnumParams>(c, P, cur);
-            have = false;
-        }
-        const PropDev &pr = P.props[c.prop];
-        if (!have) {
-            // base = clean potentials + prefix column updates (e / 256) * W1[:, p]
-            const float *u0 = P.u0f + (int64_t)u0_index[c.prop] * P.u0_stride;
-            int pp[kMaxK];
-            float ee[kMaxK];
-            int np = 0;
-            if (c.mode == SEG_PLAIN) {
-                np = c.k - 1;
-                for (int j = 0; j < kMaxK; ++j)
-                    if (j < np) {
-                        pp[j] = c.pre[j];
-                        const int xv = pr.image[pp[j]];
-                        ee[j] = (float)(clamp_pixel(xv + pr.deltas[c.dg[j]]) - xv) * (1.0f / 256.0f);
-                    }
-            }
-            for (int j = tid; j < h1; j += blockDim.x) {
-                float v = u0[j];
-                for (int t = 0; t < kMaxK; ++t)
-                    if (t < np) v = fmaf(ee[t], net.W1T[(int64_t)pp[t] * h1 + j], v);
-                base[j] = v;
-            }
-            have = true;
-        }
-        if (tid < CH) {
-            int p = 0, i = 0, pf = 0, f = 0;
-            const int64_t o = c.ch * CH + tid;
-            const bool v = last_element(c, P, o, p, i, pf, f);
-            s_valid[tid] = v;
-            s_p[tid] = v ? p : 0;
-            s_i[tid] = v ? i : 0;
-            const int xv = pr.image[s_p[tid]];
-            s_e[tid] = (float)(clamp_pixel(xv + pr.deltas[s_i[tid]]) - xv) * (1.0f / 256.0f);
-        }
-        __syncthreads();
-        // layer 1: incremental update + sigmoid
-        for (int j = tid; j < h1; j += blockDim.x) {
-            const float b = base[j];
-            for (int t = 0; t < CH; ++t)
-                act[0][t][j] = sigmoidf(fmaf(s_e[t], net.W1T[(int64_t)s_p[t] * h1 + j], b));
-        }
-        __syncthreads();
-        int cur_buf = 0;
-        for (int l = 2; l <= net.L; ++l) {
-            const int nin = net.dims[l - 1], nout = net.dims[l];
-            const float *WT = net.WT[l];
-            for (int j = tid; j < nout; j += blockDim.x) {
-                float acc[CH];
-                const float b = net.bd[l][j];
-#pragma unroll
-                for (int t = 0; t < CH; ++t) acc[t] = b;
-                // four inputs per step: one 16-byte LDS read per point feeds four
-                // FMAs (the products still accumulate in input order)
-                int i = 0;
-                for (; i + 4 <= nin; i += 4) {
-                    const float w0 = WT[(int64_t)(i + 0) * nout + j], w1 = WT[(int64_t)(i + 1) * nout + j];
-                    const float w2 = WT[(int64_t)(i + 2) * nout + j], w3 = WT[(int64_t)(i + 3) * nout + j];
-#pragma unroll
-                    for (int t = 0; t < CH; ++t) {
-                        const float4 a = *reinterpret_cast<const float4 *>(&act[cur_buf][t][i]);
-                        acc[t] = fmaf(w0, a.x, acc[t]);
-                        acc[t] = fmaf(w1, a.y, acc[t]);
-                        acc[t] = fmaf(w2, a.z, acc[t]);
-                        acc[t] = fmaf(w3, a.w, acc[t]);
-                    }
-                }
-                for (; i < nin; ++i) {
-                    const float w = WT[(int64_t)i * nout + j];
-#pragma unroll
-                    for (int t = 0; t < CH; ++t) acc[t] = fmaf(w, act[cur_buf][t][i], acc[t]);
-                }
-#pragma unroll
-                for (int t = 0; t < CH; ++t) act[cur_buf ^ 1][t][j] = (l < net.L) ? sigmoidf(acc[t]) : acc[t];
-            }
-            __syncthreads();
-            cur_buf ^= 1;
-        }
-        // decisions: one thread per point
-        if (tid < CH && s_valid[tid]) {
-            const float *z = act[cur_buf][tid];
-            const int nc = net.dims[net.L];
-            int best = 0;
-            for (int j = 1; j < nc; ++j) if (z[j] > z[best]) best = j;
-            float second = -INFINITY;
-            for (int j = 0; j < nc; ++j) if (j != best && z[j] > second) second = z[j];
-            const float margin = z[best] - second;
-            const float scale = fmaxf(1.0f, fabsf(z[best]));
-            const bool near = margin <= P.tie_rel * scale;
-            const bool viol = best != pr.label0;
-            if (near) {
-                atomicAdd(P.slot_ties + c.slot, 1ull);
-                const unsigned long long idx = atomicAdd(P.tie_count, 1ull);
-                if ((int64_t)idx < P.tie_cap) {
-                    DevRec r;
-                    r.rank = point_rank(c, P, s_p[tid], s_i[tid]);
-                    r.prop = c.prop;
-                    r.klab = (c.k << 24) | best;
-                    P.ties[idx] = r;
-                }
-            }
-            if (viol) {
-                atomicAdd(P.slot_cex + c.slot, 1ull);
-                const unsigned long long idx = atomicAdd(P.rec_count, 1ull);
-                if ((int64_t)idx < P.rec_cap) {
-                    DevRec r;
-                    r.rank = point_rank(c, P, s_p[tid], s_i[tid]);
-                    r.prop = c.prop;
-                    r.klab = (c.k << 24) | best;
-                    P.recs[idx] = r;
-                }
-            }
-        }
-        __syncthreads();
-        cur++;
-        if (cur < end && cursor_next<CH, FEnumParams>(c, P)) have = false;
-    }
-}
-
-int enum_f32_chunk() { return kF32Chunk; }
 
 hipError_t launch_forward_f32(const FNetDev &net, const uint8_t *images, int64_t n_images, int32_t *labels,
                               float *pots, int64_t pot_stride, hipStream_t s) {
@@ -277,14 +127,6 @@ hipError_t launch_forward_f32(const FNetDev &net, const uint8_t *images, int64_t
     const int grid = (int)std::min<int64_t>(n_images, 4096);
     hipLaunchKernelGGL(forward_f32_kernel, dim3(grid), dim3(256), 0, s, net, images, n_images, labels, pots,
                        pot_stride);
-    return hipGetLastError();
-}
-
-hipError_t launch_clean_f32(const FNetDev &net, PropDev *props, const int32_t *prop_ids, int32_t n_ids,
-                            float *u0_store, int64_t u0_stride, hipStream_t s) {
-    if (n_ids <= 0) return hipSuccess;
-    hipLaunchKernelGGL(clean_f32_kernel, dim3(std::min(n_ids, 4096)), dim3(256), 0, s, net, props, prop_ids, n_ids,
-                       u0_store, u0_stride);
     return hipGetLastError();
 }
 
@@ -296,9 +138,322 @@ hipError_t launch_replay_f32(const FNetDev &net, const uint8_t *clean, const int
     return hipGetLastError();
 }
 
-hipError_t launch_enum_f32(int grid, const FEnumParams &P, const int32_t *u0_index, hipStream_t s) {
-    hipLaunchKernelGGL(enum_f32_kernel, dim3(grid), dim3(256), 0, s, P, u0_index);
+// ---------------------------------------------------------------------------
+// sixteen points per wave (wide networks)
+// ---------------------------------------------------------------------------
+
+// LDS of one wave: activations of 16 points in two buffers [16][wp], logits
+// [16][64].
+__host__ __device__ inline int wide_wp(const FNetDev &net) {
+    int wp = 64;
+    for (int l = 1; l < net.L; ++l) wp = max(wp, net.HP[l]);
+    return wp;
+}
+static size_t wide_lds_bytes(const FNetDev &net) { return (size_t)(2 * 16 * wide_wp(net) + 16 * 64) * 4; }
+
+// Cross-lane exchange through this wave's LDS: earlier writes complete
+// before later reads.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Layers >= 2 of 16 points (lanes = units, 64 at a time) from the
+// first-layer activations in act0 [16][wp]; logits to zs [16][64].
+__device__ void wide_upper(const FNetDev &net, float *act0, float *act1, float *zs, int wp, int lane) {
+    float *in = act0, *out = act1;
+    for (int l = 2; l <= net.L; ++l) {
+        const int nin = net.HP[l - 1], nout = net.HP[l];
+        const float *W = net.WP[l];
+        const float *B = net.bP[l];
+        const bool last = l == net.L;
+        for (int jb = 0; jb < nout; jb += 64) {
+            const int j = jb + lane;
+            float tot[16];
+            const float bj = B[j];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) tot[t] = bj;
+            for (int ib = 0; ib < nin; ib += kF32SumBlock) {
+                float part[16];
+#pragma unroll
+                for (int t = 0; t < 16; ++t) part[t] = 0.0f;
+#pragma unroll 2
+                for (int i = ib; i < ib + kF32SumBlock; i += 4) {
+                    const float w0 = W[(int64_t)(i + 0) * nout + j], w1 = W[(int64_t)(i + 1) * nout + j];
+                    const float w2 = W[(int64_t)(i + 2) * nout + j], w3 = W[(int64_t)(i + 3) * nout + j];
+#pragma unroll
+                    for (int t = 0; t < 16; ++t) {
+                        const float4 a = *reinterpret_cast<const float4 *>(in + t * wp + i);
+                        part[t] = fmaf(w0, a.x, part[t]);
+                        part[t] = fmaf(w1, a.y, part[t]);
+                        part[t] = fmaf(w2, a.z, part[t]);
+                        part[t] = fmaf(w3, a.w, part[t]);
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < 16; ++t) tot[t] += part[t];
+            }
+            if (!last) {
+#pragma unroll
+                for (int t = 0; t < 16; ++t) out[t * wp + j] = sigmoid_f32(tot[t]);
+            } else {
+#pragma unroll
+                for (int t = 0; t < 16; ++t) zs[t * 64 + j] = tot[t];
+            }
+        }
+        wave_lds_sync();
+        float *tmp = in;
+        in = out;
+        out = tmp;
+    }
+}
+
+// Decision of point `lane` (< 16) from the logits in zs.
+__device__ __forceinline__ void wide_decide(const float *zs, int nc, int lane, int &best, float &top, float &margin) {
+    const float *z = zs + (lane & 15) * 64;
+    best = 0;
+    top = z[0];
+    for (int j = 1; j < nc; ++j)
+        if (z[j] > top) { top = z[j]; best = j; }
+    float second = -INFINITY;
+    for (int j = 0; j < nc; ++j)
+        if (j != best) second = fmaxf(second, z[j]);
+    margin = top - second;
+}
+
+__global__ void __launch_bounds__(64) enum_f32_wide_kernel(FEnumParams P) {
+    constexpr int CH = kF32WideChunk;
+    extern __shared__ __attribute__((aligned(16))) float wlds[];
+    const FNetDev &net = P.net;
+    const int wp = wide_wp(net), hp1 = net.HP[1], nc = net.dims[net.L];
+    float *act0 = wlds, *act1 = wlds + 16 * wp, *zs = wlds + 32 * wp;
+    const int lane = __lane_id();
+    Cursor c;
+    int64_t cur = 0, end = 0;
+    while (true) {
+        if (cur >= end) {
+            const int64_t start = f32_ticket(P);
+            if (start < 0) break;
+            cur = start;
+            end = min(start + (int64_t)P.batch, P.total_chunks);
+            cursor_decode<CH, FEnumParams>(c, P, cur);
+        }
+        int pp[kMaxK];
+        float ee[kMaxK];
+        const int np = c.k - 1;
+#pragma unroll
+        for (int t = 0; t < kMaxK; ++t) {
+            pp[t] = 0;
+            ee[t] = 0.0f;
+            if (t < np) {
+                pp[t] = c.pre[t];
+                const int xv = wave_uniform((int)gld(c.img + pp[t]));
+                ee[t] = eff_delta(xv, wave_uniform((int)gld(c.dl + c.dg[t])));
+            }
+        }
+        int p = 0, i = 0;
+        const bool valid = last_element32<FEnumParams>(c, P, (int)(c.ch * CH) + (lane & 15), p, i) && lane < 16;
+        const float e = eff_delta((int)gld(c.img + p), (int)gld(c.dl + i));
+        // first layer: the shared prefix once per unit, then each point's last pixel
+        const float *u0 = P.u0f + (int64_t)c.prop * P.u0_stride;
+        for (int jb = 0; jb < hp1; jb += 64) {
+            const int j = jb + lane;
+            float vb = u0[j];
+#pragma unroll
+            for (int t = 0; t < kMaxK - 1; ++t)
+                if (t < np) vb = fmaf(ee[t], net.W1P[(int64_t)pp[t] * hp1 + j], vb);
+#pragma unroll 4
+            for (int t = 0; t < 16; ++t) {
+                const int pt = __builtin_amdgcn_readlane(p, t);
+                const float et = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(e), t));
+                act0[t * wp + j] = sigmoid_f32(fmaf(et, net.W1P[(int64_t)pt * hp1 + j], vb));
+            }
+        }
+        wave_lds_sync();
+        wide_upper(net, act0, act1, zs, wp, lane);
+        int best;
+        float top, margin;
+        wide_decide(zs, nc, lane, best, top, margin);
+        wave_lds_sync();   // the logits are read before the next chunk overwrites them
+        const int label0 = wave_uniform(gld(&P.props[c.prop].label0));
+        const bool near = valid && margin <= P.tie_rel * fmaxf(1.0f, fabsf(top));
+        const bool viol = valid && best != label0;
+        emit_f32(P, c, viol, near, p, i, best);
+        cur++;
+        if (cur < end) cursor_next<CH, FEnumParams>(c, P);
+    }
+}
+
+// Listed points, sixteen per wave, through the same arithmetic: each point's
+// first-layer potentials start from u0 and take its prefix pixels in
+// ascending order, then its last pixel.
+__global__ void __launch_bounds__(64) eval_f32_wide_kernel(F32EvalParams E) {
+    extern __shared__ __attribute__((aligned(16))) float wlds[];
+    const FNetDev &net = E.net;
+    const int wp = wide_wp(net), hp1 = net.HP[1], nc = net.dims[net.L];
+    float *act0 = wlds, *act1 = wlds + 16 * wp, *zs = wlds + 32 * wp;
+    const int lane = __lane_id();
+    const int64_t t0 = (int64_t)blockIdx.x * 16 + (lane & 15);
+    const bool ok = lane < 16 && t0 < E.n;
+    const int64_t tt = t0 < E.n ? t0 : 0;
+    const int prop = E.prop_of ? E.prop_of[tt] : 0;
+    const PropDev &pr = E.props[prop];
+    const int k = E.label_props ? 0 : E.ks[tt];
+    const int64_t rank = E.label_props ? 0 : E.ranks[tt];
+    int pix[kMaxK], dig[kMaxK];
+    decode_point_dev(pr.n, pr.m, k, rank, pix, dig);
+    int pp[kMaxK];
+    float ee[kMaxK];
+    const int np = k > 0 ? k - 1 : 0;
+    int p = 0;
+    float e = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j) {
+        pp[j] = 0;
+        ee[j] = 0.0f;
+        if (j < np) { pp[j] = pix[j]; ee[j] = eff_delta(pr.image[pix[j]], pr.deltas[dig[j]]); }
+        if (k > 0 && j == k - 1) { p = pix[j]; e = eff_delta(pr.image[pix[j]], pr.deltas[dig[j]]); }
+    }
+    for (int jb = 0; jb < hp1; jb += 64) {
+        const int j = jb + lane;
+        for (int t = 0; t < 16; ++t) {
+            const int pt = __builtin_amdgcn_readlane(prop, t);
+            float v = E.u0f[(int64_t)pt * E.u0_stride + j];
+            const int npt = __builtin_amdgcn_readlane(np, t);
+#pragma unroll
+            for (int q = 0; q < kMaxK - 1; ++q)
+                if (q < npt) {
+                    const int ppq = __builtin_amdgcn_readlane(pp[q], t);
+                    const float eeq = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ee[q]), t));
+                    v = fmaf(eeq, net.W1P[(int64_t)ppq * hp1 + j], v);
+                }
+            const int ptl = __builtin_amdgcn_readlane(p, t);
+            const float et = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(e), t));
+            act0[t * wp + j] = sigmoid_f32(fmaf(et, net.W1P[(int64_t)ptl * hp1 + j], v));
+        }
+    }
+    wave_lds_sync();
+    wide_upper(net, act0, act1, zs, wp, lane);
+    int best;
+    float top, margin;
+    wide_decide(zs, nc, lane, best, top, margin);
+    if (!ok) return;
+    if (E.label_props) {
+        E.label_props[prop].label0 = best;
+        E.label_props[prop].tie0 = 0;
+        return;
+    }
+    if (E.logits)
+        for (int j = 0; j < nc; ++j) E.logits[tt * nc + j] = zs[lane * 64 + j];
+    if (E.labels) E.labels[tt] = best;
+    if (E.margins) E.margins[tt] = margin;
+}
+
+// ---------------------------------------------------------------------------
+// layouts, dispatch, launchers
+// ---------------------------------------------------------------------------
+
+static int lane_class(int h) {
+    for (int c : {16, 32, 64, 128})
+        if (h <= c) return c;
+    return 0;
+}
+
+static const F32LaneVariant *find_lane(int L, const int *HP) {
+    int n2 = 0, n3 = 0;
+    const F32LaneVariant *v2 = f32_lane_variants_l2(&n2), *v3 = f32_lane_variants_l3(&n3);
+    if (L == 2)
+        for (int i = 0; i < n2; ++i)
+            if (v2[i].h1 == HP[1] && v2[i].ncp == HP[2]) return &v2[i];
+    if (L == 3)
+        for (int i = 0; i < n3; ++i)
+            if (v3[i].h1 == HP[1] && v3[i].h2 == HP[2] && v3[i].ncp == HP[3]) return &v3[i];
+    return nullptr;
+}
+
+bool f32_lane_supported(int L, const int *HP) { return find_lane(L, HP) != nullptr; }
+
+F32Layout f32_layout(int L, const int *dims) {
+    F32Layout lay{};
+    lay.HP[0] = dims[0];
+    bool lane = (L == 2 || L == 3) && dims[L] <= 16;
+    for (int l = 1; l < L && lane; ++l) {
+        lay.HP[l] = lane_class(dims[l]);
+        if (lay.HP[l] == 0) lane = false;
+    }
+    if (lane) {
+        lay.HP[L] = dims[L] <= 8 ? 8 : 16;
+        if (!find_lane(L, lay.HP)) lane = false;
+    }
+    if (lane) {
+        lay.kind = F32_LANE;
+        return lay;
+    }
+    lay.kind = F32_WIDE;
+    for (int l = 1; l < L; ++l) lay.HP[l] = round_up(dims[l], 64);
+    lay.HP[L] = 64;
+    return lay;
+}
+
+int enum_f32_chunk(const FNetDev &net) { return net.kind == F32_LANE ? kF32LaneChunk : kF32WideChunk; }
+
+int f32_enum_grid(const FNetDev &net, int n_cu) {
+    int occ = 0;
+    if (net.kind == F32_LANE) {
+        const F32LaneVariant *v = find_lane(net.L, net.HP);
+        if (!v || hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, v->enum_fn, 256, 0) != hipSuccess) return 0;
+        return std::max(occ, 1) * n_cu * kLaneWaves;
+    }
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, enum_f32_wide_kernel, 64, wide_lds_bytes(net)) !=
+        hipSuccess)
+        return 0;
+    return std::max(occ, 1) * n_cu;
+}
+
+hipError_t launch_enum_f32(int grid_waves, const FEnumParams &P, hipStream_t s) {
+    if (P.net.kind == F32_LANE) {
+        const F32LaneVariant *v = find_lane(P.net.L, P.net.HP);
+        if (!v) return hipErrorInvalidValue;
+        FEnumParams a = P;
+        void *args[] = {&a};
+        return hipLaunchKernel(v->enum_fn, dim3((grid_waves + kLaneWaves - 1) / kLaneWaves), dim3(256), args, 0, s);
+    }
+    hipLaunchKernelGGL(enum_f32_wide_kernel, dim3(grid_waves), dim3(64), wide_lds_bytes(P.net), s, P);
     return hipGetLastError();
+}
+
+hipError_t launch_eval_f32(const F32EvalParams &E, hipStream_t s) {
+    if (E.n <= 0) return hipSuccess;
+    if (E.net.kind == F32_LANE) {
+        const F32LaneVariant *v = find_lane(E.net.L, E.net.HP);
+        if (!v) return hipErrorInvalidValue;
+        F32EvalParams a = E;
+        void *args[] = {&a};
+        return hipLaunchKernel(v->eval_fn, dim3((unsigned)((E.n + 255) / 256)), dim3(256), args, 0, s);
+    }
+    hipLaunchKernelGGL(eval_f32_wide_kernel, dim3((unsigned)((E.n + 15) / 16)), dim3(64), wide_lds_bytes(E.net), s, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_clean_f32(const FNetDev &net, PropDev *props, const int32_t *prop_ids, int32_t n_ids,
+                            float *u0_store, int64_t u0_stride, hipStream_t s) {
+    if (n_ids <= 0) return hipSuccess;
+    hipLaunchKernelGGL(clean_u0_f32_kernel, dim3(std::min(n_ids, 4096)), dim3(256), 0, s, net, props, prop_ids, n_ids,
+                       u0_store, u0_stride);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // the clean label through the enumeration's own arithmetic (a point with
+    // no changed pixel), so that a zero perturbation reproduces it exactly
+    F32EvalParams E{};
+    E.net = net;
+    E.props = props;
+    E.label_props = props;
+    E.prop_of = prop_ids;
+    E.n = n_ids;
+    E.u0f = u0_store;
+    E.u0_stride = (int32_t)u0_stride;
+    return launch_eval_f32(E, s);
 }
 
 }  // namespace ibmc

@@ -121,6 +121,7 @@ SIGNATURES = {
     "ibmc_decode_point": (I32, [I32, I32, I32, I64, P_I32, P_I32]),
     "ibmc_replay": (I32, [VP, VP, P_U8, P_I16, I32, P_CEX, I64, P_I32]),
     "ibmc_forward": (I32, [VP, VP, P_U8, I64, VP, P_I32]),
+    "ibmc_eval_points_f32": (I32, [VP, VP, P_U8, P_I16, I32, P_I32, P_I64, I64, P_F32, P_I32, P_F32, P_I32]),
     "ibmc_coverage": (I32, [VP, VP, P_U8, P_U8, I64, I32, P_COVP, P_COVS, P_U64]),
     "ibmc_coverage_dev": (I32, [VP, VP, VP, VP, I64, I32, P_COVP, P_COVS, P_U64]),
     "ibmc_coverage_all_dev": (I32, [VP, VP, VP, VP, I64, P_COVP, P_COVS, P_U64]),
@@ -401,6 +402,25 @@ def ibmc_forward(ctx, net, images, want_potentials=True):
     _ck(lib().ibmc_forward(ctx.handle, net.handle, _ptr(images, P_U8), n,
                            pots.ctypes.data if pots is not None else None, _ptr(labels, P_I32)))
     return (pots, labels) if want_potentials else labels
+
+
+def ibmc_eval_points_f32(ctx, net, image, deltas, ks, ranks):
+    """Logits [n][classes], labels, margins and the clean label of listed
+    points of a float network, by the float enumeration's own arithmetic."""
+    image = np.ascontiguousarray(image, np.uint8)
+    D = np.ascontiguousarray(deltas, np.int16)
+    ks = np.ascontiguousarray(ks, np.int32)
+    ranks = np.ascontiguousarray(ranks, np.int64)
+    n = ks.size
+    nc = net.dims[-1]
+    logits = np.zeros((max(n, 1), nc), np.float32)
+    labels = np.zeros(max(n, 1), np.int32)
+    margins = np.zeros(max(n, 1), np.float32)
+    clean = I32()
+    _ck(lib().ibmc_eval_points_f32(ctx.handle, net.handle, _ptr(image, P_U8), _ptr(D, P_I16), D.size,
+                                   _ptr(ks, P_I32), _ptr(ranks, P_I64), n, _ptr(logits, P_F32), _ptr(labels, P_I32),
+                                   _ptr(margins, P_F32), C.byref(clean)))
+    return logits[:n], labels[:n], margins[:n], clean.value
 
 
 def ibmc_abort(ctx):

@@ -216,8 +216,9 @@ def batch_workload(seed: int = 3, per_net: int = 32, mac_budget: float = 2e12):
 
     The delta set is drawn from DELTA_MENU.  A property whose plain-enumeration
     cost (points up to level k times the dense forward MACs) exceeds the budget
-    first loses the pair of largest-|d| deltas, and once only two deltas are
-    left, one level of k.
+    first loses the pair of largest-|d| deltas while at least two deltas
+    remain after the drop, then one level of k; a property still over budget
+    at k = 1 stays as it is.
     """
     g = rng(seed)
     nets = [random_qnet(g, dims, shift=7) for dims in BATCH_TOPOLOGIES]
@@ -234,9 +235,10 @@ def batch_workload(seed: int = 3, per_net: int = 32, mac_budget: float = 2e12):
                 img = blob_images(g, 1, r)[0]
             macs = net.dense_macs()
             while sum(point_count(n, len(D), j) for j in range(1, k + 1)) * macs > mac_budget:
-                if len(D) > 2:
-                    big = max(abs(d) for d in D)
-                    D = [d for d in D if abs(d) != big] if sum(abs(d) == big for d in D) < len(D) else D[:2]
+                big = max(abs(d) for d in D)
+                rest = [d for d in D if abs(d) != big]
+                if len(rest) >= 2:
+                    D = rest
                 elif k > 1:
                     k -= 1
                 else:

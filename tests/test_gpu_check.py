@@ -178,6 +178,41 @@ def test_load_errors(ctx):
     with pytest.raises(ibmc.IbmcError) as e:
         ibmc.Mlp(ctx, rng_net)
     assert e.value.code == ibmc.IBMC_E_RANGE
+    # shifts above 24 are refused (the kernels hold u - 64 * 2^s in int32)
+    g = I.rng(3)
+    with pytest.raises(ibmc.IbmcError) as e:
+        ibmc.Mlp(ctx, I.random_qnet(g, [8, 16, 4], shift=25, wmax=8, bmax=8))
+    assert e.value.code == ibmc.IBMC_E_INVALID
+    # shift 24 with a bias of 2^30: |b| + 64 * 2^24 reaches 2^31 although
+    # |b| + 255 sum|w| alone does not
+    off = I.QNet([2, 2, 2], [np.ones((2, 2), np.int8), np.ones((2, 2), np.int8)],
+                 [np.array([2**30, 0], np.int32), np.zeros(2, np.int32)], [24])
+    with pytest.raises(ibmc.IbmcError) as e:
+        ibmc.Mlp(ctx, off)
+    assert e.value.code == ibmc.IBMC_E_RANGE
+
+
+@pytest.mark.parametrize("seed,dims,shifts,bmax", [
+    (42, [48, 64, 32, 6], [11, 9], 1 << 16),
+    (59, [48, 64, 32, 6], [11, 9], 1 << 16),
+    (7, [16, 32, 5], [24], 1 << 29),
+])
+def test_natural_large_shift(ctx, orc, seed, dims, shifts, bmax):
+    """Shifts above 8 take the int32 first-layer path and the general
+    requantiser on their own (no forcing); up to the largest accepted shift
+    the records equal the oracle's."""
+    from paper_1907_12933_amd import ibmc
+    g = I.rng(seed)
+    net = I.random_qnet(g, dims, shift=12, wmax=127, bmax=bmax)
+    net.shift = list(shifts)
+    x = g.integers(0, 255, size=dims[0], endpoint=True).astype(np.uint8)
+    D = np.array([-255, -128, 128, 255], np.int16)
+    m = ibmc.Mlp(ctx, net)
+    s, cex, _ = ibmc.ibmc_check_property(ctx, m, x, D, 0, 2)
+    r = orc.q8_check(net, x, D, 0, 2)
+    assert_same(s, cex, r)
+    if seed in (42, 59):
+        assert r["cex_total"] > 0
 
 
 def test_general_first_layer_path(orc, monkeypatch):

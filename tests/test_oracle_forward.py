@@ -87,3 +87,57 @@ def test_euclid_worked_example(orc):
     q[flip] = 1.0 - q[flip]
     assert abs(orc.euclid(p, q) - 2.449) < 5e-4
     assert orc.euclid(p, p) == 0.0
+
+
+def numpy_f64(net, X):
+    """Logits of images X [B][n] by numpy's float64 matmul and exp."""
+    a = X.astype(np.float64) / 256.0
+    for l, (W, b) in enumerate(zip(net.W, net.b)):
+        u = a @ np.asarray(W, np.float64).T + np.asarray(b, np.float64)
+        a = 1.0 / (1.0 + np.exp(-u)) if l < len(net.W) - 1 else u
+    return a
+
+
+@pytest.mark.parametrize("dims", [[6, 8, 4], [7, 5, 6, 3], [6, 9, 4, 4, 2]])
+def test_f64_eval_points_matches_numpy(orc, dims):
+    """orc_f64_eval_points: every point of levels 0..3, decoded here by
+    itertools' lexicographic order and applied with numpy, gives numpy's
+    float64 logits, the lowest-index argmax and the top-2 margin."""
+    import itertools
+    g = I.rng(23)
+    net = I.fnet_from_qnet(I.random_qnet(g, dims, shift=7))
+    n = dims[0]
+    x = g.integers(0, 255, size=n, endpoint=True).astype(np.uint8)
+    D = np.array([-200, -5, 0, 60], np.int16)
+    ks, ranks, imgs = [], [], []
+    for k in range(0, 4):
+        rank = 0
+        for S in itertools.combinations(range(n), k):
+            for dig in itertools.product(range(len(D)), repeat=k):
+                xp = x.astype(np.int64).copy()
+                for p, i in zip(S, dig):
+                    xp[p] = min(max(int(x[p]) + int(D[i]), 0), 255)
+                ks.append(k); ranks.append(rank); imgs.append(xp)
+                rank += 1
+    labels, logits, margins = orc.f64_eval_points(net, x, D, ks, ranks)
+    ref = numpy_f64(net, np.array(imgs))
+    assert np.allclose(logits, ref, rtol=1e-12, atol=1e-12)
+    assert np.array_equal(labels, np.argmax(ref, axis=1))
+    srt = np.sort(ref, axis=1)
+    assert np.allclose(margins, srt[:, -1] - srt[:, -2], rtol=1e-9, atol=1e-12)
+
+
+def test_f64_eval_points_closed_form(orc):
+    """The O3 net (identity first layer, logits +-(a0 - a1) with
+    a = sigmoid(x / 256)): margin 2 |a0 - a1|, class 0 iff x0' >= x1'."""
+    net = I.FNet([2, 2, 2], [np.eye(2), np.array([[1.0, -1.0], [-1.0, 1.0]])], [np.zeros(2), np.zeros(2)])
+    x = np.array([100, 90], np.uint8)
+    D = np.arange(-16, 17, dtype=np.int16)
+    ranks = np.arange(33 * 33)
+    labels, logits, margins = orc.f64_eval_points(net, x, D, np.full(ranks.size, 2), ranks)
+    d0, d1 = np.divmod(ranks, 33)
+    x0, x1 = 100 + D[d0].astype(np.int64), 90 + D[d1].astype(np.int64)
+    sig = lambda v: 1.0 / (1.0 + np.exp(-v / 256.0))
+    assert np.array_equal(labels, np.where(x0 >= x1, 0, 1))
+    assert np.allclose(margins, 2 * np.abs(sig(x0) - sig(x1)), rtol=1e-12, atol=1e-15)
+    assert np.allclose(logits[:, 0], sig(x0) - sig(x1), rtol=1e-12, atol=1e-15)
