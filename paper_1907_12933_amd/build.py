@@ -28,13 +28,28 @@ def _compile(src):
     return obj, msgs
 
 
+def _deps(path, seen=None):
+    """path and every project header it includes, transitively."""
+    import re
+    seen = set() if seen is None else seen
+    if path in seen:
+        return seen
+    seen.add(path)
+    for name in re.findall(r'#include\s+"([^"]+)"', open(path).read()):
+        for d in (CSRC, INCLUDE):
+            cand = os.path.join(d, name)
+            if os.path.exists(cand):
+                _deps(cand, seen)
+                break
+    return seen
+
+
 def _fresh(src):
-    """The object of src is newer than src and every header it could include."""
+    """The object of src is newer than src and every header it includes."""
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
     if not os.path.exists(obj):
         return False
-    deps = [src] + glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(INCLUDE, "*.h"))
-    return os.path.getmtime(obj) > max(os.path.getmtime(d) for d in deps)
+    return os.path.getmtime(obj) > max(os.path.getmtime(d) for d in _deps(src))
 
 
 def build(verbose: bool = False, jobs: int = 6, incremental: bool = False) -> str:

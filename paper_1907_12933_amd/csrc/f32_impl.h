@@ -42,6 +42,14 @@ __device__ __forceinline__ float sigmoid_f32(float u) {
     return __builtin_amdgcn_rcpf(1.0f + e);
 }
 
+// Cross-lane exchange through this wave's LDS: earlier writes complete
+// before later reads.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ float eff_delta(int xv, int d) {
     return (float)(clamp_pixel(xv + d) - xv) * (1.0f / 256.0f);
 }
@@ -111,18 +119,47 @@ __device__ __forceinline__ void emit_f32(const FEnumParams &P, const Cursor &c, 
     }
 }
 
-// Next queue ticket of a persistent wave: the first chunk of a batch of
-// P.batch, or -1 when the queue is drained or a stop / abort was requested.
-__device__ __forceinline__ int64_t f32_ticket(const FEnumParams &P) {
-    unsigned long long t = 0;
-    int stop = 0;
-    if (__lane_id() == 0) {
-        t = atomicAdd(P.queue, (unsigned long long)P.batch);
-        stop = *P.stop_flag || (P.abort_host && *P.abort_host);
+// Tickets between two reads of the host's abort request by one wave (a read
+// of host memory crosses PCIe; one per ticket from every wave saturated it).
+constexpr int kAbortPollTickets = 64;
+
+// Next queue ticket of a persistent wave: [start, end) of at most P.batch
+// chunks from the wave's current slice q; a drained slice sends the wave to
+// the next one (tries counts the slices visited).  Returns -1 when every
+// slice is drained or a stop / abort was requested.  The device stop flag is
+// read per ticket, the host abort request every kAbortPollTickets tickets
+// (polls counts them); a wave that sees the abort raises the stop flag.
+__device__ __forceinline__ int64_t f32_ticket(const FEnumParams &P, int &q, int &tries, int64_t &end, int &polls) {
+    while (tries < kF32Queues) {
+        const int64_t lo = (int64_t)q * P.slice;
+        const int64_t hi = min(lo + P.slice, P.total_chunks);
+        unsigned long long t = 0;
+        int stop = 0;
+        const bool poll_host = P.abort_host && (polls++ % kAbortPollTickets) == 0;
+        if (__lane_id() == 0) {
+            if (lo < hi) t = atomicAdd(P.queue + (int64_t)q * kQueueStride, (unsigned long long)P.batch);
+            stop = *P.stop_flag;
+            if (poll_host && *P.abort_host) {
+                stop = 1;
+                *P.stop_flag = 1;
+            }
+        }
+        if (wave_uniform(stop)) return -1;
+        const int64_t start = lo + (int64_t)wave_uniform(t);
+        if (lo < hi && start < hi) {
+            end = min(start + (int64_t)P.batch, hi);
+            return start;
+        }
+        q = q + 1 == kF32Queues ? 0 : q + 1;
+        tries++;
     }
-    const int64_t start = (int64_t)wave_uniform(t);
-    if (wave_uniform(stop) || start >= P.total_chunks) return -1;
-    return start;
+    return -1;
+}
+
+// The first slice of a wave: waves are spread evenly over the slices.
+__device__ __forceinline__ int f32_first_slice() {
+    const int w = (int)((blockIdx.x * (blockDim.x >> 6)) + (threadIdx.x >> 6));
+    return w % kF32Queues;
 }
 
 // Decode point (k, rank) of a property: ascending pixels and delta indices.
@@ -145,155 +182,201 @@ __device__ __forceinline__ void decode_point_dev(int n, int m, int k, int64_t ra
 
 constexpr int kLaneWaves = 4;  // waves per workgroup of the lane kernels
 
-// Logits of the lane's point.  u0: the property's clean first-layer
-// potentials [H1]; np prefix elements (pixel pp[t], effective delta ee[t]),
-// then the last pixel p with effective delta e.  a2w: this wave's LDS
-// columns of the second hidden layer ([H2][64]); each lane touches only its
+// Layers >= 2 of the lane's point from its first-layer activations a1.
+// a2w: this wave's LDS columns ([H2][64] of the second hidden layer, or
+// [NCP][64] of the logits with one hidden layer); each lane touches only its
 // own column.
 template <int H1, int H2, int NCP>
-__device__ __forceinline__ void lane_logits(const FNetDev &net, const float *u0, int np, const int (&pp)[kMaxK],
-                                            const float (&ee)[kMaxK], int p, float e, float *a2w, int lane,
-                                            float (&z)[NCP]) {
-    float a1[H1];
-    {
-        float v[H1];
-#pragma unroll
-        for (int j = 0; j < H1; ++j) v[j] = cld(u0 + j);
-#pragma unroll
-        for (int t = 0; t < kMaxK - 1; ++t) {
-            if (t < np) {
-                const float *row = net.W1P + (int64_t)pp[t] * H1;
-#pragma unroll
-                for (int j = 0; j < H1; ++j) v[j] = fmaf(ee[t], cld(row + j), v[j]);
-            }
-        }
-        const float4 *w1 = reinterpret_cast<const float4 *>(net.W1P + (int64_t)p * H1);
-#pragma unroll
-        for (int j4 = 0; j4 < H1 / 4; ++j4) {
-            const float4 w = w1[j4];
-            a1[4 * j4 + 0] = sigmoid_f32(fmaf(e, w.x, v[4 * j4 + 0]));
-            a1[4 * j4 + 1] = sigmoid_f32(fmaf(e, w.y, v[4 * j4 + 1]));
-            a1[4 * j4 + 2] = sigmoid_f32(fmaf(e, w.z, v[4 * j4 + 2]));
-            a1[4 * j4 + 3] = sigmoid_f32(fmaf(e, w.w, v[4 * j4 + 3]));
-        }
-    }
+__device__ __forceinline__ void lane_upper(const FNetDev &net, const float (&a1)[H1], float *a2w, int lane,
+                                           float (&z)[NCP]) {
     if constexpr (H2 == 0) {
         const float *W = opaque(net.WP[2]);
         const float *B = opaque(net.bP[2]);
-#pragma unroll
-        for (int j = 0; j < NCP; ++j) z[j] = cld(B + j);
-#pragma unroll
-        for (int ib = 0; ib < H1; ib += kF32SumBlock) {
-            float part[NCP];
-#pragma unroll
-            for (int j = 0; j < NCP; ++j) part[j] = 0.0f;
-#pragma unroll
-            for (int i = ib; i < ib + kF32SumBlock && i < H1; ++i)
-#pragma unroll
-                for (int j = 0; j < NCP; ++j) part[j] = fmaf(cld(W + i * NCP + j), a1[i], part[j]);
-#pragma unroll
-            for (int j = 0; j < NCP; ++j) z[j] += part[j];
-        }
-    } else {
-        const float *W2 = opaque(net.WP[2]);
-        const float *B2 = opaque(net.bP[2]);
-        // second hidden layer, 16 units per step, into this lane's LDS column
+        // eight classes per step (eight scalar weights per input in flight),
+        // each step's logits parked in this lane's LDS column
 #pragma unroll 1
-        for (int jb = 0; jb < H2; jb += 16) {
-            float tot[16];
+        for (int j0 = 0; j0 < NCP; j0 += 8) {
+            float tot[8];
 #pragma unroll
-            for (int jj = 0; jj < 16; ++jj) tot[jj] = cld(B2 + jb + jj);
+            for (int j = 0; j < 8; ++j) tot[j] = cld(B + j0 + j);
 #pragma unroll
             for (int ib = 0; ib < H1; ib += kF32SumBlock) {
-                float part[16];
+                float part[8];
 #pragma unroll
-                for (int jj = 0; jj < 16; ++jj) part[jj] = 0.0f;
+                for (int j = 0; j < 8; ++j) part[j] = 0.0f;
 #pragma unroll
                 for (int i = ib; i < ib + kF32SumBlock && i < H1; ++i)
 #pragma unroll
-                    for (int jj = 0; jj < 16; ++jj) part[jj] = fmaf(cld(W2 + i * H2 + jb + jj), a1[i], part[jj]);
+                    for (int j = 0; j < 8; ++j) part[j] = fmaf(cld(W + i * NCP + j0 + j), a1[i], part[j]);
 #pragma unroll
-                for (int jj = 0; jj < 16; ++jj) tot[jj] += part[jj];
+                for (int j = 0; j < 8; ++j) tot[j] += part[j];
             }
 #pragma unroll
-            for (int jj = 0; jj < 16; ++jj) a2w[(jb + jj) * 64 + lane] = sigmoid_f32(tot[jj]);
+            for (int j = 0; j < 8; ++j) a2w[(j0 + j) * 64 + lane] = tot[j];
+        }
+#pragma unroll
+        for (int j = 0; j < NCP; ++j) z[j] = a2w[j * 64 + lane];
+    } else {
+        const float *W2 = opaque(net.WP[2]);
+        const float *B2 = opaque(net.bP[2]);
+        // second hidden layer, eight units per step, into this lane's LDS column
+#pragma unroll 1
+        for (int jb = 0; jb < H2; jb += 8) {
+            float tot[8];
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) tot[jj] = cld(B2 + jb + jj);
+#pragma unroll
+            for (int ib = 0; ib < H1; ib += kF32SumBlock) {
+                float part[8];
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) part[jj] = 0.0f;
+#pragma unroll
+                for (int i = ib; i < ib + kF32SumBlock && i < H1; ++i)
+#pragma unroll
+                    for (int jj = 0; jj < 8; ++jj) part[jj] = fmaf(cld(W2 + i * H2 + jb + jj), a1[i], part[jj]);
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) tot[jj] += part[jj];
+            }
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) a2w[(jb + jj) * 64 + lane] = sigmoid_f32(tot[jj]);
         }
         const float *W3 = opaque(net.WP[3]);
         const float *B3 = opaque(net.bP[3]);
 #pragma unroll
-        for (int j = 0; j < NCP; ++j) z[j] = cld(B3 + j);
+        for (int j0 = 0; j0 < NCP; j0 += 8) {
 #pragma unroll
-        for (int ib = 0; ib < H2; ib += kF32SumBlock) {
-            float part[NCP];
+            for (int j = 0; j < 8; ++j) z[j0 + j] = cld(B3 + j0 + j);
 #pragma unroll
-            for (int j = 0; j < NCP; ++j) part[j] = 0.0f;
+            for (int ib = 0; ib < H2; ib += kF32SumBlock) {
+                float part[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) part[j] = 0.0f;
 #pragma unroll 4
-            for (int i = ib; i < ib + (H2 < kF32SumBlock ? H2 : kF32SumBlock); ++i) {
-                const float a = a2w[i * 64 + lane];
+                for (int i = ib; i < ib + (H2 < kF32SumBlock ? H2 : kF32SumBlock); ++i) {
+                    const float a = a2w[i * 64 + lane];
 #pragma unroll
-                for (int j = 0; j < NCP; ++j) part[j] = fmaf(cld(W3 + i * NCP + j), a, part[j]);
+                    for (int j = 0; j < 8; ++j) part[j] = fmaf(cld(W3 + i * NCP + j0 + j), a, part[j]);
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j) z[j0 + j] += part[j];
             }
-#pragma unroll
-            for (int j = 0; j < NCP; ++j) z[j] += part[j];
         }
+    }
+}
+
+// First-layer potentials before the last pixel: v_j = u0_j, then one fma
+// per prefix element in ascending pixel order.
+__device__ __forceinline__ float prefix_potential_rt(const FNetDev &net, int h1p, const float *u0, int np,
+                                                     const int (&pp)[kMaxK], const float (&ee)[kMaxK], int j) {
+    float v = u0[j];
+#pragma unroll
+    for (int t = 0; t < kMaxK - 1; ++t)
+        if (t < np) v = fmaf(ee[t], net.W1P[(int64_t)pp[t] * h1p + j], v);
+    return v;
+}
+
+template <int H1>
+__device__ __forceinline__ float prefix_potential(const FNetDev &net, const float *u0, int np, const int (&pp)[kMaxK],
+                                                  const float (&ee)[kMaxK], int j) {
+    return prefix_potential_rt(net, H1, u0, np, pp, ee, j);
+}
+
+// The prefix of the cursor's segment: pixels and effective deltas (their
+// loads issued together).
+__device__ __forceinline__ void segment_prefix(const Cursor &c, int (&pp)[kMaxK], float (&ee)[kMaxK]) {
+    const int np = c.k - 1;
+    int xs[kMaxK], ds[kMaxK];
+#pragma unroll
+    for (int t = 0; t < kMaxK; ++t) {
+        xs[t] = 0;
+        ds[t] = 0;
+        if (t < np) { xs[t] = gld(c.img + c.pre[t]); ds[t] = gld(c.dl + c.dg[t]); }
+    }
+#pragma unroll
+    for (int t = 0; t < kMaxK; ++t) {
+        pp[t] = t < np ? c.pre[t] : 0;
+        ee[t] = t < np ? eff_delta(xs[t], ds[t]) : 0.0f;
     }
 }
 
 // Persistent enumeration, one point per lane; chunks of 64 consecutive
-// last-element positions of one segment (the prefix is the same for the
-// whole wave, so its loads go through the scalar cache).
+// last-element positions of one segment.  Per segment (all prefix pixels
+// fixed) the wave computes v_j before the last pixel once into its LDS slot;
+// per property it keeps the clean label in a register; a chunk then loads
+// only its own pixels, deltas and first-layer rows.
 template <int H1, int H2, int NCP>
 __global__ void __launch_bounds__(256) enum_f32_lane_kernel(FEnumParams P) {
     constexpr int CH = kF32LaneChunk;
-    __shared__ float a2s[kLaneWaves][H2 > 0 ? H2 : 1][64];
+    __shared__ float a2s[kLaneWaves][H2 > 0 ? H2 : NCP][64];
+    __shared__ __attribute__((aligned(16))) float bases[kLaneWaves][H1];
     const int lane = __lane_id();
     float *a2w = &a2s[threadIdx.x >> 6][0][0];
+    float *base = &bases[threadIdx.x >> 6][0];
     const int nc = P.net.dims[P.net.L];
     Cursor c;
     int64_t cur = 0, end = 0;
+    bool seg_new = true;
+    int prop_seen = -1, label0 = 0;
+    int q = f32_first_slice(), tries = 0, polls = 0;
     while (true) {
         if (cur >= end) {
-            const int64_t start = f32_ticket(P);
+            const int64_t start = f32_ticket(P, q, tries, end, polls);
             if (start < 0) break;
             cur = start;
-            end = min(start + (int64_t)P.batch, P.total_chunks);
             cursor_decode<CH, FEnumParams>(c, P, cur);
+            seg_new = true;
         }
-        int pp[kMaxK];
-        float ee[kMaxK];
-        const int np = c.k - 1;
-#pragma unroll
-        for (int t = 0; t < kMaxK; ++t) {
-            pp[t] = 0;
-            ee[t] = 0.0f;
-            if (t < np) {
-                pp[t] = c.pre[t];
-                const int xv = wave_uniform((int)gld(c.img + pp[t]));
-                ee[t] = eff_delta(xv, wave_uniform((int)gld(c.dl + c.dg[t])));
-            }
-        }
+        // the lane's point: its loads go out first
         int p = 0, i = 0;
         const bool valid = last_element32<FEnumParams>(c, P, (int)(c.ch * CH) + lane, p, i);
-        const float e = eff_delta((int)gld(c.img + p), (int)gld(c.dl + i));
+        const int xv = gld(c.img + p), dv = gld(c.dl + i);
+        float4 wrow[H1 / 4];
+        const float4 *w1 = reinterpret_cast<const float4 *>(P.net.W1P + (int64_t)p * H1);
+#pragma unroll
+        for (int j4 = 0; j4 < H1 / 4; ++j4) wrow[j4] = w1[j4];
+        if (c.prop != prop_seen) {
+            prop_seen = c.prop;
+            label0 = wave_uniform(gld(&P.props[c.prop].label0));
+        }
+        if (seg_new) {
+            int pp[kMaxK];
+            float ee[kMaxK];
+            segment_prefix(c, pp, ee);
+            const float *u0 = P.u0f + (int64_t)c.prop * P.u0_stride;
+#pragma unroll
+            for (int j0 = 0; j0 < H1; j0 += 64)
+                if (j0 + lane < H1) base[j0 + lane] = prefix_potential<H1>(P.net, u0, c.k - 1, pp, ee, j0 + lane);
+            wave_lds_sync();
+            seg_new = false;
+        }
+        const float e = eff_delta(xv, dv);
+        float a1[H1];
+#pragma unroll
+        for (int j4 = 0; j4 < H1 / 4; ++j4) {
+            const float4 b = *reinterpret_cast<const float4 *>(base + 4 * j4);
+            a1[4 * j4 + 0] = sigmoid_f32(fmaf(e, wrow[j4].x, b.x));
+            a1[4 * j4 + 1] = sigmoid_f32(fmaf(e, wrow[j4].y, b.y));
+            a1[4 * j4 + 2] = sigmoid_f32(fmaf(e, wrow[j4].z, b.z));
+            a1[4 * j4 + 3] = sigmoid_f32(fmaf(e, wrow[j4].w, b.w));
+        }
         float z[NCP];
-        lane_logits<H1, H2, NCP>(P.net, P.u0f + (int64_t)c.prop * P.u0_stride, np, pp, ee, p, e, a2w, lane, z);
+        lane_upper<H1, H2, NCP>(P.net, a1, a2w, lane, z);
         int best;
         float top, margin;
         decide_f32<NCP>(z, nc, best, top, margin);
-        const int label0 = wave_uniform(gld(&P.props[c.prop].label0));
         const bool near = valid && margin <= P.tie_rel * fmaxf(1.0f, fabsf(top));
         const bool viol = valid && best != label0;
         emit_f32(P, c, viol, near, p, i, best);
         cur++;
-        if (cur < end) cursor_next<CH, FEnumParams>(c, P);
+        if (cur < end) seg_new = cursor_next<CH, FEnumParams>(c, P);
     }
 }
 
 // Listed points (or the clean images of listed properties), one per lane,
-// through lane_logits.
+// in the same sequence of operations.
 template <int H1, int H2, int NCP>
 __global__ void __launch_bounds__(256) eval_f32_lane_kernel(F32EvalParams E) {
-    __shared__ float a2s[kLaneWaves][H2 > 0 ? H2 : 1][64];
+    __shared__ float a2s[kLaneWaves][H2 > 0 ? H2 : NCP][64];
     const int lane = __lane_id();
     float *a2w = &a2s[threadIdx.x >> 6][0][0];
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -308,22 +391,22 @@ __global__ void __launch_bounds__(256) eval_f32_lane_kernel(F32EvalParams E) {
     int pp[kMaxK];
     float ee[kMaxK];
     const int np = k > 0 ? k - 1 : 0;
+    int p = 0;
+    float e = 0.0f;
 #pragma unroll
     for (int j = 0; j < kMaxK; ++j) {
         pp[j] = 0;
         ee[j] = 0.0f;
-        if (j < np) {
-            pp[j] = pix[j];
-            ee[j] = eff_delta(pr.image[pix[j]], pr.deltas[dig[j]]);
-        }
-    }
-    int p = 0;
-    float e = 0.0f;
-#pragma unroll
-    for (int j = 0; j < kMaxK; ++j)
+        if (j < np) { pp[j] = pix[j]; ee[j] = eff_delta(pr.image[pix[j]], pr.deltas[dig[j]]); }
         if (k > 0 && j == k - 1) { p = pix[j]; e = eff_delta(pr.image[pix[j]], pr.deltas[dig[j]]); }
+    }
+    const float *u0 = E.u0f + (int64_t)prop * E.u0_stride;
+    const float *w1 = E.net.W1P + (int64_t)p * H1;
+    float a1[H1];
+#pragma unroll
+    for (int j = 0; j < H1; ++j) a1[j] = sigmoid_f32(fmaf(e, w1[j], prefix_potential<H1>(E.net, u0, np, pp, ee, j)));
     float z[NCP];
-    lane_logits<H1, H2, NCP>(E.net, E.u0f + (int64_t)prop * E.u0_stride, np, pp, ee, p, e, a2w, lane, z);
+    lane_upper<H1, H2, NCP>(E.net, a1, a2w, lane, z);
     const int nc = E.net.dims[E.net.L];
     int best;
     float top, margin;

@@ -248,9 +248,12 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
     }
     const int NN = (int)plans.size();
     // counters: [1] rec_count, [2] first_chunk, [3] tie_count, [4] stop flag,
-    //           [8, 8+NN) per-network queues, then slot_cex[n_slots], slot_ties[n_slots]
+    //           [8, 8+NN) per-network queues (integer kernels), then
+    //           slot_cex[n_slots], slot_ties[n_slots], then per network the
+    //           float kernels' kF32Queues counters, kQueueStride apart
     const int64_t q0 = 8, sc0 = 8 + NN, st0 = sc0 + B.n_slots;
-    const int64_t n_ctr = st0 + B.n_slots;
+    const int64_t fq0 = (st0 + B.n_slots + kQueueStride - 1) / kQueueStride * kQueueStride;
+    const int64_t n_ctr = fq0 + (int64_t)NN * kF32Queues * kQueueStride;
     IBMC_TRY(ctx->counters.reserve(n_ctr * 8));
     unsigned long long *ctr = ctx->counters.as<unsigned long long>();
     const int64_t cap = o->cex_capacity, tcap = o->near_tie_capacity;
@@ -340,6 +343,9 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
     HIP_OK(hipStreamSynchronize(s));  // host staging vectors may go now
 
     PropDev *dprops = ctx->props.as<PropDev>();
+    // One network: the enumeration launch alone is bracketed by ek0 / ek1
+    // (the kernel time reported for rooflines); several: the whole graph.
+    const bool time_enum = NN <= 1;
     auto launch_net = [&](const NetPlan &pl, size_t id_off, hipStream_t st) -> ibmc_status {
         const ibmc_mlp *net = pl.net;
         const int32_t *ids = ctx->prop_ids.as<int32_t>() + id_off;
@@ -372,19 +378,25 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
             P.packed = pl.packed;
             P.vb_lo = pl.vb_lo;
             P.vb_hi = pl.vb_hi;
+            if (time_enum) HIP_OK(hipEventRecord(ctx->ek0, st));
             HIP_OK(launch_enum_q8(*pl.v, pl.grid, P, ctx->u0.as<int32_t>(), max_h1, ctx->u0_index.as<int32_t>(), st));
+            if (time_enum) HIP_OK(hipEventRecord(ctx->ek1, st));
         } else {
             FEnumParams P{};
             P.net = net->fd;
             P.jobs = ctx->jobs.as<EnumJob>() + pl.job_off;
             P.n_jobs = (int32_t)pl.n_jobs;
             P.total_chunks = pl.total;
-            P.batch = (int32_t)std::max<int64_t>(1, std::min<int64_t>(16, pl.total / ((int64_t)pl.grid * 8)));
+            // slices of the chunk range, each with its own queue counter;
+            // tickets of up to 16 chunks, about 8 per wave of a slice
+            P.slice = std::max<int64_t>(1, (pl.total + kF32Queues - 1) / kF32Queues);
+            const int64_t waves_per_slice = std::max<int64_t>(1, pl.grid / kF32Queues);
+            P.batch = (int32_t)std::max<int64_t>(1, std::min<int64_t>(16, P.slice / (waves_per_slice * 8)));
             P.props = dprops;
             P.u0f = ctx->u0.as<float>();
             P.u0_stride = (int32_t)max_h1;
             P.tie_rel = (o->near_tie_rel > 0) ? o->near_tie_rel : kDefaultTieRel;
-            P.queue = ctr + q0 + pi;
+            P.queue = ctr + fq0 + (int64_t)pi * kF32Queues * kQueueStride;
             P.rec_count = ctr + 1;
             P.rec_cap = rec_slots;
             P.recs = ctx->recs.as<DevRec>();
@@ -395,14 +407,17 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
             P.slot_ties = ctr + st0;
             P.stop_flag = reinterpret_cast<volatile int32_t *>(ctr + 4);
             P.abort_host = ctx->flags_dev;
+            if (time_enum) HIP_OK(hipEventRecord(ctx->ek0, st));
             HIP_OK(launch_enum_f32(pl.grid, P, st));
+            if (time_enum) HIP_OK(hipEventRecord(ctx->ek1, st));
         }
         return IBMC_OK;
     };
 
     kernel_seconds = 0.0;
     launches = 0;
-    HIP_OK(hipEventRecord(ctx->ek0, s));
+    bool timed = false;
+    if (!time_enum) HIP_OK(hipEventRecord(ctx->ek0, s));
     if (NN <= 1) {
         HIP_OK(launch_fill_u64(ctr, n_ctr, 0ull, s));
         HIP_OK(launch_fill_u64(ctr + 2, 1, ~0ull, s));
@@ -410,6 +425,7 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
         for (auto &pl : plans) {
             IBMC_TRY(launch_net(pl, id_off, s));
             id_off += pl.ids.size();
+            timed = pl.n_jobs > 0 && pl.total > 0;
         }
     } else {
         // one graph: counters cleared by a kernel (no memset node), then a
@@ -460,12 +476,17 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
         HIP_OK(le);
         ctx->graph_launches++;
     }
-    HIP_OK(hipEventRecord(ctx->ek1, s));
-    HIP_OK(hipEventSynchronize(ctx->ek1));
+    if (!time_enum) {
+        HIP_OK(hipEventRecord(ctx->ek1, s));
+        timed = true;
+    }
     float ms = 0.f;
-    HIP_OK(hipEventElapsedTime(&ms, ctx->ek0, ctx->ek1));
+    if (timed) {
+        HIP_OK(hipEventSynchronize(ctx->ek1));
+        HIP_OK(hipEventElapsedTime(&ms, ctx->ek0, ctx->ek1));
+    }
     kernel_seconds = ms * 1e-3;
-    launches = NN;
+    launches = timed ? NN : 0;
     // gather
     std::vector<unsigned long long> h(n_ctr);
     HIP_OK(hipMemcpyAsync(h.data(), ctr, n_ctr * 8, hipMemcpyDeviceToHost, s));

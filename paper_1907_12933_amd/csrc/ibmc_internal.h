@@ -177,6 +177,12 @@ struct EnumParams {
 // Record slots a wave of the integer kernel reserves at a time.
 constexpr int kRecBlock = 64;
 
+// The float kernels' work queue: the chunk range is cut into kF32Queues
+// contiguous slices, each with its own counter on its own 128-byte line, so
+// that tickets of small chunks do not serialise on one address.
+constexpr int kF32Queues = 32;
+constexpr int kQueueStride = 16;   // u64 words between counters
+
 // Float enumeration parameters.
 struct FEnumParams {
     FNetDev net;
@@ -188,7 +194,9 @@ struct FEnumParams {
     const float *u0f;                  // clean first-layer potentials per property [prop][h1]
     int32_t u0_stride;
     float tie_rel;
-    unsigned long long *queue;
+    unsigned long long *queue;         // kF32Queues counters, kQueueStride apart: counter q hands out
+                                       // chunks of slice q ([q * slice, (q + 1) * slice)) by offset
+    int64_t slice;
     unsigned long long *rec_count;
     int64_t rec_cap;
     DevRec *recs;

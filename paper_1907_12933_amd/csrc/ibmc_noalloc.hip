@@ -65,7 +65,7 @@ static ibmc_status scratch_need(ibmc_ctx *ctx, const ibmc_mlp *net, int32_t n_de
     size_t b = 0;
     b += al256((size_t)((n + 15) / 16 * 16));                       // image
     b += al256(sizeof(PropDev));                                     // property
-    b += al256((size_t)(8 + 1 + 2 * levels) * 8);                    // counters
+    b += al256((size_t)(8 + 1 + 2 * levels + kQueueStride + kF32Queues * kQueueStride) * 8);  // counters, queues
     b += al256((size_t)std::max<int64_t>(tcap, 1) * sizeof(DevRec)); // near-tie slots
     b += al256((size_t)h1 * 4) + 2 * al256(4);                       // u0, u0 index, property ids
     b += al256((size_t)std::max(levels, 1) * n * 8);                 // prefix tables

@@ -143,20 +143,14 @@ hipError_t launch_replay_f32(const FNetDev &net, const uint8_t *clean, const int
 // ---------------------------------------------------------------------------
 
 // LDS of one wave: activations of 16 points in two buffers [16][wp], logits
-// [16][64].
+// [16][64], the segment's first-layer potentials before the last pixel [HP1].
 __host__ __device__ inline int wide_wp(const FNetDev &net) {
     int wp = 64;
     for (int l = 1; l < net.L; ++l) wp = max(wp, net.HP[l]);
     return wp;
 }
-static size_t wide_lds_bytes(const FNetDev &net) { return (size_t)(2 * 16 * wide_wp(net) + 16 * 64) * 4; }
-
-// Cross-lane exchange through this wave's LDS: earlier writes complete
-// before later reads.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+static size_t wide_lds_bytes(const FNetDev &net) {
+    return (size_t)(2 * 16 * wide_wp(net) + 16 * 64 + net.HP[1]) * 4;
 }
 
 // Layers >= 2 of 16 points (lanes = units, 64 at a time) from the
@@ -227,42 +221,42 @@ __global__ void __launch_bounds__(64) enum_f32_wide_kernel(FEnumParams P) {
     extern __shared__ __attribute__((aligned(16))) float wlds[];
     const FNetDev &net = P.net;
     const int wp = wide_wp(net), hp1 = net.HP[1], nc = net.dims[net.L];
-    float *act0 = wlds, *act1 = wlds + 16 * wp, *zs = wlds + 32 * wp;
+    float *act0 = wlds, *act1 = wlds + 16 * wp, *zs = wlds + 32 * wp, *base = wlds + 32 * wp + 16 * 64;
     const int lane = __lane_id();
     Cursor c;
     int64_t cur = 0, end = 0;
+    bool seg_new = true;
+    int prop_seen = -1, label0 = 0;
+    int q = f32_first_slice(), tries = 0, polls = 0;
     while (true) {
         if (cur >= end) {
-            const int64_t start = f32_ticket(P);
+            const int64_t start = f32_ticket(P, q, tries, end, polls);
             if (start < 0) break;
             cur = start;
-            end = min(start + (int64_t)P.batch, P.total_chunks);
             cursor_decode<CH, FEnumParams>(c, P, cur);
-        }
-        int pp[kMaxK];
-        float ee[kMaxK];
-        const int np = c.k - 1;
-#pragma unroll
-        for (int t = 0; t < kMaxK; ++t) {
-            pp[t] = 0;
-            ee[t] = 0.0f;
-            if (t < np) {
-                pp[t] = c.pre[t];
-                const int xv = wave_uniform((int)gld(c.img + pp[t]));
-                ee[t] = eff_delta(xv, wave_uniform((int)gld(c.dl + c.dg[t])));
-            }
+            seg_new = true;
         }
         int p = 0, i = 0;
         const bool valid = last_element32<FEnumParams>(c, P, (int)(c.ch * CH) + (lane & 15), p, i) && lane < 16;
         const float e = eff_delta((int)gld(c.img + p), (int)gld(c.dl + i));
-        // first layer: the shared prefix once per unit, then each point's last pixel
-        const float *u0 = P.u0f + (int64_t)c.prop * P.u0_stride;
+        if (c.prop != prop_seen) {
+            prop_seen = c.prop;
+            label0 = wave_uniform(gld(&P.props[c.prop].label0));
+        }
+        if (seg_new) {
+            // the segment's potentials before the last pixel, each lane its own units
+            int pp[kMaxK];
+            float ee[kMaxK];
+            segment_prefix(c, pp, ee);
+            const float *u0 = P.u0f + (int64_t)c.prop * P.u0_stride;
+            for (int jb = 0; jb < hp1; jb += 64)
+                base[jb + lane] = prefix_potential_rt(net, hp1, u0, c.k - 1, pp, ee, jb + lane);
+            seg_new = false;
+        }
+        // first layer: each point's last pixel on the segment's potentials
         for (int jb = 0; jb < hp1; jb += 64) {
             const int j = jb + lane;
-            float vb = u0[j];
-#pragma unroll
-            for (int t = 0; t < kMaxK - 1; ++t)
-                if (t < np) vb = fmaf(ee[t], net.W1P[(int64_t)pp[t] * hp1 + j], vb);
+            const float vb = base[j];
 #pragma unroll 4
             for (int t = 0; t < 16; ++t) {
                 const int pt = __builtin_amdgcn_readlane(p, t);
@@ -276,12 +270,11 @@ __global__ void __launch_bounds__(64) enum_f32_wide_kernel(FEnumParams P) {
         float top, margin;
         wide_decide(zs, nc, lane, best, top, margin);
         wave_lds_sync();   // the logits are read before the next chunk overwrites them
-        const int label0 = wave_uniform(gld(&P.props[c.prop].label0));
         const bool near = valid && margin <= P.tie_rel * fmaxf(1.0f, fabsf(top));
         const bool viol = valid && best != label0;
         emit_f32(P, c, viol, near, p, i, best);
         cur++;
-        if (cur < end) cursor_next<CH, FEnumParams>(c, P);
+        if (cur < end) seg_new = cursor_next<CH, FEnumParams>(c, P);
     }
 }
 
@@ -319,15 +312,15 @@ __global__ void __launch_bounds__(64) eval_f32_wide_kernel(F32EvalParams E) {
         const int j = jb + lane;
         for (int t = 0; t < 16; ++t) {
             const int pt = __builtin_amdgcn_readlane(prop, t);
-            float v = E.u0f[(int64_t)pt * E.u0_stride + j];
             const int npt = __builtin_amdgcn_readlane(np, t);
+            int ppt[kMaxK];
+            float eet[kMaxK];
 #pragma unroll
-            for (int q = 0; q < kMaxK - 1; ++q)
-                if (q < npt) {
-                    const int ppq = __builtin_amdgcn_readlane(pp[q], t);
-                    const float eeq = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ee[q]), t));
-                    v = fmaf(eeq, net.W1P[(int64_t)ppq * hp1 + j], v);
-                }
+            for (int q = 0; q < kMaxK; ++q) {
+                ppt[q] = __builtin_amdgcn_readlane(pp[q], t);
+                eet[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ee[q]), t));
+            }
+            const float v = prefix_potential_rt(net, hp1, E.u0f + (int64_t)pt * E.u0_stride, npt, ppt, eet, j);
             const int ptl = __builtin_amdgcn_readlane(p, t);
             const float et = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(e), t));
             act0[t * wp + j] = sigmoid_f32(fmaf(et, net.W1P[(int64_t)ptl * hp1 + j], v));
