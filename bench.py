@@ -19,43 +19,59 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 MI355X_INT8_PEAK_TOPS = 5000.0     # dense int8 MFMA, TOP/s
+MI355X_FP32_PEAK_TFLOPS = 157.3    # FP32 vector, TFLOP/s (half of it without packed FP32)
+MI355X_HBM_PEAK_GBS = 8000.0
+MI355X_SPEC_CLOCK_GHZ = 2.4
 HERE = os.path.dirname(os.path.abspath(__file__))
-# enumeration kernel sources whose hash keys the measured HBM traffic
+# enumeration kernel sources whose hash keys the profile record
 KERNEL_SOURCES = ["paper_1907_12933_amd/csrc/enum_q8_impl.h", "paper_1907_12933_amd/csrc/enum_common.h",
                   "paper_1907_12933_amd/csrc/ibmc_internal.h"]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the enumeration kernel on this workload, from the
-    FETCH_SIZE / WRITE_SIZE counter runs recorded in profiles/ (scaled by a
-    plain copy's counters); None once the kernel sources differ from the ones
-    measured."""
+def kernel_source_sha():
     import hashlib
-    path = os.path.join(HERE, "profiles", "enum_q8_blob784_traffic.json")
-    if not os.path.exists(path):
-        return None
-    rec = json.load(open(path))
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(HERE, f), "rb") as fh:
             h.update(fh.read())
-    return rec["hbm_bytes_per_launch"] if rec.get("kernel_source_sha256") == h.hexdigest() else None
-MI355X_HBM_PEAK_GBS = 8000.0
+    return h.hexdigest()
+
+
+def profile_record():
+    """The rocprofv3 figures of the enumeration kernel on this workload kept in
+    profiles/ (kernel-trace average duration of this benchmark's command, HBM
+    bytes per launch from FETCH_SIZE / WRITE_SIZE scaled by a plain copy's
+    counters, shader clock and matrix-pipe busy from the counter run), or None
+    once the kernel sources differ from the ones profiled."""
+    path = os.path.join(HERE, "profiles", "enum_q8_blob784.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    return rec if rec.get("kernel_source_sha256") == kernel_source_sha() else None
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, target_seconds=15.0):
-    """The oracle (plain full forward per point) on a seeded sample of the
-    same workload's points: image 0, levels 1 and 2 in proportion."""
-    from oracle import oracle as O
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(O, w, threads, target_seconds, seed):
+    """Points/s of the oracle on a seeded random sample of the workload's
+    points (image 0, levels 1 and 2 in proportion), grown until about
+    target_seconds of work."""
     n, m = w.net.dims[0], len(w.deltas)
     n1, n2 = O.points(n, m, 1), O.points(n, m, 2)
-    g = np.random.Generator(np.random.PCG64(1234))
-    threads = int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
-    size = 20000
+    g = np.random.Generator(np.random.PCG64(seed))
+    size = 2000 if threads == 1 else 20000
     total_pts, total_t = 0, 0.0
     while total_t < target_seconds:
         ks = np.where(g.random(size) < n1 / (n1 + n2), 1, 2).astype(np.int32)
@@ -68,9 +84,21 @@ def cpu_baseline(w, target_seconds=15.0):
         size = int(min(max(size * 2, 1), max(1, (target_seconds - total_t) / max(dt / size, 1e-9))) + 1)
         if target_seconds - total_t < 0.5:
             break
-    return dict(value=total_pts / total_t, unit="points/s", cores=threads, kind="oracle",
-                sample=f"{total_pts} seeded random points (k=1 and k=2 in proportion) of image 0, "
-                       f"full int64 forward per point, {total_t:.1f} s")
+    return total_pts / total_t, total_pts, total_t
+
+
+def cpu_baseline(w, target_seconds=15.0):
+    """The oracle (plain full int64 forward per point) on a bounded sample of
+    the same workload, on all host cores and on one core."""
+    from oracle import oracle as O
+    threads = int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
+    rate, pts, t = _oracle_rate(O, w, threads, target_seconds, 1234)
+    rate1, pts1, t1 = _oracle_rate(O, w, 1, 5.0, 4321)
+    return dict(value=rate, unit="points/s", cores=threads, kind="oracle",
+                sample=f"{pts} seeded random points (k=1 and k=2 in proportion) of image 0, "
+                       f"full int64 forward per point, {t:.1f} s",
+                single_core_value=rate1, single_core_sample=f"{pts1} points, {t1:.1f} s",
+                cpu_model=cpu_model())
 
 
 def proposer_leg(ctx, ibmc, inputs, w, net, recs, args):
@@ -164,6 +192,19 @@ def coverage_leg(ctx, ibmc, inputs, torch):
                           for c, r in zip(["SS", "DS", "SV", "DV"], res)})
 
 
+def dense_macs(dims):
+    """int8 MACs of the dense layers >= 2 (the first layer is the rank-k update)."""
+    return sum(dims[l] * dims[l + 1] for l in range(1, len(dims) - 1))
+
+
+def f32_flops(dims):
+    """Algorithmic FP32 operations of one point of the float variant: the
+    first-layer update (one FMA per unit), the later layers' FMAs, and four
+    operations per sigmoid (scale, exponential, add, reciprocal)."""
+    fma = dims[1] + dense_macs(dims)
+    return 2 * fma + 4 * sum(dims[1:-1])
+
+
 def batch_leg(ctx, ibmc, inputs):
     """256 properties over eight uneven nets (k <= 3, per-property deltas) as one
     graph of persistent launches; and 64 FP32-sigmoid properties."""
@@ -174,7 +215,11 @@ def batch_leg(ctx, ibmc, inputs):
     t0 = time.perf_counter()
     sums, cex, _, rc = ibmc.ibmc_check_batch(ctx, P, cex_capacity=1 << 24)
     t = time.perf_counter() - t0
+    dev = sums[0]["seconds"]
     pts = sum(s["points_total"] for s in sums)
+    # point-weighted int8 work of the batch: each property's points times its
+    # network's dense later-layer MACs
+    ops = sum(2.0 * s["points_total"] * dense_macs(nets[p.net_index].dims) for s, p in zip(sums, props))
     fn, fp = inputs.batch_workload(seed=33, per_net=8, mac_budget=2e11)
     fms = [ibmc.Mlp(ctx, inputs.fnet_from_qnet(n)) for n in fn]
     FP = [(fms[p.net_index], p.image, p.deltas, 1, p.k) for p in fp]
@@ -182,11 +227,50 @@ def batch_leg(ctx, ibmc, inputs):
     t1 = time.perf_counter()
     fs, fc, ft, _ = ibmc.ibmc_check_batch(ctx, FP, cex_capacity=1 << 22, near_tie_capacity=1 << 20)
     tf = time.perf_counter() - t1
+    fdev = fs[0]["seconds"]
     fpts = sum(s["points_total"] for s in fs)
+    fflops = sum(float(s["points_total"]) * f32_flops(fn[p.net_index].dims) for s, p in zip(fs, fp))
     return dict(properties=len(props), networks=len(nets), points=pts, seconds=round(t, 4),
-                points_per_s=pts / t, counterexamples=int(sum(s["cex_total"] for s in sums)),
-                fp32_properties=len(fp), fp32_points=fpts, fp32_seconds=round(tf, 4), fp32_points_per_s=fpts / tf,
-                fp32_near_ties=int(sum(s["near_ties_total"] for s in fs)))
+                device_seconds=round(dev, 4), points_per_s=pts / t,
+                counterexamples=int(sum(s["cex_total"] for s in sums)),
+                int8_roofline=dict(bound="mfma", achieved=round(ops / dev / 1e12, 2), peak=MI355X_INT8_PEAK_TOPS,
+                                   unit="TOP/s", frac=round(ops / dev / 1e12 / MI355X_INT8_PEAK_TOPS, 4),
+                                   work="sum over properties of points x dense later-layer MACs x 2, "
+                                        "over the batch call's device time"),
+                fp32_properties=len(fp), fp32_points=fpts, fp32_seconds=round(tf, 4),
+                fp32_device_seconds=round(fdev, 4), fp32_points_per_s=fpts / tf,
+                fp32_near_ties=int(sum(s["near_ties_total"] for s in fs)),
+                fp32_roofline=dict(bound="alu", achieved=round(fflops / fdev / 1e12, 2),
+                                   peak=MI355X_FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                                   frac=round(fflops / fdev / 1e12 / MI355X_FP32_PEAK_TFLOPS, 4),
+                                   work="per point 2 x (first-layer update + later-layer FMAs) + 4 per sigmoid, "
+                                        "over the batch call's device time"))
+
+
+def glyph_leg(ctx, ibmc, inputs):
+    """The CPU-sized plain workload: 35-16-5 net, ten 7x5 glyphs, deltas
+    -16..16, k <= 2 (649,110 points per image), as one batch."""
+    g = inputs.workload_glyph35()
+    m = ibmc.Mlp(ctx, g.net)
+    P = [(m, x, g.deltas, 1, 2) for x in g.images]
+    ibmc.ibmc_check_batch(ctx, P, cex_capacity=1 << 20)
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        sums, _, _, _ = ibmc.ibmc_check_batch(ctx, P, cex_capacity=1 << 20)
+        ts.append(time.perf_counter() - t0)
+    t = float(np.median(ts))
+    pts = sum(s["points_total"] for s in sums)
+    return dict(workload="glyph35: 35-16-5, 10 glyph images, deltas -16..16, k=1..2", points=pts,
+                seconds=round(t, 6), points_per_s=pts / t, us_per_image=round(t / len(P) * 1e6, 2),
+                counterexamples=int(sum(s["cex_total"] for s in sums)))
+
+
+def per_image(ibmc, ctx, net, w, sums):
+    pots, labels = ibmc.ibmc_forward(ctx, net, w.images)
+    z = np.sort(pots[:, -w.net.dims[-1]:].astype(np.int64), axis=1)
+    return dict(counterexamples=[int(s["cex_total"]) for s in sums],
+                clean_margin=[int(v) for v in (z[:, -1] - z[:, -2])])
 
 
 def main():
@@ -242,15 +326,30 @@ def main():
     unsafe = sum(1 for s in sums if s["cex_total"] > 0)
 
     # roofline of the enumeration kernel: algorithmic int8 MACs per point are
-    # the later layers' dense products (the first layer is the rank-k update)
-    d = w.net.dims
-    macs_per_point = sum(d[l] * d[l + 1] for l in range(1, len(d) - 1))
+    # the later layers' dense products (the first layer is the rank-k update);
+    # its duration is the average of HIP events around the enumeration launch
+    # alone, on the library's stream
+    macs_per_point = dense_macs(w.net.dims)
     k_avg = float(np.mean(ksec))
     achieved_tops = 2.0 * macs_per_point * points / k_avg / 1e12
+    prof = profile_record() if args.images == 64 else None
     roof = dict(bound="mfma", achieved=round(achieved_tops, 2), peak=MI355X_INT8_PEAK_TOPS, unit="TOP/s",
                 frac=round(achieved_tops / MI355X_INT8_PEAK_TOPS, 4),
-                traffic=measured_traffic() if args.images == 64 else None,
-                kernel="enum_q8", kernel_ms=round(k_avg * 1e3, 3))
+                traffic=prof["hbm_bytes_per_launch"] if prof else None,
+                kernel="enum_q8", kernel_ms=round(k_avg * 1e3, 3),
+                ops_per_point=2 * macs_per_point, points_per_launch=points)
+    if prof:
+        # the same figures from the committed rocprofv3 summaries of this
+        # workload, and the ceiling at the shader clock measured there
+        clk = prof["shader_clock_ghz"]
+        roof.update(profile_kernel_ms=prof["kernel_trace_avg_ms"],
+                    profile_frac=round(2.0 * macs_per_point * points / (prof["kernel_trace_avg_ms"] * 1e-3) / 1e12
+                                       / MI355X_INT8_PEAK_TOPS, 4),
+                    measured_clock_ghz=clk, peak_at_measured_clock=round(MI355X_INT8_PEAK_TOPS * clk /
+                                                                         MI355X_SPEC_CLOCK_GHZ, 1),
+                    frac_at_measured_clock=round(achieved_tops / (MI355X_INT8_PEAK_TOPS * clk /
+                                                                  MI355X_SPEC_CLOCK_GHZ), 4),
+                    mfma_busy=prof.get("mfma_busy"))
     out = {
         "metric": "perturbation points verified/sec + time-to-first-counterexample, plain vs learned",
         "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -261,8 +360,12 @@ def main():
                    "points_per_step": points, "images": args.images},
         "roofline": roof,
         "counterexamples_per_step": n_cex, "unsafe_images": unsafe,
+        # per image: counterexamples and the clean top-2 logit margin
+        "per_image": per_image(ibmc, ctx, net, w, sums),
     }
     if not args.no_extras:
+        log("[bench] glyph leg")
+        out["glyph35"] = glyph_leg(ctx, ibmc, inputs)
         log("[bench] proposer leg")
         out["ttfc"] = proposer_leg(ctx, ibmc, inputs, w, net, cex, args)
         log("[bench] coverage leg")
