@@ -73,6 +73,7 @@ typedef int32_t ibmc_status;
 
 #define IBMC_OK 0
 #define IBMC_W_TRUNCATED 1      /* more records than capacity; totals stay exact */
+#define IBMC_W_PARTIAL 2        /* stopped at chunk_budget: resume from next_cursor */
 #define IBMC_E_INVALID (-1)     /* bad argument, size or null pointer */
 #define IBMC_E_RANGE (-2)       /* a potential could leave int32 */
 #define IBMC_E_HIP (-3)         /* a HIP runtime call failed */
@@ -117,13 +118,26 @@ typedef struct {
  * cex_capacity / near_tie_capacity: room in the caller's record buffers.
  * near_tie_rel: float nets only; <= 0 selects 4e-5.
  * records_on_device: nonzero when cex_buf / near_tie_buf are device memory
- * of the context's device (the records then never cross to the host). */
+ * of the context's device (the records then never cross to the host).
+ * resume_cursor / chunk_budget (integer networks, one network per call, no
+ * stop_at_first; else IBMC_E_UNIMPL when nonzero): the points of all levels
+ * form one sequence of work chunks; a call checks the chunks from
+ * resume_cursor on (0: from the start) and, with chunk_budget > 0, at most
+ * that many.  A call that stops early (budget reached, or ibmc_abort)
+ * reports in next_cursor the first chunk it did not check: every chunk
+ * before it is checked, and its counts and records cover exactly the chunks
+ * it checked.  Calling again with resume_cursor = next_cursor (same network,
+ * image, deltas, k range and library build) continues the check; the union
+ * of the calls' records and the sums of their counts equal one uninterrupted
+ * call's. */
 typedef struct {
     int32_t k_min, k_max, k_step, stop_at_first;
     int64_t cex_capacity;
     int64_t near_tie_capacity;
     float near_tie_rel;
     int32_t records_on_device;
+    int64_t resume_cursor;
+    int64_t chunk_budget;
 } ibmc_check_opts;
 
 /* One counterexample (or near tie): decode with ibmc_decode_point.  prop is
@@ -151,6 +165,8 @@ typedef struct {
     double seconds;                      /* device time of the call (HIP events) */
     double ttfc_seconds;                 /* ordered search: time to the first counterexample; -1 if none */
     int64_t points_before_first;         /* ordered search: points visited before the first counterexample; -1 if none */
+    int64_t next_cursor;                 /* -1: checked to the end; else the chunk to resume from (see
+                                            ibmc_check_opts); points[] still give the levels' sizes */
 } ibmc_check_summary;
 
 /* One property of a batch: a network, an image of dims[0] pixels, a delta
@@ -235,6 +251,13 @@ ibmc_status ibmc_check_property_noalloc(ibmc_ctx *ctx, const ibmc_mlp *net, cons
                                         const ibmc_check_opts *opts, ibmc_check_summary *out,
                                         ibmc_cex *cex_buf, ibmc_cex *near_tie_buf);
 
+/* As ibmc_check_property with `image` a device pointer (n_pixels bytes on
+ * the context's device); the delta set stays in host memory. */
+ibmc_status ibmc_check_property_dev(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *image,
+                                    int32_t n_pixels, const int16_t *delta_set, int32_t n_deltas,
+                                    const ibmc_check_opts *opts, ibmc_check_summary *out,
+                                    ibmc_cex *cex_buf, ibmc_cex *near_tie_buf);
+
 /* Check many properties, possibly over different networks, as one
  * batch.  outs: one summary per property.  Records of all properties share
  * cex_buf / near_tie_buf (capacities in opts), tagged with ibmc_cex.prop.
@@ -251,8 +274,9 @@ ibmc_status ibmc_check_batch_dev(ibmc_ctx *ctx, const ibmc_property *props, int3
                                  ibmc_cex *cex_buf, ibmc_cex *near_tie_buf);
 
 /* Stop a running check from another host thread: the kernels poll a flag in
- * host-mapped memory once per work chunk and drain; the check returns
- * IBMC_E_ABORTED with the counts reached so far. */
+ * host-mapped memory before taking work and drain; the check returns
+ * IBMC_E_ABORTED with the counts and records of the chunks it finished (and,
+ * for a resumable call, next_cursor). */
 ibmc_status ibmc_abort(ibmc_ctx *ctx);
 
 /* Decode (k, rank) into ascending pixels[k] and delta indices[k] (host only,
@@ -368,6 +392,12 @@ ibmc_status ibmc_proposer_train(ibmc_ctx *ctx, ibmc_proposer *p, const float *fe
 ibmc_status ibmc_proposer_score(ibmc_ctx *ctx, const ibmc_proposer *p, const ibmc_mlp *net,
                                 const uint8_t *image, int32_t rows, int32_t cols,
                                 const int16_t *delta_set, int32_t n_deltas, float *scores);
+
+/* As ibmc_proposer_score with `image` (dims[0] bytes) and `scores`
+ * (n_pixels * n_deltas floats) device pointers on the context's device. */
+ibmc_status ibmc_proposer_score_dev(ibmc_ctx *ctx, const ibmc_proposer *p, const ibmc_mlp *net,
+                                    const uint8_t *image, int32_t rows, int32_t cols,
+                                    const int16_t *delta_set, int32_t n_deltas, float *scores);
 
 /* Training labels from a property's counterexample records: labels_out
  * (host float [n_pixels * n_deltas], candidate p * n_deltas + i) is 1 for

@@ -597,13 +597,17 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
             seg = cursor_next<CH, EnumParams>(c, Q);
             return true;
         }
+        // host-mapped: poll sparsely, and before taking a ticket, so that every
+        // ticket handed out is worked through (the queue counter then marks a
+        // finished prefix of the chunks, the point a check resumes from)
+        if (Q.abort_host && (fetches++ & 15) == 0 && wave_uniform(*Q.abort_host)) return false;
         int64_t start = (int64_t)sround * n_waves + gwave, len = 1;
         if (start < Q.single) {
             ++sround;
         } else {
             unsigned long long ticket = 0;
             if (lane == 0) ticket = atomicAdd(Q.queue, 1ull);
-            start = Q.single + (int64_t)wave_uniform(ticket) * Q.batch;  // lane 0's ticket
+            start = Q.resume + Q.single + (int64_t)wave_uniform(ticket) * Q.batch;  // lane 0's ticket
             len = Q.batch;
         }
         if (start >= Q.total_chunks) return false;
@@ -616,8 +620,6 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
                 wave_uniform(*reinterpret_cast<volatile unsigned long long *>(Q.first_chunk));
             if ((unsigned long long)start > fc) return false;
         }
-        // host-mapped: poll sparsely
-        if (Q.abort_host && (fetches++ & 15) == 0 && wave_uniform(*Q.abort_host)) return false;
         cur_chunk = start;
         end_chunk = min(start + len, Q.total_chunks);
         cursor_decode<CH, EnumParams>(c, Q, cur_chunk);

@@ -216,6 +216,8 @@ struct NetPlan {
     std::vector<int> ids;
     const EnumVariant *v = nullptr;
     int64_t total = 0;
+    int64_t limit = 0;      // chunks handed out stop here (a budgeted call), else total
+    int32_t batch = 1;      // chunks per queue ticket (integer kernels)
     size_t job_off = 0, n_jobs = 0;
     int grid = 0;
     int32_t packed = 0, vb_lo = 0, vb_hi = 0;
@@ -227,7 +229,8 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
                               std::vector<unsigned long long> &slot_cex, std::vector<unsigned long long> &slot_ties,
                               std::vector<CexRec> &recs, std::vector<CexRec> &ties, int64_t &rec_total,
                               int64_t &tie_total, double &kernel_seconds, int &launches,
-                              CexRec *direct_recs = nullptr, CexRec *direct_ties = nullptr, bool direct_dev = false) {
+                              CexRec *direct_recs = nullptr, CexRec *direct_ties = nullptr, bool direct_dev = false,
+                              int64_t resume = 0, int64_t budget = 0, int64_t *next_cursor = nullptr) {
     (void)images_on_device;
     hipStream_t s = ctx->stream;
     std::vector<NetPlan> plans;
@@ -320,11 +323,13 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
                                                                 (size_t)enum_lds_bytes(*pl.v, net->qd)));
             if (occ < 1) return fail(IBMC_E_UNIMPL, "variant %s does not fit", pl.v->name);
             pl.grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * occ, std::max<int64_t>(1, pl.total / 2));
+            pl.batch = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, pl.total / ((int64_t)pl.grid * 32)));
         } else {
             const int g = f32_enum_grid(net->fd, ctx->n_cu);
             if (g < 1) return fail(IBMC_E_UNIMPL, "no float enumeration kernel for network %s", shape_key(net).c_str());
             pl.grid = (int)std::min<int64_t>(g, std::max<int64_t>(1, pl.total));
         }
+        pl.limit = budget > 0 ? std::min(pl.total, resume + budget) : pl.total;
         all_ids.insert(all_ids.end(), pl.ids.begin(), pl.ids.end());
     }
     // record slots: the capacity plus one partly used block per wave of the
@@ -360,8 +365,9 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
             P.net = net->qd;
             P.jobs = ctx->jobs.as<EnumJob>() + pl.job_off;
             P.n_jobs = (int32_t)pl.n_jobs;
-            P.total_chunks = pl.total;
-            P.batch = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, pl.total / ((int64_t)pl.grid * 32)));
+            P.total_chunks = pl.limit;
+            P.batch = pl.batch;
+            P.resume = resume;
             P.props = dprops;
             P.queue = ctr + q0 + pi;
             P.rec_count = ctr + 1;
@@ -492,6 +498,16 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
     HIP_OK(hipMemcpyAsync(h.data(), ctr, n_ctr * 8, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     tie_total = (int64_t)h[3];
+    if (next_cursor) {
+        // every queue ticket handed out was worked through: chunks below
+        // resume + tickets * batch are done
+        *next_cursor = -1;
+        if (NN == 1 && plans[0].net->act == IBMC_ACT_RELU_Q8) {
+            const NetPlan &pl = plans[0];
+            const int64_t done = std::min<int64_t>(pl.limit, resume + (int64_t)h[q0] * pl.batch);
+            if (done < pl.total) *next_cursor = done;
+        }
+    }
     slot_cex.assign(h.begin() + sc0, h.begin() + st0);
     slot_ties.assign(h.begin() + st0, h.begin() + st0 + B.n_slots);
     // exact total from the level counters; record slots handed out (with the
@@ -531,6 +547,14 @@ ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props, int32_t 
     IBMC_TRY(validate_props(props, n_props, o));
     if (o->cex_capacity > 0 && !cex_buf) return fail(IBMC_E_INVALID, "cex_buf is null with capacity > 0");
     if (o->near_tie_capacity > 0 && !tie_buf) return fail(IBMC_E_INVALID, "near_tie_buf is null with capacity > 0");
+    const bool resumable = o->resume_cursor != 0 || o->chunk_budget != 0;
+    if (o->resume_cursor < 0 || o->chunk_budget < 0) return fail(IBMC_E_INVALID, "negative resume cursor or budget");
+    if (resumable) {
+        if (o->stop_at_first) return fail(IBMC_E_UNIMPL, "resume / budget with stop_at_first");
+        for (int i = 0; i < n_props; ++i)
+            if (props[i].net != props[0].net || props[i].net->act != IBMC_ACT_RELU_Q8)
+                return fail(IBMC_E_UNIMPL, "resume / budget need one integer network per call");
+    }
     HIP_OK(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     ctx->flags_host[0] = 0;
@@ -576,6 +600,7 @@ ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props, int32_t 
     int nlaunch = 0;
     std::vector<bool> stopped(n_props, false);
     std::vector<int> next_level(n_props, 0);
+    int64_t next_cursor = -1;
     ibmc_status st = IBMC_OK;
     int rounds = 0;
     while (true) {
@@ -604,7 +629,8 @@ ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props, int32_t 
         const bool direct = !o->stop_at_first;
         st = run_levels(ctx, props, n_props, &oo, B, sel, images_on_device, sc, stt, r, t, rt, tt, ks, nl,
                         direct ? reinterpret_cast<CexRec *>(cex_buf) : nullptr,
-                        direct ? reinterpret_cast<CexRec *>(tie_buf) : nullptr, o->records_on_device != 0);
+                        direct ? reinterpret_cast<CexRec *>(tie_buf) : nullptr, o->records_on_device != 0,
+                        o->resume_cursor, o->chunk_budget, &next_cursor);
         rounds++;
         if (st < 0 && st != IBMC_E_ABORTED) return st;
         ksec += ks;
@@ -650,6 +676,7 @@ ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props, int32_t 
         S.ttfc_seconds = -1.0;
         S.points_before_first = -1;
         S.seconds = ms * 1e-3;
+        S.next_cursor = next_cursor;
         std::vector<int> lv = done_levels[i];
         std::sort(lv.begin(), lv.end());
         S.n_levels = (int32_t)lv.size();
@@ -672,6 +699,7 @@ ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props, int32_t 
     }
     if (st == IBMC_E_ABORTED) return st;
     if (rec_total > o->cex_capacity || tie_total > o->near_tie_capacity) return IBMC_W_TRUNCATED;
+    if (next_cursor >= 0) return IBMC_W_PARTIAL;
     return IBMC_OK;
 }
 
@@ -689,6 +717,24 @@ extern "C" ibmc_status ibmc_check_batch_dev(ibmc_ctx *ctx, const ibmc_property *
                                             const ibmc_check_opts *opts, ibmc_check_summary *outs, ibmc_cex *cex_buf,
                                             ibmc_cex *near_tie_buf) {
     return check_batch_impl(ctx, props, n_props, opts, outs, cex_buf, near_tie_buf, true);
+}
+
+extern "C" ibmc_status ibmc_check_property_dev(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *image,
+                                               int32_t n_pixels, const int16_t *delta_set, int32_t n_deltas,
+                                               const ibmc_check_opts *opts, ibmc_check_summary *out, ibmc_cex *cex_buf,
+                                               ibmc_cex *near_tie_buf) {
+    clear_error();
+    if (!net || !opts) return fail(IBMC_E_INVALID, "null net / opts");
+    if (n_pixels != net->dims[0]) return fail(IBMC_E_INVALID, "n_pixels %d != network input %d", n_pixels, net->dims[0]);
+    ibmc_property p{};
+    p.net = net;
+    p.image = image;
+    p.deltas = delta_set;
+    p.n_deltas = n_deltas;
+    p.k_min = opts->k_min;
+    p.k_max = opts->k_max;
+    p.k_step = opts->k_step;
+    return check_batch_impl(ctx, &p, 1, opts, out, cex_buf, near_tie_buf, true);
 }
 
 extern "C" ibmc_status ibmc_check_property(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *image, int32_t n_pixels,
@@ -1089,6 +1135,7 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
     }
     ibmc_check_summary &S = *out;
     memset(&S, 0, sizeof(S));
+    S.next_cursor = -1;
     S.clean_label = back.label0;
     S.first_unsafe_k = -1;
     S.safe_up_to_k = -1;

@@ -172,6 +172,8 @@ struct EnumParams {
     int32_t vb_lo, vb_hi;              // pre-clamp of the scaled base for the packed path
     int32_t track_first;               // maintain first_chunk (ordered searches)
     int32_t notify;                    // any of stop_on_first, track_first, hit_host (set at launch)
+    int64_t resume;                    // queue tickets start at this chunk (a resumed check); chunks
+                                       // below it were checked by an earlier call
 };
 
 // Record slots a wave of the integer kernel reserves at a time.

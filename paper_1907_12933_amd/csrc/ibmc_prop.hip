@@ -176,6 +176,23 @@ extern "C" ibmc_status ibmc_proposer_score(ibmc_ctx *ctx, const ibmc_proposer *p
     return IBMC_OK;
 }
 
+extern "C" ibmc_status ibmc_proposer_score_dev(ibmc_ctx *ctx, const ibmc_proposer *p, const ibmc_mlp *net,
+                                               const uint8_t *image, int32_t rows, int32_t cols, const int16_t *deltas,
+                                               int32_t m, float *scores) {
+    clear_error();
+    if (!ctx || !p || !image || !scores) return fail(IBMC_E_INVALID, "null argument");
+    IBMC_TRY(check_net_for_prop(net, rows, cols));
+    PropCand pc;
+    IBMC_TRY(upload_cand(deltas, m, pc));
+    HIP_OK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    DevBuf feat, sc;
+    IBMC_TRY(score_image(ctx, p, net, image, rows, cols, pc, feat, sc, true));
+    HIP_OK(hipMemcpyAsync(scores, sc.p, (size_t)net->dims[0] * m * 4, hipMemcpyDeviceToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return IBMC_OK;
+}
+
 extern "C" ibmc_status ibmc_proposer_grad(ibmc_ctx *ctx, ibmc_proposer *p, const float *features, const float *labels,
                                           int32_t B, float pos_weight, float *loss, float *gW1, float *gb1, float *gw2,
                                           float *gc) {

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libibmc.so")
 
 IBMC_OK = 0
 IBMC_W_TRUNCATED = 1
+IBMC_W_PARTIAL = 2
 IBMC_E_INVALID = -1
 IBMC_E_RANGE = -2
 IBMC_E_HIP = -3
@@ -48,7 +49,8 @@ class ibmc_mlp_desc(C.Structure):
 class ibmc_check_opts(C.Structure):
     _fields_ = [("k_min", C.c_int32), ("k_max", C.c_int32), ("k_step", C.c_int32),
                 ("stop_at_first", C.c_int32), ("cex_capacity", C.c_int64),
-                ("near_tie_capacity", C.c_int64), ("near_tie_rel", C.c_float), ("records_on_device", C.c_int32)]
+                ("near_tie_capacity", C.c_int64), ("near_tie_rel", C.c_float), ("records_on_device", C.c_int32),
+                ("resume_cursor", C.c_int64), ("chunk_budget", C.c_int64)]
 
 
 class ibmc_cex(C.Structure):
@@ -67,7 +69,7 @@ class ibmc_check_summary(C.Structure):
                 ("points", C.c_int64 * IBMC_MAX_LEVELS), ("cex", C.c_int64 * IBMC_MAX_LEVELS),
                 ("ties", C.c_int64 * IBMC_MAX_LEVELS), ("points_total", C.c_int64), ("cex_total", C.c_int64),
                 ("near_ties_total", C.c_int64), ("seconds", C.c_double), ("ttfc_seconds", C.c_double),
-                ("points_before_first", C.c_int64)]
+                ("points_before_first", C.c_int64), ("next_cursor", C.c_int64)]
 
 
 class ibmc_property(C.Structure):
@@ -115,6 +117,7 @@ SIGNATURES = {
     "ibmc_free_mlp": (None, [VP]),
     "ibmc_check_property": (I32, [VP, VP, P_U8, I32, P_I16, I32, P_OPTS, P_SUM, P_CEX, P_CEX]),
     "ibmc_check_property_noalloc": (I32, [VP, VP, P_U8, I32, P_I16, I32, P_OPTS, P_SUM, P_CEX, P_CEX]),
+    "ibmc_check_property_dev": (I32, [VP, VP, VP, I32, P_I16, I32, P_OPTS, P_SUM, P_CEX, P_CEX]),
     "ibmc_check_batch": (I32, [VP, C.POINTER(ibmc_property), I32, P_OPTS, P_SUM, P_CEX, P_CEX]),
     "ibmc_check_batch_dev": (I32, [VP, C.POINTER(ibmc_property), I32, P_OPTS, P_SUM, P_CEX, P_CEX]),
     "ibmc_abort": (I32, [VP]),
@@ -134,6 +137,7 @@ SIGNATURES = {
     "ibmc_proposer_grad": (I32, [VP, VP, P_F32, P_F32, I32, C.c_float, P_F32, P_F32, P_F32, P_F32, P_F32]),
     "ibmc_proposer_train": (I32, [VP, VP, P_F32, P_F32, I64, C.POINTER(ibmc_train_opts), P_F32]),
     "ibmc_proposer_score": (I32, [VP, VP, VP, P_U8, I32, I32, P_I16, I32, P_F32]),
+    "ibmc_proposer_score_dev": (I32, [VP, VP, VP, VP, I32, I32, P_I16, I32, VP]),
     "ibmc_label_candidates": (I32, [VP, I32, I32, P_CEX, I64, P_F32]),
     "ibmc_check_property_ranked": (I32, [VP, VP, VP, P_U8, I32, I32, I32, P_I16, I32, P_OPTS, P_SUM, P_CEX]),
     "ibmc_autotune": (I32, [VP, VP, I32, I32, C.c_char_p, I64]),
@@ -266,9 +270,9 @@ def ibmc_decode_point(n_pixels, n_deltas, k, rank):
 # check
 # ---------------------------------------------------------------------------
 
-def _opts(k_min, k_max, k_step, stop_at_first, cap, tie_cap, tie_rel, on_device=False):
+def _opts(k_min, k_max, k_step, stop_at_first, cap, tie_cap, tie_rel, on_device=False, resume=0, budget=0):
     return ibmc_check_opts(int(k_min), int(k_max), int(k_step), int(bool(stop_at_first)), int(cap), int(tie_cap),
-                           float(tie_rel), int(bool(on_device)))
+                           float(tie_rel), int(bool(on_device)), int(resume), int(budget))
 
 
 def summary_dict(s: ibmc_check_summary):
@@ -277,7 +281,7 @@ def summary_dict(s: ibmc_check_summary):
                 levels=list(s.level_k[:n]), points=list(s.points[:n]), cex=list(s.cex[:n]),
                 ties=list(s.ties[:n]), points_total=s.points_total, cex_total=s.cex_total,
                 near_ties_total=s.near_ties_total, seconds=s.seconds, ttfc_seconds=s.ttfc_seconds,
-                points_before_first=s.points_before_first)
+                points_before_first=s.points_before_first, next_cursor=s.next_cursor)
 
 
 def summary_dicts(outs, n):
@@ -294,22 +298,47 @@ def summary_dicts(outs, n):
                         safe_up_to_k=d["safe_up_to_k"], levels=d["level_k"][:m].tolist(), points=d["points"][:m].tolist(),
                         cex=d["cex"][:m].tolist(), ties=d["ties"][:m].tolist(), points_total=d["points_total"],
                         cex_total=d["cex_total"], near_ties_total=d["near_ties_total"], seconds=d["seconds"],
-                        ttfc_seconds=d["ttfc_seconds"], points_before_first=d["points_before_first"]))
+                        ttfc_seconds=d["ttfc_seconds"], points_before_first=d["points_before_first"],
+                        next_cursor=d["next_cursor"]))
     return res
 
 
 def ibmc_check_property(ctx, net, image, deltas, k_min=1, k_max=2, k_step=1, stop_at_first=False,
-                        cex_capacity=1 << 20, near_tie_capacity=0, near_tie_rel=0.0, _entry="ibmc_check_property"):
-    """Returns (summary dict, cex records, near-tie records) as numpy structured arrays."""
+                        cex_capacity=1 << 20, near_tie_capacity=0, near_tie_rel=0.0, resume_cursor=0,
+                        chunk_budget=0, _entry="ibmc_check_property"):
+    """Returns (summary dict, cex records, near-tie records) as numpy structured arrays.  With
+    chunk_budget the call may stop early (status IBMC_W_PARTIAL, summary next_cursor >= 0);
+    resume_cursor continues such a call."""
     image = np.ascontiguousarray(image, np.uint8)
     D = np.ascontiguousarray(deltas, np.int16)
     cex = np.empty(max(cex_capacity, 1), CEX_DTYPE)
     ties = np.empty(max(near_tie_capacity, 1), CEX_DTYPE)
-    o = _opts(k_min, k_max, k_step, stop_at_first, cex_capacity, near_tie_capacity, near_tie_rel)
+    o = _opts(k_min, k_max, k_step, stop_at_first, cex_capacity, near_tie_capacity, near_tie_rel,
+              resume=resume_cursor, budget=chunk_budget)
     s = ibmc_check_summary()
     rc = _ck(getattr(lib(), _entry)(ctx.handle, net.handle, _ptr(image, P_U8), image.size, _ptr(D, P_I16),
                                     D.size, C.byref(o), C.byref(s), cex.ctypes.data_as(P_CEX),
                                     ties.ctypes.data_as(P_CEX)))
+    sd = summary_dict(s)
+    sd["status"] = rc
+    nrec = min(sd["cex_total"], cex_capacity)
+    ntie = min(sd["near_ties_total"], near_tie_capacity)
+    return sd, cex[:nrec].copy(), ties[:ntie].copy()
+
+
+def ibmc_check_property_dev(ctx, net, image, deltas, k_min=1, k_max=2, k_step=1, stop_at_first=False,
+                            cex_capacity=1 << 20, near_tie_capacity=0, near_tie_rel=0.0, resume_cursor=0,
+                            chunk_budget=0):
+    """ibmc_check_property with the image a torch uint8 device tensor; records come back to the host."""
+    D = np.ascontiguousarray(deltas, np.int16)
+    cex = np.empty(max(cex_capacity, 1), CEX_DTYPE)
+    ties = np.empty(max(near_tie_capacity, 1), CEX_DTYPE)
+    o = _opts(k_min, k_max, k_step, stop_at_first, cex_capacity, near_tie_capacity, near_tie_rel,
+              resume=resume_cursor, budget=chunk_budget)
+    s = ibmc_check_summary()
+    rc = _ck(lib().ibmc_check_property_dev(ctx.handle, net.handle, VP(image.data_ptr()), image.numel(),
+                                           _ptr(D, P_I16), D.size, C.byref(o), C.byref(s),
+                                           cex.ctypes.data_as(P_CEX), ties.ctypes.data_as(P_CEX)))
     sd = summary_dict(s)
     sd["status"] = rc
     nrec = min(sd["cex_total"], cex_capacity)
@@ -344,13 +373,15 @@ def _props(props, on_device):
 
 
 def ibmc_check_batch(ctx, props, stop_at_first=False, cex_capacity=1 << 20, near_tie_capacity=0,
-                     near_tie_rel=0.0, on_device=False, cex_buf=None, records_on_device=False):
+                     near_tie_rel=0.0, on_device=False, cex_buf=None, records_on_device=False, resume_cursor=0,
+                     chunk_budget=0, allow_abort=False):
     """props: list of (net, image, deltas, k_min, k_max[, k_step]); with on_device the images are
     torch device tensors (uint8).  cex_buf: optional preallocated buffer of at least cex_capacity
     records, reused across calls: a CEX_DTYPE array, or with records_on_device a torch uint8
     device tensor of CEX_DTYPE.itemsize bytes per record (the records then stay on the device).
     Returns (list of summary dicts, cex records (a view into cex_buf when given; with
-    records_on_device a uint8 device tensor), near-tie records, status)."""
+    records_on_device a uint8 device tensor), near-tie records, status).  With allow_abort an
+    aborted call returns its partial results with status IBMC_E_ABORTED instead of raising."""
     arr, keep = _props(props, on_device)
     n = len(props)
     outs = (ibmc_check_summary * n)()
@@ -366,9 +397,12 @@ def ibmc_check_batch(ctx, props, stop_at_first=False, cex_capacity=1 << 20, near
             cex_buf = np.empty(max(cex_capacity, 1), CEX_DTYPE)
         ties = np.empty(max(near_tie_capacity, 1), CEX_DTYPE)
         cex_ptr, tie_ptr = cex_buf.ctypes.data_as(P_CEX), ties.ctypes.data_as(P_CEX)
-    o = _opts(0, 0, 1, stop_at_first, cex_capacity, near_tie_capacity, near_tie_rel, records_on_device)
+    o = _opts(0, 0, 1, stop_at_first, cex_capacity, near_tie_capacity, near_tie_rel, records_on_device,
+              resume=resume_cursor, budget=chunk_budget)
     fn = lib().ibmc_check_batch_dev if on_device else lib().ibmc_check_batch
-    rc = _ck(fn(ctx.handle, arr, n, C.byref(o), outs, cex_ptr, tie_ptr))
+    rc = fn(ctx.handle, arr, n, C.byref(o), outs, cex_ptr, tie_ptr)
+    if not (allow_abort and rc == IBMC_E_ABORTED):
+        _ck(rc)
     sums = summary_dicts(outs, n)
     tot = min(sum(s["cex_total"] for s in sums), cex_capacity)
     ttot = min(sum(s["near_ties_total"] for s in sums), near_tie_capacity)
@@ -601,6 +635,15 @@ def ibmc_proposer_score(ctx, prop, net, image, rows, cols, deltas):
     _ck(lib().ibmc_proposer_score(ctx.handle, prop.handle, net.handle, _ptr(image, P_U8), rows, cols,
                                   _ptr(D, P_I16), D.size, _ptr(s, P_F32)))
     return s
+
+
+def ibmc_proposer_score_dev(ctx, prop, net, image, rows, cols, deltas, scores):
+    """Scores into a torch float32 device tensor of n_pixels * n_deltas, from a device image."""
+    D = np.ascontiguousarray(deltas, np.int16)
+    assert scores.numel() >= net.dims[0] * D.size
+    _ck(lib().ibmc_proposer_score_dev(ctx.handle, prop.handle, net.handle, VP(image.data_ptr()), rows, cols,
+                                      _ptr(D, P_I16), D.size, VP(scores.data_ptr())))
+    return scores
 
 
 def ibmc_label_candidates(ctx, n_pixels, n_deltas, recs):
