@@ -405,6 +405,11 @@ ibmc_status ibmc_proposer_score_dev(ibmc_ctx *ctx, const ibmc_proposer *p, const
 ibmc_status ibmc_label_candidates(ibmc_ctx *ctx, int32_t n_pixels, int32_t n_deltas, const ibmc_cex *recs,
                                   int64_t n, float *labels_out);
 
+/* As ibmc_label_candidates, with counts_out[c] the number of records in
+ * which candidate c occurs (a graded training signal). */
+ibmc_status ibmc_count_candidates(ibmc_ctx *ctx, int32_t n_pixels, int32_t n_deltas, const ibmc_cex *recs,
+                                  int64_t n, float *counts_out);
+
 /* Ordered check of levels k <= 2 (integer nets): level 1 visits candidates by
  * decreasing score; level 2 visits "shells": candidates sorted c0, c1, ...,
  * shell t holds the pairs (c_t, c_j), j < t, on distinct pixels, so every

@@ -711,7 +711,7 @@ int orc_prop_features(int L, const int32_t *dims, const int8_t *W, const int32_t
         for (int i = 0; i < n; ++i) u += (int64_t)W[(int64_t)j * n + i] * x[i];
         live[j] = u >= 0 && u < top;
     }
-    double m1 = 1.0, m2 = 1.0, ml = 1.0;
+    double m1 = 1.0, m2 = 1.0;
     for (int p = 0; p < n; ++p) {
         double s1 = 0, s2 = 0, sl = 0;
         for (int j = 0; j < h1; ++j) {
@@ -723,7 +723,6 @@ int orc_prop_features(int L, const int32_t *dims, const int8_t *W, const int32_t
         n1[p] = s1; n2[p] = sqrt(s2); nl[p] = sl;
         if (s1 > m1) m1 = s1;
         if (n2[p] > m2) m2 = n2[p];
-        if (sl > ml) ml = sl;
     }
     double dmax = 1.0;
     for (int i = 0; i < m; ++i) if (fabs((double)D[i]) > dmax) dmax = fabs((double)D[i]);
@@ -741,7 +740,7 @@ int orc_prop_features(int L, const int32_t *dims, const int8_t *W, const int32_t
             f[4] = (v - (int)x[p]) / dmax;
             f[5] = n1[p] / m1;
             f[6] = n2[p] / m2;
-            f[7] = nl[p] / ml;
+            f[7] = nl[p] / m1;   /* live part of the column norm, on the full norm's scale */
             f[8] = 1.0;
             for (int z = 9; z < 32; ++z) f[z] = 0.0;
         }

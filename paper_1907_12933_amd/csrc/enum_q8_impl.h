@@ -333,8 +333,12 @@ __device__ __forceinline__ void emit_tiles(RecOut &o, int einfo, int w, const bo
         o.notified = true;
         const int64_t gchunk = lane_get64(einfo, EI_GCLO, EI_GCHI);
         if (lane == 0) {
-            if (P.track_first) atomicMin(P.first_chunk, (unsigned long long)gchunk);
-            if (P.hit_host) *P.hit_host = 1;
+            // the host-mapped hit flag is written once per grid, by the wave
+            // that lowers first_chunk from its initial value (a write per
+            // wave would keep the bus and the host's polled line busy)
+            const unsigned long long was =
+                P.track_first ? atomicMin(P.first_chunk, (unsigned long long)gchunk) : 0ull;
+            if (P.hit_host && was == ~0ull) *P.hit_host = 1;
             if (P.stop_on_first) *P.stop_flag = 1;
         }
     }
@@ -597,10 +601,12 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
             seg = cursor_next<CH, EnumParams>(c, Q);
             return true;
         }
-        // host-mapped: poll sparsely, and before taking a ticket, so that every
-        // ticket handed out is worked through (the queue counter then marks a
+        // host-mapped abort request: polled on every 16th fetch of a wave,
+        // never on its first (a grid whose waves all read host memory at once
+        // waits on the bus), and before taking a ticket, so that every ticket
+        // handed out is worked through (the queue counter then marks a
         // finished prefix of the chunks, the point a check resumes from)
-        if (Q.abort_host && (fetches++ & 15) == 0 && wave_uniform(*Q.abort_host)) return false;
+        if (Q.abort_host && (++fetches & 15) == 0 && wave_uniform(*Q.abort_host)) return false;
         int64_t start = (int64_t)sround * n_waves + gwave, len = 1;
         if (start < Q.single) {
             ++sround;

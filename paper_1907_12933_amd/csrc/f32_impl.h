@@ -128,14 +128,16 @@ constexpr int kAbortPollTickets = 64;
 // the next one (tries counts the slices visited).  Returns -1 when every
 // slice is drained or a stop / abort was requested.  The device stop flag is
 // read per ticket, the host abort request every kAbortPollTickets tickets
-// (polls counts them); a wave that sees the abort raises the stop flag.
+// (polls counts them; never at a wave's first ticket, where every wave of the
+// grid would read host memory at once); a wave that sees the abort raises
+// the stop flag.
 __device__ __forceinline__ int64_t f32_ticket(const FEnumParams &P, int &q, int &tries, int64_t &end, int &polls) {
     while (tries < kF32Queues) {
         const int64_t lo = (int64_t)q * P.slice;
         const int64_t hi = min(lo + P.slice, P.total_chunks);
         unsigned long long t = 0;
         int stop = 0;
-        const bool poll_host = P.abort_host && (polls++ % kAbortPollTickets) == 0;
+        const bool poll_host = P.abort_host && (++polls % kAbortPollTickets) == 0;
         if (__lane_id() == 0) {
             if (lo < hi) t = atomicAdd(P.queue + (int64_t)q * kQueueStride, (unsigned long long)P.batch);
             stop = *P.stop_flag;

@@ -976,14 +976,11 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
         for (int i = 0; i < m; ++i) { pc.deltas[i] = deltas[i]; pc.dmax = std::max(pc.dmax, std::abs((int)deltas[i])); }
         const PropParams PP = prop_views(p);
         // the context's buffers (no allocation once sized); the clean pass
-        // above has left the first-layer potentials in u0
-        IBMC_TRY(ctx->prop_feat.reserve((size_t)N1 * kPropF * 4));
+        // above has left the first-layer potentials in u0: one launch for
+        // live norms, features and scores, one for the order
         IBMC_TRY(ctx->prop_scores.reserve((size_t)N1 * 4));
-        IBMC_TRY(ctx->prop_scratch.reserve((size_t)(net->qd.H[1] + n) * 4));
-        HIP_OK(launch_prop_features(net->qd, pd.image, ctx->u0.as<int32_t>(), rows, cols, pc,
-                                    ctx->prop_scratch.as<int32_t>(), ctx->prop_scratch.as<float>() + net->qd.H[1],
-                                    ctx->prop_feat.as<float>(), s));
-        HIP_OK(launch_prop_score(PP, ctx->prop_feat.as<float>(), N1, ctx->prop_scores.as<float>(), s));
+        HIP_OK(launch_prop_fused(net->qd, pd.image, ctx->u0.as<int32_t>(), rows, cols, pc, PP,
+                                 ctx->prop_scores.as<float>(), s));
         HIP_OK(launch_prop_sort(ctx->prop_scores.as<float>(), (int)N1, ctx->order.as<int32_t>(), s));
     }
     double ttfc = -1.0;

@@ -165,8 +165,10 @@ struct EnumParams {
     unsigned long long *slot_ties;     // per slot exact top-2 ties
     unsigned long long *first_chunk;   // min chunk index holding a counterexample (ordered searches)
     volatile int32_t *stop_flag;       // device memory: set on the first counterexample if stop_on_first
-    volatile int32_t *abort_host;      // host-mapped abort request (nullable), polled per queue fetch
-    volatile int32_t *hit_host;        // host-mapped, set on the first counterexample (nullable)
+    volatile int32_t *abort_host;      // host-mapped abort request (nullable), polled every 16th queue
+                                       // fetch of a wave, after its first
+    volatile int32_t *hit_host;        // host-mapped, set on the first counterexample (nullable;
+                                       // needs track_first)
     int32_t stop_on_first;
     int32_t packed;                    // packed int16 first layer (bound checked by the host)
     int32_t vb_lo, vb_hi;              // pre-clamp of the scaled base for the packed path

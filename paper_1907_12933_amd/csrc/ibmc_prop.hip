@@ -64,14 +64,18 @@ static ibmc_status score_image(ibmc_ctx *ctx, const ibmc_proposer *p, const ibmc
                                int rows, int cols, const PropCand &pc, DevBuf &feat, DevBuf &scores, bool want_scores) {
     hipStream_t s = ctx->stream;
     const int64_t N = (int64_t)net->dims[0] * pc.m;
-    IBMC_TRY(feat.reserve((size_t)N * kPropF * 4));
     IBMC_TRY(ctx->prop_scratch.reserve((size_t)(net->qd.H[1] + net->dims[0]) * 4));
+    if (want_scores) {
+        // clean potentials, then live norms, features and scores in one launch
+        IBMC_TRY(scores.reserve((size_t)N * 4));
+        HIP_OK(launch_prop_u0(net->qd, dimage, ctx->prop_scratch.as<int32_t>(), s));
+        HIP_OK(launch_prop_fused(net->qd, dimage, ctx->prop_scratch.as<int32_t>(), rows, cols, pc, prop_views(p),
+                                 scores.as<float>(), s));
+        return IBMC_OK;
+    }
+    IBMC_TRY(feat.reserve((size_t)N * kPropF * 4));
     HIP_OK(launch_prop_features(net->qd, dimage, nullptr, rows, cols, pc, ctx->prop_scratch.as<int32_t>(),
                                 ctx->prop_scratch.as<float>() + net->qd.H[1], feat.as<float>(), s));
-    if (want_scores) {
-        IBMC_TRY(scores.reserve((size_t)N * 4));
-        HIP_OK(launch_prop_score(prop_views(p), feat.as<float>(), N, scores.as<float>(), s));
-    }
     return IBMC_OK;
 }
 
@@ -262,8 +266,21 @@ extern "C" ibmc_status ibmc_proposer_train(ibmc_ctx *ctx, ibmc_proposer *p, cons
     return IBMC_OK;
 }
 
+static ibmc_status label_or_count(ibmc_ctx *ctx, int32_t n_pixels, int32_t m, const ibmc_cex *recs, int64_t n,
+                                  float *labels, bool count);
+
 extern "C" ibmc_status ibmc_label_candidates(ibmc_ctx *ctx, int32_t n_pixels, int32_t m, const ibmc_cex *recs,
                                              int64_t n, float *labels) {
+    return label_or_count(ctx, n_pixels, m, recs, n, labels, false);
+}
+
+extern "C" ibmc_status ibmc_count_candidates(ibmc_ctx *ctx, int32_t n_pixels, int32_t m, const ibmc_cex *recs,
+                                             int64_t n, float *counts) {
+    return label_or_count(ctx, n_pixels, m, recs, n, counts, true);
+}
+
+static ibmc_status label_or_count(ibmc_ctx *ctx, int32_t n_pixels, int32_t m, const ibmc_cex *recs, int64_t n,
+                                  float *labels, bool count) {
     clear_error();
     if (!ctx || n_pixels < 1 || m < 1 || m > kMaxDeltas || n < 0 || !labels || (n > 0 && !recs))
         return fail(IBMC_E_INVALID, "bad argument");
@@ -282,7 +299,7 @@ extern "C" ibmc_status ibmc_label_candidates(ibmc_ctx *ctx, int32_t n_pixels, in
     HIP_OK(launch_fill_u64((unsigned long long *)dl.p, (N + 1) / 2, 0ull, s));
     if (n > 0) {
         IBMC_TRY(dr.upload(recs, (size_t)n * sizeof(ibmc_cex), s));
-        HIP_OK(launch_label_candidates(n_pixels, m, dr.as<CexRec>(), n, dl.as<float>(), s));
+        HIP_OK(launch_label_candidates(n_pixels, m, dr.as<CexRec>(), n, dl.as<float>(), count, s));
     }
     HIP_OK(hipMemcpyAsync(labels, dl.p, (size_t)N * 4, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));

@@ -36,6 +36,13 @@ hipError_t launch_prop_features(const QNetDev &net, const uint8_t *image, const 
                                 const PropCand &pc, int32_t *u0_scratch, float *nl_scratch, float *feat,
                                 hipStream_t s);
 hipError_t launch_prop_score(const PropParams &P, const float *feat, int64_t N, float *scores, hipStream_t s);
+// Scores of an image's candidates [n m] in one launch (live norms, features
+// and the forward pass), from its clean first-layer potentials u0 (sigma
+// order); equal to launch_prop_features then launch_prop_score.
+// Clean first-layer potentials of one image, sigma order, H[1] ints.
+hipError_t launch_prop_u0(const QNetDev &net, const uint8_t *image, int32_t *u0, hipStream_t s);
+hipError_t launch_prop_fused(const QNetDev &net, const uint8_t *image, const int32_t *u0, int rows, int cols,
+                             const PropCand &pc, const PropParams &P, float *scores, hipStream_t s);
 hipError_t launch_prop_train(const PropParams &P, const float *feat, const float *labels, const int32_t *index,
                              int64_t begin, int64_t count, float inv_b, float pw, const PropGrads &G, int n_cu,
                              hipStream_t s);
@@ -43,6 +50,9 @@ hipError_t launch_prop_adam(float *theta, float *grad, float *mom, float *vel, i
                             float eps, float c1, float c2, hipStream_t s);
 int prop_sort_max();
 hipError_t launch_prop_sort(const float *scores, int N, int32_t *order, hipStream_t s);
-hipError_t launch_label_candidates(int n, int m, const CexRec *recs, int64_t nrec, float *labels, hipStream_t s);
+// Per candidate (p * m + i): 1 when it occurs in some record (count false),
+// or the number of records it occurs in (count true); labels start at 0.
+hipError_t launch_label_candidates(int n, int m, const CexRec *recs, int64_t nrec, float *labels, bool count,
+                                  hipStream_t s);
 
 }  // namespace ibmc

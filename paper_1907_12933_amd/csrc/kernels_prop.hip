@@ -57,41 +57,41 @@ __global__ void __launch_bounds__(256) prop_live_norm_kernel(QNetDev net, const 
     if (lane == 0) nl[p] = (float)sl;
 }
 
-// Feature rows of the candidates (p, i): position, clean value, delta and its
-// clamped effect, the three column norms (each over its maximum), a constant.
+// The nine nonzero features of candidate (p, i): position, clean value,
+// delta and its clamped effect, the full and L2 column norms over their
+// maxima, the live part of the L1 norm on the full norm's scale, a constant.
+__device__ __forceinline__ void cand_features(const QNetDev &net, const uint8_t *image, int rows, int cols,
+                                              const PropCand &pc, int p, int i, float nlp, float (&f)[9]) {
+    const int n = net.dims[0];
+    const float M1 = net.pnorm[2 * n], M2 = net.pnorm[2 * n + 1];
+    const float rden = rows > 1 ? (float)(rows - 1) : 1.f, cden = cols > 1 ? (float)(cols - 1) : 1.f;
+    const float dmax = fmaxf((float)pc.dmax, 1.f);
+    const int r = p / cols, c = p - r * cols;
+    const int x = image[p];
+    const int d = pc.deltas[i];
+    const int e = min(max(x + d, 0), 255) - x;
+    f[0] = (float)r / rden;
+    f[1] = (float)c / cden;
+    f[2] = (float)x / 255.f;
+    f[3] = (float)d / dmax;
+    f[4] = (float)e / dmax;
+    f[5] = net.pnorm[p] / M1;
+    f[6] = net.pnorm[n + p] / M2;
+    f[7] = nlp / M1;
+    f[8] = 1.f;
+}
+
+// Feature rows [n m][32] of the candidates (p, i) from the live norms nl.
 __global__ void __launch_bounds__(256) prop_feat_kernel(QNetDev net, const uint8_t *image, int rows, int cols,
                                                         PropCand pc, const float *nl, float *feat) {
-    __shared__ float red[256];
-    const int tid = threadIdx.x, n = net.dims[0];
-    float ml = 0.f;
-    for (int p = tid; p < n; p += blockDim.x) ml = fmaxf(ml, nl[p]);
-    red[tid] = ml;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if (tid < st) red[tid] = fmaxf(red[tid], red[tid + st]);
-        __syncthreads();
-    }
-    const float *n1 = net.pnorm, *n2 = net.pnorm + n;
-    const float M1 = net.pnorm[2 * n], M2 = net.pnorm[2 * n + 1], ML = fmaxf(red[0], 1.f);
-    const float rden = rows > 1 ? (float)(rows - 1) : 1.f, cden = cols > 1 ? (float)(cols - 1) : 1.f;
-    const int m = pc.m;
-    const float dmax = fmaxf((float)pc.dmax, 1.f);
-    for (int t = blockIdx.x * blockDim.x + tid; t < n * m; t += gridDim.x * blockDim.x) {
+    const int n = net.dims[0], m = pc.m;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n * m; t += gridDim.x * blockDim.x) {
         const int p = t / m, i = t - p * m;
-        const int r = p / cols, c = p - r * cols;
-        const int x = image[p];
-        const int d = pc.deltas[i];
-        const int e = min(max(x + d, 0), 255) - x;
+        float fv[9];
+        cand_features(net, image, rows, cols, pc, p, i, nl[p], fv);
         float *f = feat + (int64_t)t * 32;
-        f[0] = (float)r / rden;
-        f[1] = (float)c / cden;
-        f[2] = (float)x / 255.f;
-        f[3] = (float)d / dmax;
-        f[4] = (float)e / dmax;
-        f[5] = n1[p] / M1;
-        f[6] = n2[p] / M2;
-        f[7] = nl[p] / ML;
-        f[8] = 1.f;
+#pragma unroll
+        for (int z = 0; z < 9; ++z) f[z] = fv[z];
         for (int z = 9; z < 32; ++z) f[z] = 0.f;
     }
 }
@@ -145,6 +145,67 @@ __global__ void __launch_bounds__(256) prop_score_kernel(PropParams P, const flo
         part += __shfl_xor(part, 16);
         part += __shfl_xor(part, 32);
         if (g == 0 && s < N) scores[s] = part + P.c[0];
+    }
+}
+
+// Live norms, features and scores of the candidates of 16 pixels per
+// workgroup in one launch: each wave sums the live column norms of its
+// pixels, then the candidates go through the same bf16 matrix-core forward
+// as prop_score_kernel, their features built in registers (bf16 operands
+// equal to those of the feature rows prop_feat_kernel writes).
+constexpr int kFusedPix = 16;
+
+__global__ void __launch_bounds__(256) prop_fused_kernel(QNetDev net, const uint8_t *image, int rows, int cols,
+                                                         PropCand pc, const int32_t *u0, PropParams P, float *scores) {
+    __shared__ v8bf wt[8 * 64];
+    __shared__ float nls[kFusedPix];
+    stage_w1(P, wt);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = net.dims[0], H1 = net.H[1], m = pc.m;
+    const int p0 = blockIdx.x * kFusedPix;
+    const int top = 128 << net.shift[0];
+    for (int pp = wave; pp < kFusedPix; pp += 4) {
+        const int p = p0 + pp;
+        int sl = 0;
+        if (p < n)
+            for (int q = lane; q < H1; q += 64) {
+                const int u = u0[q];
+                const int w = net.W1T[(int64_t)p * H1 + q];
+                if (sigma64(q) < net.dims[1] && u >= 0 && u < top) sl += w < 0 ? -w : w;
+            }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) sl += __shfl_xor(sl, off);
+        if (lane == 0) nls[pp] = (float)sl;
+    }
+    __syncthreads();
+    const int N = min(kFusedPix, n - p0) * m;
+    const int j = lane & 15, g = lane >> 4;
+    for (int tile = wave; tile * 16 < N; tile += 4) {
+        const int t = tile * 16 + j;
+        v8bf B;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) B[e] = to_bf16(0.f);
+        if (t < N && g < 2) {
+            const int pl = t / m, i = t - pl * m;
+            float fv[9];
+            cand_features(net, image, rows, cols, pc, p0 + pl, i, nls[pl], fv);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) B[e] = to_bf16(g * 8 + e < 9 ? fv[g * 8 + e] : 0.f);
+        }
+        float part = 0.f;
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            v4f acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wt[mt * 64 + lane], B, acc, 0, 0, 0);
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) {
+                const int h = mt * 16 + g * 4 + tt;
+                part += P.w2[h] * fmaxf(acc[tt] + P.b1[h], 0.f);
+            }
+        }
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (g == 0 && t < N) scores[(int64_t)p0 * m + t] = part + P.c[0];
     }
 }
 
@@ -366,7 +427,7 @@ __global__ void __launch_bounds__(64 * kRankWaves) prop_rank_kernel(const float 
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(256) label_candidates_kernel(int n, int m, const CexRec *recs, int64_t nrec,
-                                                               float *labels) {
+                                                               float *labels, int count) {
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nrec;
          r += (int64_t)gridDim.x * blockDim.x) {
         const int k = recs[r].k;
@@ -377,7 +438,9 @@ __global__ void __launch_bounds__(256) label_candidates_kernel(int n, int m, con
         lex_unrank_subset(recs[r].rank / mk, k, n, p);
         int64_t d = recs[r].rank % mk;
         for (int j = k - 1; j >= 0; --j) {
-            labels[(int64_t)p[j] * m + (int)(d % m)] = 1.f;
+            float *slot = labels + (int64_t)p[j] * m + (int)(d % m);
+            if (count) atomicAdd(slot, 1.f);   // exact while a count stays below 2^24
+            else *slot = 1.f;
             d /= m;
         }
     }
@@ -398,6 +461,19 @@ hipError_t launch_prop_features(const QNetDev &net, const uint8_t *image, const 
     hipLaunchKernelGGL(prop_live_norm_kernel, dim3((n + 3) / 4), dim3(256), 0, s, net, u0, nl_scratch);
     const int grid = (int)std::min<int64_t>(((int64_t)n * pc.m + 255) / 256, 1024);
     hipLaunchKernelGGL(prop_feat_kernel, dim3(grid), dim3(256), 0, s, net, image, rows, cols, pc, nl_scratch, feat);
+    return hipGetLastError();
+}
+
+hipError_t launch_prop_u0(const QNetDev &net, const uint8_t *image, int32_t *u0, hipStream_t s) {
+    hipLaunchKernelGGL(prop_u0_kernel, dim3((net.H[1] + 63) / 64), dim3(256), 0, s, net, image, u0);
+    return hipGetLastError();
+}
+
+hipError_t launch_prop_fused(const QNetDev &net, const uint8_t *image, const int32_t *u0, int rows, int cols,
+                             const PropCand &pc, const PropParams &P, float *scores, hipStream_t s) {
+    const int n = net.dims[0];
+    hipLaunchKernelGGL(prop_fused_kernel, dim3((n + kFusedPix - 1) / kFusedPix), dim3(256), 0, s, net, image, rows,
+                       cols, pc, u0, P, scores);
     return hipGetLastError();
 }
 
@@ -435,10 +511,11 @@ hipError_t launch_prop_sort(const float *scores, int N, int32_t *order, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_label_candidates(int n, int m, const CexRec *recs, int64_t nrec, float *labels, hipStream_t s) {
+hipError_t launch_label_candidates(int n, int m, const CexRec *recs, int64_t nrec, float *labels, bool count,
+                                  hipStream_t s) {
     if (nrec <= 0) return hipSuccess;
     const int grid = (int)std::min<int64_t>((nrec + 255) / 256, 4096);
-    hipLaunchKernelGGL(label_candidates_kernel, dim3(grid), dim3(256), 0, s, n, m, recs, nrec, labels);
+    hipLaunchKernelGGL(label_candidates_kernel, dim3(grid), dim3(256), 0, s, n, m, recs, nrec, labels, count ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -139,6 +139,7 @@ SIGNATURES = {
     "ibmc_proposer_score": (I32, [VP, VP, VP, P_U8, I32, I32, P_I16, I32, P_F32]),
     "ibmc_proposer_score_dev": (I32, [VP, VP, VP, VP, I32, I32, P_I16, I32, VP]),
     "ibmc_label_candidates": (I32, [VP, I32, I32, P_CEX, I64, P_F32]),
+    "ibmc_count_candidates": (I32, [VP, I32, I32, P_CEX, I64, P_F32]),
     "ibmc_check_property_ranked": (I32, [VP, VP, VP, P_U8, I32, I32, I32, P_I16, I32, P_OPTS, P_SUM, P_CEX]),
     "ibmc_autotune": (I32, [VP, VP, I32, I32, C.c_char_p, I64]),
     "ibmc_set_variant": (I32, [VP, VP, C.c_char_p]),
@@ -651,6 +652,15 @@ def ibmc_label_candidates(ctx, n_pixels, n_deltas, recs):
     recs = np.ascontiguousarray(recs, CEX_DTYPE)
     out = np.zeros(n_pixels * n_deltas, np.float32)
     _ck(lib().ibmc_label_candidates(ctx.handle, n_pixels, n_deltas, recs.ctypes.data_as(P_CEX), len(recs),
+                                    _ptr(out, P_F32)))
+    return out
+
+
+def ibmc_count_candidates(ctx, n_pixels, n_deltas, recs):
+    """Number of records in which each (pixel, delta index) candidate occurs."""
+    recs = np.ascontiguousarray(recs, CEX_DTYPE)
+    out = np.zeros(n_pixels * n_deltas, np.float32)
+    _ck(lib().ibmc_count_candidates(ctx.handle, n_pixels, n_deltas, recs.ctypes.data_as(P_CEX), len(recs),
                                     _ptr(out, P_F32)))
     return out
 

@@ -148,6 +148,36 @@ def test_labels_from_records(ctx, orc):
         pix, dig = orc.decode(30, 4, int(k), int(r))
         exp[pix * 4 + dig] = 1.0
     assert np.array_equal(lab, exp)
+    # counts: the number of records each candidate occurs in
+    cnt = ibmc.ibmc_count_candidates(ctx, 30, 4, cex)
+    ref = np.zeros(30 * 4, np.float32)
+    for k, r in zip(cex["k"], cex["rank"]):
+        pix, dig = orc.decode(30, 4, int(k), int(r))
+        np.add.at(ref, np.asarray(pix) * 4 + np.asarray(dig), 1.0)
+    assert np.array_equal(cnt, ref) and cnt.sum() == int(cex["k"].sum())
+
+
+def test_fused_scores_match_features_forward(ctx, orc):
+    """The one-launch scoring (live norms, features, bf16 MFMA forward) equals
+    the network's FP64 forward on the feature rows (themselves pinned to the
+    oracle's above), with features and first layer weights rounded to
+    bfloat16 as the kernel takes them."""
+    from paper_1907_12933_amd import ibmc
+    w = I.workload_blob784(count=2)
+    m = ibmc.Mlp(ctx, w.net)
+    g = I.rng(19)
+    prop = ibmc.Proposer(ctx, seed=8)
+    W1, b1, w2, c = prop.get()
+    prop.set(W1, (g.normal(size=128) * 0.2).astype(np.float32), w2, 0.05)
+    W1, b1, w2, c = prop.get()
+    for i in range(2):
+        f = ibmc.ibmc_proposer_features(ctx, m, w.images[i], 28, 28, w.deltas)
+        np.testing.assert_allclose(f, orc.prop_features(w.net, w.images[i], 28, 28, w.deltas), rtol=2e-6, atol=1e-7)
+        h = np.maximum(bf16_round(f) @ bf16_round(W1).T + b1.astype(np.float64), 0.0)
+        ref = h @ w2.astype(np.float64) + float(c)
+        got = ibmc.ibmc_proposer_score(ctx, prop, m, w.images[i], 28, 28, w.deltas).astype(np.float64)
+        err = np.abs(got - ref) / np.maximum(1.0, np.abs(ref))
+        assert err.max() <= 1e-3, float(err.max())
 
 
 def _order_keys(scores):

@@ -86,7 +86,7 @@ def test_features_hand_built(orc):
             row = f[p * 2 + i]
             e = min(max(int(x[p]) + int(d), 0), 255) - int(x[p])
             assert np.allclose(row[:9], [p // 2, p % 2, x[p] / 255, d / 20, e / 20,
-                                         n1[p] / 7, n2[p] / np.sqrt(21), nl[p] / 5, 1.0])
+                                         n1[p] / 7, n2[p] / np.sqrt(21), nl[p] / 7, 1.0])
             assert np.all(row[9:] == 0)
     # clamping: pixel 2 (255) with +5 has e = 0; pixel 1 (0) with -20 has e = 0
     assert f[2 * 2 + 1][4] == 0 and f[1 * 2 + 0][4] == 0
