@@ -101,23 +101,26 @@ def cpu_baseline(w, target_seconds=15.0):
                 cpu_model=cpu_model())
 
 
+def top_count_labels(counts, frac=0.05):
+    """1 for the candidates of one image whose record count lies in the top
+    frac of its counts (and is nonzero), else 0."""
+    return ((counts >= np.quantile(counts, 1.0 - frac)) & (counts > 0)).astype(np.float32)
+
+
 def proposer_leg(ctx, ibmc, inputs, w, net, recs, args):
-    """Train the proposal network on plain-enumeration labels (10 glyph images
-    of the 35-16-5 net and the step's 64 blob images), then compare the time to
-    the first counterexample, plain order vs learned order, on 64 held-out blob
-    images; every held-out verdict and record list must be identical."""
+    """Train the proposal network on the step's 64 blob images (label: the
+    candidate is among the 5% of its image taking part in the most
+    counterexamples), then search 64 held-out blob images in plain order,
+    untrained-proposer order and trained-proposer order: points visited and
+    host time before the first counterexample; every held-out verdict and
+    record list must be identical across the three."""
     t_all = time.perf_counter()
     feats, labels = [], []
-    g1 = inputs.workload_glyph35()
-    m1 = ibmc.Mlp(ctx, g1.net)
-    for img in g1.images:
-        s, cex, _ = ibmc.ibmc_check_property(ctx, m1, img, g1.deltas, 1, 2, cex_capacity=1 << 21)
-        labels.append(ibmc.ibmc_label_candidates(ctx, 35, len(g1.deltas), cex))
-        feats.append(ibmc.ibmc_proposer_features(ctx, m1, img, 7, 5, g1.deltas))
     props_col = recs["prop"]
     for i in range(len(w.images)):
         lo, hi = np.searchsorted(props_col, i, "left"), np.searchsorted(props_col, i, "right")
-        labels.append(ibmc.ibmc_label_candidates(ctx, 784, len(w.deltas), recs[lo:hi]))
+        counts = ibmc.ibmc_count_candidates(ctx, 784, len(w.deltas), recs[lo:hi])
+        labels.append(top_count_labels(counts))
         feats.append(ibmc.ibmc_proposer_features(ctx, net, w.images[i], 28, 28, w.deltas))
     F = np.concatenate(feats)
     Y = np.concatenate(labels)
@@ -125,47 +128,45 @@ def proposer_leg(ctx, ibmc, inputs, w, net, recs, args):
     t0 = time.perf_counter()
     losses = ibmc.ibmc_proposer_train(ctx, prop, F, Y, epochs=20, batch=4096, lr=1e-3, seed=4)
     t_train = time.perf_counter() - t0
+    untrained = ibmc.Proposer(ctx, seed=4)
     held = inputs.heldout_blob_images()
+    orders = (("plain", None), ("untrained", untrained), ("trained", prop))
     rows = []
+    identical = True
     for x in held:
-        sp, cp = ibmc.ibmc_check_property_ranked(ctx, net, None, x, 28, 28, w.deltas, 1, 2, cex_capacity=1 << 22)
-        sl, cl = ibmc.ibmc_check_property_ranked(ctx, net, prop, x, 28, 28, w.deltas, 1, 2, cex_capacity=1 << 22)
-        same = (sp["cex"] == sl["cex"] and sp["clean_label"] == sl["clean_label"]
-                and np.array_equal(cp["rank"], cl["rank"]) and np.array_equal(cp["k"], cl["k"]))
-        rows.append((sp["cex_total"] > 0, same, sp["ttfc_seconds"], sl["ttfc_seconds"],
-                     sp["points_before_first"], sl["points_before_first"]))
-    unsafe = [r for r in rows if r[0]]
+        res = {}
+        for name, p in orders:
+            res[name] = ibmc.ibmc_check_property_ranked(ctx, net, p, x, 28, 28, w.deltas, 1, 2, cex_capacity=1 << 22)
+        s0, c0 = res["plain"]
+        for name, (s, c) in res.items():
+            identical &= (s["cex"] == s0["cex"] and s["clean_label"] == s0["clean_label"]
+                          and np.array_equal(c["rank"], c0["rank"]) and np.array_equal(c["k"], c0["k"]))
+        if s0["cex_total"] > 0:
+            rows.append({name: (s["points_before_first"], s["ttfc_seconds"]) for name, (s, _) in res.items()})
     med = lambda v: float(np.median(v)) if len(v) else None
     out = dict(
+        labels="top 5% of candidates by record count per image", train_images=len(w.images),
         train_samples=int(len(Y)), train_positive=int(Y.sum()), epochs=20, batch=4096,
         loss_first=float(losses[0]), loss_last=float(losses[-1]), train_seconds=round(t_train, 3),
-        heldout_images=len(held), heldout_unsafe=len(unsafe),
-        identical_verdicts=all(r[1] for r in rows),
-        ttfc_plain_median_s=med([r[2] for r in unsafe]), ttfc_learned_median_s=med([r[3] for r in unsafe]),
-        points_before_first_plain_median=med([r[4] for r in unsafe]),
-        points_before_first_learned_median=med([r[5] for r in unsafe]),
-        learned_first_earlier=int(sum(1 for r in unsafe if r[5] < r[4])),
-        leg_seconds=round(time.perf_counter() - t_all, 2))
-    if unsafe:
-        out["ttfc_speedup_median"] = med([r[2] / r[3] for r in unsafe if r[3] > 0])
-        out["points_before_first_ratio_median"] = med([(r[4] + 1) / (r[5] + 1) for r in unsafe])
-        # totals over the unsafe held-out images (the tail of late first hits counts)
-        out["ttfc_plain_total_s"] = float(sum(r[2] for r in unsafe))
-        out["ttfc_learned_total_s"] = float(sum(r[3] for r in unsafe))
-        out["points_before_first_plain_total"] = int(sum(r[4] for r in unsafe))
-        out["points_before_first_learned_total"] = int(sum(r[5] for r in unsafe))
-        # The first round of the persistent grid (two workgroups of four waves
-        # per CU, one 64-point chunk each) is visited at once, so the order
-        # only decides the time of first hits that lie beyond it.
-        n_cu = ctx.device_info()[0]
-        round_pts = n_cu * 2 * 4 * 64
-        late = [r for r in unsafe if r[4] >= round_pts]
-        out["first_round_points"] = int(round_pts)
-        out["late_images"] = len(late)
-        if late:
-            out["ttfc_plain_late_median_s"] = med([r[2] for r in late])
-            out["ttfc_learned_late_median_s"] = med([r[3] for r in late])
-            out["ttfc_late_speedup_median"] = med([r[2] / r[3] for r in late if r[3] > 0])
+        heldout_images=len(held), heldout_unsafe=len(rows), identical_verdicts=bool(identical))
+    n_cu = ctx.device_info()[0]
+    # the first round of the persistent grid (two workgroups of four waves
+    # per compute unit, one 64-point chunk each) is visited at once, so the
+    # order only decides the time of first hits that lie beyond it
+    round_pts = n_cu * 2 * 4 * 64
+    out["first_round_points"] = int(round_pts)
+    late = [r for r in rows if r["plain"][0] >= round_pts]
+    out["late_images"] = len(late)
+    for name, _ in orders:
+        pb = [r[name][0] for r in rows]
+        tt = [r[name][1] for r in rows]
+        out[name] = dict(
+            points_before_first_median=med(pb), points_before_first_total=int(sum(pb)),
+            ttfc_median_s=med(tt), ttfc_mean_s=float(np.mean(tt)) if tt else None,
+            ttfc_total_s=float(sum(tt)),
+            ttfc_late_median_s=med([r[name][1] for r in late]),
+            first_before_plain=int(sum(1 for r in rows if r[name][0] < r["plain"][0])))
+    out["leg_seconds"] = round(time.perf_counter() - t_all, 2)
     return out
 
 

@@ -118,6 +118,7 @@ struct PropDev {
     int32_t m;             // |D|
     int32_t n;             // pixels
     int32_t tie0;          // clean image has an exact top-2 tie (written by the clean pass)
+    int32_t clean_done;    // first-layer slices of the integer clean pass finished; 0 when uploaded
     int16_t deltas[kMaxDeltas];
 };
 

@@ -29,6 +29,9 @@ __device__ __forceinline__ int pack4(int a0, int a1, int a2, int a3) {
 constexpr int kFwdThreads = 1024;
 constexpr int kFwdSplit = 4;  // every dot product is split over this many threads
 
+__device__ void dense_tail_block(const QNetDev &net, int *act0, int *act1, int (*part)[kMaxWidth], int32_t *pot,
+                                 int *label_out, int *tie_out);
+
 // xs: n pixel values; act0/act1: scratch of kMaxWidth ints each; part:
 // kFwdSplit x kMaxWidth ints of partial sums.  Every layer's dot products are
 // split over the inputs (short dependent chains, coalesced weight reads).
@@ -81,20 +84,37 @@ __device__ void dense_forward_block(const QNetDev &net, const int *xs, int *act0
         }
     }
     __syncthreads();
+    dense_tail_block(net, act0, act1, part, pot, label_out, tie_out);
+}
+
+// Layers 2..L and the label of one image whose first-layer activations
+// (natural order, requantised unless the net has one layer) are in act0.
+// act1 and part are scratch as above; pot as above (layers >= 2).
+__device__ void dense_tail_block(const QNetDev &net, int *act0, int *act1, int (*part)[kMaxWidth], int32_t *pot,
+                                 int *label_out, int *tie_out) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
     int *in = act0, *out = act1;
     int po = net.dims[1];
     for (int l = 2; l <= net.L; ++l) {
         const int nin = net.dims[l - 1], nout = net.dims[l];
         const int8_t *W = net.Wd[l];
         const bool wide = (nin % 16) == 0 && (reinterpret_cast<uintptr_t>(W) % 16) == 0;
+        // every dot product split sp ways, as many as the block's threads
+        // allow (one task each where possible: the loads of a task are issued
+        // together, so a layer costs about one memory round trip), at most
+        // one 16-weight load per split point and within the partial sums
+        const int units = wide ? nin / 16 : nin;
+        const int split = max(1, min(min(nthr / nout, units), kFwdSplit * kMaxWidth / nout));
         // split points on 16-weight boundaries when the rows are read 16 at a time
-        const int seg = wide ? (nin / 16 + kFwdSplit - 1) / kFwdSplit * 16 : (nin + kFwdSplit - 1) / kFwdSplit;
-        for (int t = tid; t < nout * kFwdSplit; t += nthr) {
-            const int j = t / kFwdSplit, sp = t % kFwdSplit;
+        const int seg = wide ? (units + split - 1) / split * 16 : (nin + split - 1) / split;
+        int *const pf = &part[0][0];                     // [split][nout]
+        for (int t = tid; t < nout * split; t += nthr) {
+            const int j = t / split, sp = t % split;
             const int i0 = sp * seg, i1 = min(nin, i0 + seg);
             const int8_t *row = W + (int64_t)j * nin;
             int u = 0;
             if (wide) {
+#pragma unroll 4
                 for (int i = i0; i < i1; i += 16) {
                     const int4 w = *reinterpret_cast<const int4 *>(row + i);
                     const int ww[4] = {w.x, w.y, w.z, w.w};
@@ -108,13 +128,12 @@ __device__ void dense_forward_block(const QNetDev &net, const int *xs, int *act0
 #pragma unroll 8
                 for (int i = i0; i < i1; ++i) u += (int)row[i] * in[i];
             }
-            part[sp][j] = u;
+            pf[sp * nout + j] = u;
         }
         __syncthreads();
         for (int j = tid; j < nout; j += nthr) {
             int u = net.bd[l][j];
-#pragma unroll
-            for (int sp = 0; sp < kFwdSplit; ++sp) u += part[sp][j];
+            for (int sp = 0; sp < split; ++sp) u += pf[sp * nout + j];
             if (pot) pot[po + j] = u;
             out[j] = (l < net.L) ? requant_relu(u, net.shift[l - 1]) : u;
         }
@@ -153,22 +172,81 @@ __global__ void __launch_bounds__(kFwdThreads) forward_q8_kernel(QNetDev net, co
 
 // Clean pass of the properties listed in prop_ids: first-layer potentials in
 // sigma order (the base of every incremental update, stored at the property's
-// index) and the clean label.
-__global__ void __launch_bounds__(kFwdThreads) clean_q8_kernel(QNetDev net, PropDev *props,
-                                                               const int32_t *prop_ids, int32_t n_ids,
-                                                               int32_t *u0_store, int64_t u0_stride) {
-    __shared__ int xs[kMaxWidth];
+// index) and the clean label.  Block b of the grid takes property
+// prop_ids[b / S] and the first-layer neurons of slice b % S (S = H1 /
+// clean_slice(H1)) over all pixels; the last of a property's S blocks to
+// finish (counted in its clean_done, which starts at a multiple of S) runs
+// the later layers from the stored potentials and writes the label.  One
+// property thus spreads over S compute units instead of one.
+__host__ __device__ inline int clean_slice(int H1) { return H1 % 64 == 0 ? 64 : 16; }
+constexpr int kCleanThreads = 1024;
+// a slice's partial sums, segs x slice = 4 kCleanThreads ints, fit in part
+static_assert(4 * kCleanThreads <= kFwdSplit * kMaxWidth, "clean pass partial sums");
+
+__global__ void __launch_bounds__(kCleanThreads) clean_q8_kernel(QNetDev net, PropDev *props,
+                                                                 const int32_t *prop_ids, int32_t n_ids,
+                                                                 int32_t *u0_store, int64_t u0_stride) {
     __shared__ int a0[kMaxWidth], a1[kMaxWidth];
     __shared__ int part[kFwdSplit][kMaxWidth];
-    __shared__ int lab, tie;
-    for (int t = blockIdx.x; t < n_ids; t += gridDim.x) {
-        const int pid = prop_ids[t];
+    __shared__ int lab, tie, last;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int n = net.dims[0], H1 = net.H[1];
+    const int slice = clean_slice(H1), S = H1 / slice;
+    const int G = slice / 4;                             // four neurons per 32-bit weight word
+    const int segs = nthr / G;                           // pixel segments (segs * slice <= 4 kMaxWidth)
+    const int G1 = H1 / 4;
+    for (int64_t b = blockIdx.x; b < (int64_t)n_ids * S; b += gridDim.x) {
+        const int pid = prop_ids[b / S];
+        const int w = (int)(b % S);
         const uint8_t *x = props[pid].image;
-        for (int i = threadIdx.x; i < net.dims[0]; i += blockDim.x) xs[i] = x[i];
+        int32_t *u0s = u0_store + (int64_t)pid * u0_stride;
+        // partial sums of the slice over this thread's pixel segment
+        const int grp = tid % G, sg = tid / G;
+        const int seg = (n + segs - 1) / segs;
+        const int i0 = sg * seg, i1 = min(n, i0 + seg);
+        const int *w4 = reinterpret_cast<const int *>(net.W1T) + w * G + grp;   // row stride G1 words
+        int u0 = 0, u1 = 0, u2 = 0, u3 = 0;
+#pragma unroll 8
+        for (int i = i0; i < i1; ++i) {
+            const int wv = w4[(int64_t)i * G1];
+            const int xv = x[i];
+            u0 += (int)(int8_t)wv * xv;
+            u1 += (int)(int8_t)(wv >> 8) * xv;
+            u2 += (int)(int8_t)(wv >> 16) * xv;
+            u3 += (wv >> 24) * xv;
+        }
+        int *pf = &part[0][0];                            // [segs][slice]
+        pf[sg * slice + 4 * grp + 0] = u0;
+        pf[sg * slice + 4 * grp + 1] = u1;
+        pf[sg * slice + 4 * grp + 2] = u2;
+        pf[sg * slice + 4 * grp + 3] = u3;
         __syncthreads();
-        dense_forward_block(net, xs, a0, a1, part, nullptr, u0_store + (int64_t)pid * u0_stride, &lab, &tie);
+        if (tid < slice) {
+            const int q = w * slice + tid;
+            int u = net.b1s[q];
+            for (int t = 0; t < segs; ++t) u += pf[t * slice + tid];
+            u0s[q] = u;
+        }
+        // publish the slice, then count it (release); the block that
+        // completes the count sees every slice (acquire)
+        __threadfence();
         __syncthreads();
-        if (threadIdx.x == 0) { props[pid].label0 = lab; props[pid].tie0 = tie; }
+        if (tid == 0) last = (atomicAdd(&props[pid].clean_done, 1) + 1) % S == 0;
+        __syncthreads();
+        if (last) {
+            __threadfence();
+            for (int q = tid; q < H1; q += nthr) {
+                const int neuron = sigma64(q);
+                if (neuron < net.dims[1]) {
+                    const int u = u0s[q];
+                    a0[neuron] = (net.L > 1) ? requant_relu(u, net.shift[0]) : u;
+                }
+            }
+            __syncthreads();
+            dense_tail_block(net, a0, a1, part, nullptr, &lab, &tie);
+            __syncthreads();
+            if (tid == 0) { props[pid].label0 = lab; props[pid].tie0 = tie; }
+        }
         __syncthreads();
     }
 }
@@ -259,8 +337,9 @@ hipError_t launch_forward_q8(const QNetDev &net, const uint8_t *images, int64_t 
 hipError_t launch_clean_q8(const QNetDev &net, PropDev *props, const int32_t *prop_ids,
                            int32_t n_ids, int32_t *u0_store, int64_t u0_stride, hipStream_t s) {
     if (n_ids <= 0) return hipSuccess;
-    const int grid = std::min(n_ids, 4096);
-    hipLaunchKernelGGL(clean_q8_kernel, dim3(grid), dim3(kFwdThreads), 0, s, net, props, prop_ids, n_ids,
+    if (net.H[1] % 16) return hipErrorInvalidValue;
+    const int grid = (int)std::min<int64_t>((int64_t)n_ids * (net.H[1] / clean_slice(net.H[1])), 8192);
+    hipLaunchKernelGGL(clean_q8_kernel, dim3(grid), dim3(kCleanThreads), 0, s, net, props, prop_ids, n_ids,
                        u0_store, u0_stride);
     return hipGetLastError();
 }

@@ -246,3 +246,50 @@ def test_ranked_order_many_candidates(ctx, orc):
         assert s["points_before_first"] == expect, (t, key_ties)
         checked += 1
     assert checked >= 2
+
+
+def top_count_labels(counts, frac=0.05):
+    """1 for the candidates of one image whose record count lies in the top
+    frac of its counts (and is nonzero), else 0."""
+    return ((counts >= np.quantile(counts, 1.0 - frac)) & (counts > 0)).astype(np.float32)
+
+
+def test_trained_proposer_finds_counterexamples_earlier(ctx):
+    """Trained on the 64 benchmark images' records (label: the candidate is
+    among the 5% taking part in the most counterexamples of its image), the
+    proposer's order reaches the first counterexample of held-out images after
+    fewer points, at the median, than both the plain order and the same
+    network untrained; all three orders return identical records."""
+    from paper_1907_12933_amd import ibmc
+    w = I.workload_blob784()
+    m = ibmc.Mlp(ctx, w.net)
+    D = w.deltas
+    sums, recs, _, _ = ibmc.ibmc_check_batch(ctx, [(m, x, D, 1, 2) for x in w.images], cex_capacity=1 << 25)
+    feats, labels = [], []
+    for i, x in enumerate(w.images):
+        lo, hi = np.searchsorted(recs["prop"], i, "left"), np.searchsorted(recs["prop"], i, "right")
+        assert hi - lo == sums[i]["cex_total"]
+        counts = ibmc.ibmc_count_candidates(ctx, 784, len(D), recs[lo:hi])
+        feats.append(ibmc.ibmc_proposer_features(ctx, m, x, 28, 28, D))
+        labels.append(top_count_labels(counts))
+    trained = ibmc.Proposer(ctx, seed=4)
+    losses = ibmc.ibmc_proposer_train(ctx, trained, np.concatenate(feats), np.concatenate(labels), epochs=20,
+                                      batch=4096, lr=1e-3, seed=4)
+    assert losses[-1] < losses[0]
+    untrained = ibmc.Proposer(ctx, seed=4)
+    pbf = {"plain": [], "untrained": [], "trained": []}
+    for x in I.heldout_blob_images():
+        out = {}
+        for name, p in (("plain", None), ("untrained", untrained), ("trained", trained)):
+            out[name] = ibmc.ibmc_check_property_ranked(ctx, m, p, x, 28, 28, D, 1, 2, cex_capacity=1 << 22)
+        s0, c0 = out["plain"]
+        for name, (s, c) in out.items():
+            assert s["cex"] == s0["cex"] and s["clean_label"] == s0["clean_label"]
+            assert np.array_equal(c["k"], c0["k"]) and np.array_equal(c["rank"], c0["rank"])
+            assert np.array_equal(c["new_label"], c0["new_label"])
+        if s0["cex_total"]:
+            for name, (s, _) in out.items():
+                pbf[name].append(s["points_before_first"])
+    assert len(pbf["plain"]) >= 20
+    med = {k: float(np.median(v)) for k, v in pbf.items()}
+    assert med["trained"] < med["plain"] and med["trained"] < med["untrained"], med
