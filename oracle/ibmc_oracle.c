@@ -25,6 +25,11 @@
  *     one in exactly k pixels p1 < ... < pk, pixel pj set to
  *     clamp(x[pj] + D[ij], 0, 255) for a delta index ij.  Points are counted
  *     as enumerated (duplicates from 0 in D or from clamping included).
+ *   - the L2-ball restricted set (Eq. (9) with the distance of Eq. (7) on
+ *     pixel values 0..255, b^2 given as an integer r2): every image x' in
+ *     {0..255}^n with sum (x' - x)^2 <= r2, at bound k those that differ
+ *     from the clean one in exactly k pixels (nothing is clamped: offsets
+ *     that leave [0, 255] do not give an image); points are counted once.
  *   - rank of a point: (number of k-subsets lexicographically before S)
  *     * |D|^k + the delta indices read as a base-|D| number, i1 most
  *     significant.
@@ -344,8 +349,66 @@ static int enum_first(const net_ref *nr, const uint8_t *x, const int16_t *D, int
     return ORC_OK;
 }
 
+/* L2-ball domain (Sec. III-C, Eq. (9), the restriction R with the Euclidean
+ * distance of Eq. (7)): the images x' in {0..255}^n with
+ * sum_p (x'_p - x_p)^2 <= r2, grouped by support size k (the pixels where
+ * x' differs from x).  For ranks a point of level k is written as its k
+ * pixels and one digit per pixel: the offset e = x'_p - x_p (nonzero,
+ * |e| <= rd = min(floor(sqrt(r2)), 255)) has digit e + rd when negative and
+ * e + rd - 1 when positive, so m = 2 rd digits per pixel and the rank is
+ * (subset rank) m^k + (digits read in base m), as in the box domain. */
+int orc_ball_digits(int64_t r2) {
+    if (r2 < 0) return 0;
+    int64_t r = 0;
+    while ((r + 1) * (r + 1) <= r2) ++r;
+    return (int)(r < 255 ? r : 255);
+}
+
+static int ball_offset(int digit, int rd) { return digit < rd ? digit - rd : digit - rd + 1; }
+
+/* Enumerate level k of the ball with first pixel `first` in rank order,
+ * skipping digit vectors that leave [0, 255] or the ball.  *n_points counts
+ * the points of the domain visited. */
+static int enum_first_ball(const net_ref *nr, const uint8_t *x, int64_t r2, int rd, int k, int first,
+                           int64_t base_rank, int32_t clean, rec_list *cex, int64_t *n_ties, int64_t *n_points,
+                           uint8_t *xp, void *sa, void *sb) {
+    int n = nr->dims[0], m = 2 * rd;
+    int32_t pix[64], dig[64];
+    pix[0] = first;
+    for (int j = 1; j < k; ++j) pix[j] = first + j;
+    int64_t rank = base_rank;
+    do {
+        for (int j = 0; j < k; ++j) dig[j] = 0;
+        do {
+            int64_t sq = 0;
+            int inside = 1;
+            memcpy(xp, x, (size_t)n);
+            for (int j = 0; j < k; ++j) {
+                int e = ball_offset(dig[j], rd);
+                int v = (int)x[pix[j]] + e;
+                if (v < 0 || v > 255) inside = 0;
+                sq += (int64_t)e * e;
+                xp[pix[j]] = (uint8_t)(v < 0 ? 0 : v > 255 ? 255 : v);
+            }
+            if (inside && sq <= r2) {
+                int32_t lab; int tie; double margin;
+                int rc = eval_image(nr, xp, sa, sb, &lab, &tie, &margin);
+                if (rc) return rc;
+                (*n_points)++;
+                if (lab != clean) {
+                    rc = rec_push(cex, k, rank, lab, margin);
+                    if (rc) return rc;
+                }
+                if (tie) (*n_ties)++;
+            }
+            rank++;
+        } while (next_digits(dig, k, m));
+    } while (k > 1 && next_subset_tail(pix, k, n));
+    return ORC_OK;
+}
+
 /* Shared driver of the integer and the float check. */
-static int check_impl(const net_ref *nr, const uint8_t *x, const int16_t *D, int m,
+static int check_impl(const net_ref *nr, const uint8_t *x, const int16_t *D, int m, int64_t ball_r2,
                       int k_min, int k_max, int k_step, int stop_at_first, int64_t cap,
                       int64_t *points, int64_t *cex_count, int64_t *tie_count,
                       int32_t *clean_label, int32_t *first_unsafe_k,
@@ -353,7 +416,11 @@ static int check_impl(const net_ref *nr, const uint8_t *x, const int16_t *D, int
                       int64_t *n_out, int64_t tie_cap, int32_t *tie_k, int64_t *tie_rank,
                       double *tie_margin, int64_t *n_tie_out, int nthreads) {
     int n = nr->dims[0];
-    if (m < 1 || k_min < 0 || k_max < k_min || k_step < 1 || k_max > n || k_max > 64)
+    /* ball_r2 >= 0: the L2-ball domain (D unused, m = 2 rd); else the box D^k */
+    const int ball = ball_r2 >= 0;
+    const int rd = ball ? orc_ball_digits(ball_r2) : 0;
+    if (ball) m = 2 * rd;
+    if ((!ball && m < 1) || k_min < 0 || k_max < k_min || k_step < 1 || k_max > n || k_max > 64)
         return ORC_E_INVALID;
     int mw = max_width(nr->L, nr->dims);
     size_t elt = nr->is_float ? sizeof(double) : sizeof(int64_t);
@@ -369,7 +436,7 @@ static int check_impl(const net_ref *nr, const uint8_t *x, const int16_t *D, int
     if (n_tie_out) *n_tie_out = 0;
     int level = 0;
     for (int k = k_min; k <= k_max; k += k_step, ++level) {
-        points[level] = orc_points(n, m, k);
+        points[level] = ball ? (k == 0) : orc_points(n, m, k);
         cex_count[level] = 0;
         tie_count[level] = 0;
         if (k == 0) {
@@ -377,12 +444,17 @@ static int check_impl(const net_ref *nr, const uint8_t *x, const int16_t *D, int
             tie_count[level] = tie0;
             continue;
         }
+        if (ball && rd == 0) continue;   /* no nonzero offset fits: the level is empty */
         int64_t md = ipow(m, k);
         rec_list *lists = calloc((size_t)n, sizeof(rec_list));
         rec_list *tlists = calloc((size_t)n, sizeof(rec_list));
         int64_t *nties = calloc((size_t)n, sizeof(int64_t));
+        int64_t *npts = calloc((size_t)n, sizeof(int64_t));
         int err = 0;
-        if (!lists || !tlists || !nties) { free(lists); free(tlists); free(nties); return ORC_E_OOM; }
+        if (!lists || !tlists || !nties || !npts) {
+            free(lists); free(tlists); free(nties); free(npts);
+            return ORC_E_OOM;
+        }
 #pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
         {
             uint8_t *xp = malloc((size_t)n);
@@ -393,9 +465,10 @@ static int check_impl(const net_ref *nr, const uint8_t *x, const int16_t *D, int
                 /* subsets starting below `first` come first in lexicographic order */
                 int64_t before = 0;
                 for (int q = 0; q < first; ++q) before += binom(n - 1 - q, k - 1);
-                int r = enum_first(nr, x, D, m, k, first, before * md, clean, &lists[first],
-                                   tie_k ? &tlists[first] : NULL, &nties[first],
-                                   xp, ta, tb);
+                int r = ball ? enum_first_ball(nr, x, ball_r2, rd, k, first, before * md, clean, &lists[first],
+                                               &nties[first], &npts[first], xp, ta, tb)
+                             : enum_first(nr, x, D, m, k, first, before * md, clean, &lists[first],
+                                          tie_k ? &tlists[first] : NULL, &nties[first], xp, ta, tb);
                 if (r) err = r;
             }
             free(xp); free(ta); free(tb);
@@ -410,6 +483,7 @@ static int check_impl(const net_ref *nr, const uint8_t *x, const int16_t *D, int
             }
             cex_count[level] += r->n;
             tie_count[level] += nties[first];
+            if (ball) points[level] += npts[first];
             rec_list *t = &tlists[first];
             for (int64_t i = 0; i < t->n; ++i) {
                 if (tie_written < tie_cap) {
@@ -420,7 +494,7 @@ static int check_impl(const net_ref *nr, const uint8_t *x, const int16_t *D, int
             }
         }
         for (int first = 0; first < n; ++first) { rec_free(&lists[first]); rec_free(&tlists[first]); }
-        free(lists); free(tlists); free(nties);
+        free(lists); free(tlists); free(nties); free(npts);
         if (err) return err;
         if (cex_count[level] > 0 && *first_unsafe_k < 0) *first_unsafe_k = k;
         if (stop_at_first && cex_count[level] > 0) { ++level; break; }
@@ -444,7 +518,24 @@ int orc_q8_check(int L, const int32_t *dims, const int8_t *W, const int32_t *b,
                  int nthreads) {
     if (L < 1 || !dims || !W || !b || !x || !D) return ORC_E_INVALID;
     net_ref nr = {0, L, dims, W, b, shift, NULL, NULL, 0.0};
-    return check_impl(&nr, x, D, m, k_min, k_max, k_step, stop_at_first, cap, points, cex_count,
+    return check_impl(&nr, x, D, m, -1, k_min, k_max, k_step, stop_at_first, cap, points, cex_count,
+                      tie_count, clean_label, first_unsafe_k, out_k, out_rank, out_label, n_out,
+                      0, NULL, NULL, NULL, NULL, nthreads);
+}
+
+/* Integer check over the L2-ball domain (see orc_ball_digits): the levels,
+ * counts, ranks and records as in orc_q8_check, points[] the number of
+ * images of each support size inside the ball. */
+int orc_q8_ball_check(int L, const int32_t *dims, const int8_t *W, const int32_t *b,
+                      const int32_t *shift, const uint8_t *x, int64_t r2,
+                      int k_min, int k_max, int k_step, int stop_at_first, int64_t cap,
+                      int64_t *points, int64_t *cex_count, int64_t *tie_count,
+                      int32_t *clean_label, int32_t *first_unsafe_k,
+                      int32_t *out_k, int64_t *out_rank, int32_t *out_label, int64_t *n_out,
+                      int nthreads) {
+    if (L < 1 || !dims || !W || !b || !x || r2 < 0) return ORC_E_INVALID;
+    net_ref nr = {0, L, dims, W, b, shift, NULL, NULL, 0.0};
+    return check_impl(&nr, x, NULL, 0, r2, k_min, k_max, k_step, stop_at_first, cap, points, cex_count,
                       tie_count, clean_label, first_unsafe_k, out_k, out_rank, out_label, n_out,
                       0, NULL, NULL, NULL, NULL, nthreads);
 }
@@ -461,7 +552,7 @@ int orc_f64_check(int L, const int32_t *dims, const double *W, const double *b,
                   int64_t *n_tie_out, int nthreads) {
     if (L < 1 || !dims || !W || !b || !x || !D) return ORC_E_INVALID;
     net_ref nr = {1, L, dims, NULL, NULL, NULL, W, b, tie_rel};
-    return check_impl(&nr, x, D, m, k_min, k_max, k_step, stop_at_first, cap, points, cex_count,
+    return check_impl(&nr, x, D, m, -1, k_min, k_max, k_step, stop_at_first, cap, points, cex_count,
                       tie_count, clean_label, first_unsafe_k, out_k, out_rank, out_label, n_out,
                       tie_cap, tie_k, tie_rank, tie_margin, n_tie_out, nthreads);
 }

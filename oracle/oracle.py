@@ -42,6 +42,10 @@ def lib():
         L.orc_q8_check.argtypes = [C.c_int, I32P, I8P, I32P, I32P, U8P, I16P, C.c_int,
                                    C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64,
                                    I64P, I64P, I64P, I32P, I32P, I32P, I64P, I32P, I64P, C.c_int]
+        L.orc_ball_digits.argtypes = [C.c_int64]
+        L.orc_q8_ball_check.argtypes = [C.c_int, I32P, I8P, I32P, I32P, U8P, C.c_int64,
+                                        C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, I64P, I64P, I64P,
+                                        I32P, I32P, I32P, I64P, I32P, I64P, C.c_int]
         L.orc_f64_check.argtypes = [C.c_int, I32P, F64P, F64P, U8P, I16P, C.c_int,
                                     C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, C.c_double,
                                     I64P, I64P, I64P, I32P, I32P, I32P, I64P, I32P, I64P,
@@ -158,6 +162,32 @@ def q8_check(net, x, deltas, k_min=1, k_max=2, k_step=1, stop_at_first=False, ca
     return dict(levels=list(range(k_min, k_max + 1, k_step))[:lev], points=pts[:lev], cex=cx[:lev],
                 ties=ti[:lev], clean_label=int(cl[0]), first_unsafe_k=int(fu[0]), cex_total=n,
                 cex_k=ok[:w].copy(), cex_rank=orr[:w].copy(), cex_label=ol[:w].copy())
+
+
+def ball_digits(r2):
+    """Digits per pixel of the L2-ball encoding: m = 2 * ball_digits(r2)."""
+    return int(lib().orc_ball_digits(int(r2)))
+
+
+def q8_ball_check(net, x, r2, k_min=1, k_max=2, k_step=1, stop_at_first=False, cap=1 << 22, nthreads=None):
+    """Exhaustive integer check over the images within squared L2 distance r2
+    of x, level k = support size.  Same result layout as q8_check."""
+    dims, W, b, sh = _flat_q8(net)
+    x = np.ascontiguousarray(x, np.uint8)
+    nl = _levels(k_min, k_max, k_step)
+    pts = np.zeros(nl, np.int64); cx = np.zeros(nl, np.int64); ti = np.zeros(nl, np.int64)
+    cl = np.zeros(1, np.int32); fu = np.zeros(1, np.int32)
+    ok = np.zeros(cap, np.int32); orr = np.zeros(cap, np.int64); ol = np.zeros(cap, np.int32)
+    nout = np.zeros(1, np.int64)
+    lev = _ck(lib().orc_q8_ball_check(len(dims) - 1, _p(dims, I32P), _p(W, I8P), _p(b, I32P), _p(sh, I32P),
+                                      _p(x, U8P), int(r2), k_min, k_max, k_step, int(stop_at_first), cap,
+                                      _p(pts, I64P), _p(cx, I64P), _p(ti, I64P), _p(cl, I32P), _p(fu, I32P),
+                                      _p(ok, I32P), _p(orr, I64P), _p(ol, I32P), _p(nout, I64P),
+                                      _threads(nthreads)))
+    n = int(nout[0]); w = min(n, cap)
+    return dict(levels=list(range(k_min, k_max + 1, k_step))[:lev], points=pts[:lev], cex=cx[:lev],
+                ties=ti[:lev], clean_label=int(cl[0]), first_unsafe_k=int(fu[0]), cex_total=n,
+                cex_k=ok[:w].copy(), cex_rank=orr[:w].copy(), cex_label=ol[:w].copy(), m=2 * ball_digits(r2))
 
 
 def f64_check(net, x, deltas, k_min=1, k_max=2, k_step=1, stop_at_first=False, cap=1 << 22,
