@@ -258,6 +258,41 @@ ibmc_status ibmc_check_property_dev(ibmc_ctx *ctx, const ibmc_mlp *net, const ui
                                     const ibmc_check_opts *opts, ibmc_check_summary *out,
                                     ibmc_cex *cex_buf, ibmc_cex *near_tie_buf);
 
+/* The L2-ball domain (Sec. III-C: the restriction R of Eq. (9) with the
+ * Euclidean distance of Eq. (7), on pixel values): every image x' in
+ * {0..255}^n with sum_p (x'_p - x_p)^2 <= radius_sq, checked level by level,
+ * level k holding the images that differ from `image` in exactly k pixels.
+ * Nothing is clamped: an offset that takes a pixel out of [0, 255] gives no
+ * image.  Records use the point rank of the delta-set domain with the
+ * implicit delta set -rd..-1, 1..rd, rd = ibmc_ball_digits(radius_sq) (so
+ * ibmc_decode_point with n_deltas = 2 rd decodes them, digit i < rd being
+ * offset i - rd and digit i >= rd offset i - rd + 1); summary.points[] count
+ * the images of each level that lie in the ball.  opts as for
+ * ibmc_check_property except: integer networks whose hidden layers (one or
+ * two) have at most 64 units and at most 16 classes (else IBMC_E_UNIMPL);
+ * near_tie_capacity must be 0; no resume_cursor / chunk_budget
+ * (IBMC_E_UNIMPL); radius_sq in [0, 2^30] (else IBMC_E_INVALID).  A radius
+ * below 1 leaves every level k >= 1 empty. */
+int32_t ibmc_ball_digits(int64_t radius_sq);   /* min(floor(sqrt(radius_sq)), 255); 0 if negative */
+ibmc_status ibmc_check_ball(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *image, int32_t n_pixels,
+                            int64_t radius_sq, const ibmc_check_opts *opts, ibmc_check_summary *out,
+                            ibmc_cex *cex_buf);
+
+/* One L2-ball property of a batch (image in host memory). */
+typedef struct {
+    const ibmc_mlp *net;
+    const uint8_t *image;
+    int64_t radius_sq;
+    int32_t k_min, k_max, k_step;
+    int32_t reserved;
+} ibmc_ball_property;
+
+/* ibmc_check_ball over many properties in one launch per network (records
+ * tagged with their property index, as in ibmc_check_batch; opts k_min /
+ * k_max / k_step are ignored in favour of the properties'). */
+ibmc_status ibmc_check_ball_batch(ibmc_ctx *ctx, const ibmc_ball_property *props, int32_t n_props,
+                                  const ibmc_check_opts *opts, ibmc_check_summary *outs, ibmc_cex *cex_buf);
+
 /* Check many properties, possibly over different networks, as one
  * batch.  outs: one summary per property.  Records of all properties share
  * cex_buf / near_tie_buf (capacities in opts), tagged with ibmc_cex.prop.

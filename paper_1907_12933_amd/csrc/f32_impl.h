@@ -131,7 +131,8 @@ constexpr int kAbortPollTickets = 64;
 // (polls counts them; never at a wave's first ticket, where every wave of the
 // grid would read host memory at once); a wave that sees the abort raises
 // the stop flag.
-__device__ __forceinline__ int64_t f32_ticket(const FEnumParams &P, int &q, int &tries, int64_t &end, int &polls) {
+template <class PT>
+__device__ __forceinline__ int64_t f32_ticket(const PT &P, int &q, int &tries, int64_t &end, int &polls) {
     while (tries < kF32Queues) {
         const int64_t lo = (int64_t)q * P.slice;
         const int64_t hi = min(lo + P.slice, P.total_chunks);

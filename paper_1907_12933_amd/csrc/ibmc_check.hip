@@ -85,6 +85,19 @@ const EnumVariant *pick_variant(ibmc_ctx *ctx, const ibmc_mlp *net) {
     return best;
 }
 
+// Integer networks the lane kernels serve run there unless a matrix-core
+// variant is forced or tuned for the shape (and always for resumable calls,
+// which only the matrix-core kernel implements, where allowed is false).
+bool use_lane(ibmc_ctx *ctx, const ibmc_mlp *net, bool allowed) {
+    if (!allowed || !net->lane.ok) return false;
+    std::string want = net->forced_variant;
+    if (want.empty()) {
+        auto it = ctx->tuned.find(shape_key(net));
+        if (it != ctx->tuned.end()) want = it->second;
+    }
+    return want.empty() || want == kLaneVariantName;
+}
+
 struct Level {
     int prop;
     int k;
@@ -99,15 +112,34 @@ struct BatchState {
     int n_slots = 0;
 };
 
-static ibmc_status validate_props(const ibmc_property *props, int32_t n_props, const ibmc_check_opts *o) {
+// Digits per pixel side of the L2-ball domain: min(floor(sqrt(r2)), 255).
+static int ball_rd(int64_t r2) {
+    int64_t r = 0;
+    while (r < 255 && (r + 1) * (r + 1) <= r2) ++r;
+    return (int)r;
+}
+
+// props: for ball properties (ball_r2[i] >= 0) n_deltas already holds the
+// digit count 2 rd and deltas is unused.
+static ibmc_status validate_props(const ibmc_property *props, int32_t n_props, const ibmc_check_opts *o,
+                                  const int64_t *ball_r2) {
     if (!props || n_props < 1) return fail(IBMC_E_INVALID, "no properties");
     if (!o) return fail(IBMC_E_INVALID, "opts is null");
     if (o->cex_capacity < 0 || o->near_tie_capacity < 0) return fail(IBMC_E_INVALID, "negative capacity");
     for (int i = 0; i < n_props; ++i) {
         const ibmc_property &p = props[i];
-        if (!p.net || !p.image || !p.deltas) return fail(IBMC_E_INVALID, "property %d: null net/image/deltas", i);
-        if (p.n_deltas < 1 || p.n_deltas > kMaxDeltas)
+        const bool ball = ball_r2 && ball_r2[i] >= 0;
+        if (!p.net || !p.image || (!ball && !p.deltas))
+            return fail(IBMC_E_INVALID, "property %d: null net/image/deltas", i);
+        if (ball) {
+            if (ball_r2[i] > ((int64_t)1 << 30))
+                return fail(IBMC_E_INVALID, "property %d: radius_sq %lld above 2^30", i, (long long)ball_r2[i]);
+            if (p.net->act != IBMC_ACT_RELU_Q8 || !p.net->lane.ok)
+                return fail(IBMC_E_UNIMPL, "property %d: the L2-ball domain needs an integer network with 1-2 hidden "
+                            "layers of at most 64 units and at most 16 classes", i);
+        } else if (p.n_deltas < 1 || p.n_deltas > kMaxDeltas) {
             return fail(IBMC_E_INVALID, "property %d: n_deltas %d outside [1, %d]", i, p.n_deltas, kMaxDeltas);
+        }
         const int n = p.net->dims[0];
         if ((int64_t)n * p.n_deltas >= ((int64_t)1 << 24))
             return fail(IBMC_E_UNIMPL, "property %d: pixels * deltas = %lld must be below 2^24", i,
@@ -121,7 +153,7 @@ static ibmc_status validate_props(const ibmc_property *props, int32_t n_props, c
             ++levels;
             // points of the level must fit comfortably in int64
             __int128 pts = (__int128)binom_small(n, k);
-            for (int j = 0; j < k; ++j) pts *= p.n_deltas;
+            for (int j = 0; j < k; ++j) pts *= std::max(p.n_deltas, 1);
             if (pts > ((__int128)1 << 56)) return fail(IBMC_E_UNIMPL, "property %d: level %d too large", i, k);
         }
         if (levels > IBMC_MAX_LEVELS) return fail(IBMC_E_INVALID, "property %d: %d levels > %d", i, levels, IBMC_MAX_LEVELS);
@@ -214,6 +246,7 @@ static ibmc_status fetch_sorted(ibmc_ctx *ctx, const DevRec *drecs, int64_t n, i
 struct NetPlan {
     const ibmc_mlp *net;
     std::vector<int> ids;
+    bool lane = false;      // integer network on the lane-per-point kernel
     const EnumVariant *v = nullptr;
     int64_t total = 0;
     int64_t limit = 0;      // chunks handed out stop here (a budgeted call), else total
@@ -227,6 +260,7 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
                               const ibmc_check_opts *o, BatchState &B,
                               const std::vector<std::vector<int>> &level_sel, bool images_on_device,
                               std::vector<unsigned long long> &slot_cex, std::vector<unsigned long long> &slot_ties,
+                              std::vector<unsigned long long> &slot_points,
                               std::vector<CexRec> &recs, std::vector<CexRec> &ties, int64_t &rec_total,
                               int64_t &tie_total, double &kernel_seconds, int &launches,
                               CexRec *direct_recs = nullptr, CexRec *direct_ties = nullptr, bool direct_dev = false,
@@ -251,11 +285,12 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
     }
     const int NN = (int)plans.size();
     // counters: [1] rec_count, [2] first_chunk, [3] tie_count, [4] stop flag,
-    //           [8, 8+NN) per-network queues (integer kernels), then
-    //           slot_cex[n_slots], slot_ties[n_slots], then per network the
-    //           float kernels' kF32Queues counters, kQueueStride apart
-    const int64_t q0 = 8, sc0 = 8 + NN, st0 = sc0 + B.n_slots;
-    const int64_t fq0 = (st0 + B.n_slots + kQueueStride - 1) / kQueueStride * kQueueStride;
+    //           [8, 8+NN) per-network queues (integer matrix-core kernels),
+    //           then slot_cex[n_slots], slot_ties[n_slots], slot_points[n_slots]
+    //           (lane kernels), then per network the sliced queues of the
+    //           float and lane kernels: kF32Queues counters, kQueueStride apart
+    const int64_t q0 = 8, sc0 = 8 + NN, st0 = sc0 + B.n_slots, sp0 = st0 + B.n_slots;
+    const int64_t fq0 = (sp0 + B.n_slots + kQueueStride - 1) / kQueueStride * kQueueStride;
     const int64_t n_ctr = fq0 + (int64_t)NN * kF32Queues * kQueueStride;
     IBMC_TRY(ctx->counters.reserve(n_ctr * 8));
     unsigned long long *ctr = ctx->counters.as<unsigned long long>();
@@ -277,12 +312,17 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
         const ibmc_mlp *net = pl.net;
         const bool q8 = net->act == IBMC_ACT_RELU_Q8;
         int CH = q8 ? 0 : enum_f32_chunk(net->fd);
-        if (q8) {
+        bool need_lane = false;   // an L2-ball property runs on the lane kernel only
+        for (int pid : pl.ids) need_lane |= B.hprops[pid].ball != 0;
+        if (q8) pl.lane = need_lane || use_lane(ctx, net, resume == 0 && budget == 0);
+        if (pl.lane) {
+            CH = kLaneChunk;
+        } else if (q8) {
             pl.v = pick_variant(ctx, net);
             if (!pl.v) return fail(IBMC_E_UNIMPL, "no enumeration kernel for network %s", shape_key(net).c_str());
             CH = pl.v->chunk;
         }
-        if (q8) {
+        if (q8 && !pl.lane) {
             int maxe = 0;
             for (int pid : pl.ids)
                 for (int j = 0; j < props[pid].n_deltas; ++j)
@@ -293,7 +333,7 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
             pl.vb_hi = (int32_t)(16384 + M2);
         }
         // segment groups: the packed integer path keeps kSegGroup bases per wave
-        const int W = (q8 && pl.packed) ? kSegGroup : 1;
+        const int W = (q8 && !pl.lane && pl.packed) ? kSegGroup : 1;
         pl.job_off = jobs.size();
         for (int pid : pl.ids) {
             const int n = net->dims[0], m = props[pid].n_deltas;
@@ -302,6 +342,7 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
                 if (k == 0) continue;
                 std::vector<int64_t> qc;
                 const int64_t ch = plan_plain_level(n, m, k, CH, W, qc);
+                if (ch == 0) continue;   // an empty level (a ball with no nonzero offset)
                 EnumJob J{};
                 J.prop = pid;
                 J.k = k;
@@ -317,7 +358,11 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
             }
         }
         pl.n_jobs = jobs.size() - pl.job_off;
-        if (q8) {
+        if (pl.lane) {
+            const int g = lane_enum_grid(net->lane, ctx->n_cu);
+            if (g < 1) return fail(IBMC_E_UNIMPL, "no lane kernel for network %s", shape_key(net).c_str());
+            pl.grid = (int)std::min<int64_t>(g, std::max<int64_t>(1, pl.total));
+        } else if (q8) {
             int occ = 0;
             HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, pl.v->fn, 256,
                                                                 (size_t)enum_lds_bytes(*pl.v, net->qd)));
@@ -336,14 +381,16 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
     // integer kernels (whose unused slots hold sentinels)
     int64_t rec_slots = cap;
     for (auto &pl : plans)
-        if (pl.net->act == IBMC_ACT_RELU_Q8) rec_slots += (int64_t)pl.grid * 4 * kRecBlock;
+        if (pl.net->act == IBMC_ACT_RELU_Q8 && !pl.lane) rec_slots += (int64_t)pl.grid * 4 * kRecBlock;
     IBMC_TRY(ctx->recs.reserve((size_t)std::max<int64_t>(rec_slots, 1) * sizeof(DevRec)));
     IBMC_TRY(ctx->qcum.reserve(std::max<size_t>(qcum_all.size(), 1) * 8));
     if (!qcum_all.empty())
         HIP_OK(hipMemcpyAsync(ctx->qcum.p, qcum_all.data(), qcum_all.size() * 8, hipMemcpyHostToDevice, s));
     for (size_t j = 0; j < jobs.size(); ++j)
         jobs[j].qcum = (qcum_off[j] == (size_t)-1) ? nullptr : ctx->qcum.as<int64_t>() + qcum_off[j];
-    IBMC_TRY(ctx->jobs.upload(jobs.data(), std::max<size_t>(jobs.size(), 1) * sizeof(EnumJob), s));
+    // (no jobs at all: every selected level is k = 0 or empty)
+    if (jobs.empty()) IBMC_TRY(ctx->jobs.reserve(sizeof(EnumJob)));
+    else IBMC_TRY(ctx->jobs.upload(jobs.data(), jobs.size() * sizeof(EnumJob), s));
     IBMC_TRY(ctx->prop_ids.upload(all_ids.data(), std::max<size_t>(all_ids.size(), 1) * 4, s));
     HIP_OK(hipStreamSynchronize(s));  // host staging vectors may go now
 
@@ -360,7 +407,31 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
             HIP_OK(launch_clean_f32(net->fd, dprops, ids, (int32_t)pl.ids.size(), ctx->u0.as<float>(), max_h1, st));
         if (pl.n_jobs == 0 || pl.total == 0) return IBMC_OK;
         const int pi = (int)(&pl - plans.data());
-        if (net->act == IBMC_ACT_RELU_Q8) {
+        if (pl.lane) {
+            LaneParams P{};
+            P.net = net->lane;
+            P.jobs = ctx->jobs.as<EnumJob>() + pl.job_off;
+            P.n_jobs = (int32_t)pl.n_jobs;
+            P.total_chunks = pl.total;
+            P.slice = std::max<int64_t>(1, (pl.total + kF32Queues - 1) / kF32Queues);
+            const int64_t waves_per_slice = std::max<int64_t>(1, (int64_t)pl.grid * 4 / kF32Queues);
+            P.batch = (int32_t)std::max<int64_t>(1, std::min<int64_t>(16, P.slice / (waves_per_slice * 8)));
+            P.props = dprops;
+            P.u0 = ctx->u0.as<int32_t>();
+            P.u0_stride = (int32_t)max_h1;
+            P.queue = ctr + fq0 + (int64_t)pi * kF32Queues * kQueueStride;
+            P.rec_count = ctr + 1;
+            P.rec_cap = rec_slots;
+            P.recs = ctx->recs.as<DevRec>();
+            P.slot_cex = ctr + sc0;
+            P.slot_ties = ctr + st0;
+            P.slot_points = ctr + sp0;
+            P.stop_flag = reinterpret_cast<volatile int32_t *>(ctr + 4);
+            P.abort_host = ctx->flags_dev;
+            if (time_enum) HIP_OK(hipEventRecord(ctx->ek0, st));
+            HIP_OK(launch_enum_lane(pl.grid, P, st));
+            if (time_enum) HIP_OK(hipEventRecord(ctx->ek1, st));
+        } else if (net->act == IBMC_ACT_RELU_Q8) {
             EnumParams P{};
             P.net = net->qd;
             P.jobs = ctx->jobs.as<EnumJob>() + pl.job_off;
@@ -502,14 +573,15 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
         // every queue ticket handed out was worked through: chunks below
         // resume + tickets * batch are done
         *next_cursor = -1;
-        if (NN == 1 && plans[0].net->act == IBMC_ACT_RELU_Q8) {
+        if (NN == 1 && plans[0].net->act == IBMC_ACT_RELU_Q8 && !plans[0].lane) {
             const NetPlan &pl = plans[0];
             const int64_t done = std::min<int64_t>(pl.limit, resume + (int64_t)h[q0] * pl.batch);
             if (done < pl.total) *next_cursor = done;
         }
     }
     slot_cex.assign(h.begin() + sc0, h.begin() + st0);
-    slot_ties.assign(h.begin() + st0, h.begin() + st0 + B.n_slots);
+    slot_ties.assign(h.begin() + st0, h.begin() + sp0);
+    slot_points.assign(h.begin() + sp0, h.begin() + sp0 + B.n_slots);
     // exact total from the level counters; record slots handed out (with the
     // sentinels of partly used blocks) from the record counter
     rec_total = 0;
@@ -540,16 +612,29 @@ static bool rec_less(const CexRec &a, const CexRec &b) {
     return a.rank < b.rank;
 }
 
-ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props, int32_t n_props, const ibmc_check_opts *o,
-                             ibmc_check_summary *outs, ibmc_cex *cex_buf, ibmc_cex *tie_buf, bool images_on_device) {
+ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props_in, int32_t n_props, const ibmc_check_opts *o,
+                             ibmc_check_summary *outs, ibmc_cex *cex_buf, ibmc_cex *tie_buf, bool images_on_device,
+                             const int64_t *ball_r2) {
     clear_error();
     if (!ctx || !outs) return fail(IBMC_E_INVALID, "null ctx / outs");
-    IBMC_TRY(validate_props(props, n_props, o));
+    if (!props_in || n_props < 1) return fail(IBMC_E_INVALID, "no properties");
+    // ball properties: m = 2 rd digits per pixel, no delta table
+    std::vector<ibmc_property> pv(props_in, props_in + n_props);
+    bool any_ball = false;
+    for (int i = 0; i < n_props; ++i)
+        if (ball_r2 && ball_r2[i] >= 0) {
+            pv[i].n_deltas = 2 * ball_rd(ball_r2[i]);
+            pv[i].deltas = nullptr;
+            any_ball = true;
+        }
+    const ibmc_property *props = pv.data();
+    IBMC_TRY(validate_props(props, n_props, o, ball_r2));
     if (o->cex_capacity > 0 && !cex_buf) return fail(IBMC_E_INVALID, "cex_buf is null with capacity > 0");
     if (o->near_tie_capacity > 0 && !tie_buf) return fail(IBMC_E_INVALID, "near_tie_buf is null with capacity > 0");
     const bool resumable = o->resume_cursor != 0 || o->chunk_budget != 0;
     if (o->resume_cursor < 0 || o->chunk_budget < 0) return fail(IBMC_E_INVALID, "negative resume cursor or budget");
     if (resumable) {
+        if (any_ball) return fail(IBMC_E_UNIMPL, "resume / budget with the L2-ball domain");
         if (o->stop_at_first) return fail(IBMC_E_UNIMPL, "resume / budget with stop_at_first");
         for (int i = 0; i < n_props; ++i)
             if (props[i].net != props[0].net || props[i].net->act != IBMC_ACT_RELU_Q8)
@@ -585,7 +670,13 @@ ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props, int32_t 
         d.image = images_on_device ? props[i].image : ctx->images.as<uint8_t>() + img_off[i];
         d.m = props[i].n_deltas;
         d.n = props[i].net->dims[0];
-        for (int j = 0; j < d.m; ++j) d.deltas[j] = props[i].deltas[j];
+        if (ball_r2 && ball_r2[i] >= 0) {
+            d.ball = 1;
+            d.ball_rd = ball_rd(ball_r2[i]);
+            d.ball_r2 = (int32_t)ball_r2[i];
+        } else {
+            for (int j = 0; j < d.m; ++j) d.deltas[j] = props[i].deltas[j];
+        }
         B.slot_base[i] = B.n_slots;
         for (int k = props[i].k_min; k <= props[i].k_max; k += props[i].k_step) B.level_k[i].push_back(k);
         B.n_slots += (int)B.level_k[i].size();
@@ -593,7 +684,7 @@ ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props, int32_t 
     IBMC_TRY(ctx->props.upload(B.hprops.data(), B.hprops.size() * sizeof(PropDev), s));
 
     std::vector<std::vector<int>> done_levels(n_props);
-    std::vector<unsigned long long> cex_acc(B.n_slots, 0), ties_acc(B.n_slots, 0);
+    std::vector<unsigned long long> cex_acc(B.n_slots, 0), ties_acc(B.n_slots, 0), pts_acc(B.n_slots, 0);
     std::vector<CexRec> all_recs, all_ties;
     int64_t rec_total = 0, tie_total = 0;
     double ksec = 0.0;
@@ -616,7 +707,7 @@ ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props, int32_t 
             }
         }
         if (!any) break;
-        std::vector<unsigned long long> sc, stt;
+        std::vector<unsigned long long> sc, stt, spt;
         std::vector<CexRec> r, t;
         int64_t rt = 0, tt = 0;
         double ks = 0;
@@ -627,7 +718,7 @@ ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props, int32_t 
         oo.near_tie_capacity = std::max<int64_t>(0, o->near_tie_capacity - (int64_t)all_ties.size());
         // a single round writes the sorted records straight into the caller's buffers
         const bool direct = !o->stop_at_first;
-        st = run_levels(ctx, props, n_props, &oo, B, sel, images_on_device, sc, stt, r, t, rt, tt, ks, nl,
+        st = run_levels(ctx, props, n_props, &oo, B, sel, images_on_device, sc, stt, spt, r, t, rt, tt, ks, nl,
                         direct ? reinterpret_cast<CexRec *>(cex_buf) : nullptr,
                         direct ? reinterpret_cast<CexRec *>(tie_buf) : nullptr, o->records_on_device != 0,
                         o->resume_cursor, o->chunk_budget, &next_cursor);
@@ -644,6 +735,7 @@ ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props, int32_t 
                 const int slot = B.slot_base[i] + li;
                 cex_acc[slot] += sc[slot];
                 ties_acc[slot] += stt[slot];
+                pts_acc[slot] += spt[slot];
                 done_levels[i].push_back(li);
                 if (o->stop_at_first && sc[slot] > 0) stopped[i] = true;
             }
@@ -685,7 +777,10 @@ ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props, int32_t 
             const int li = lv[t], k = B.level_k[i][li], slot = B.slot_base[i] + li;
             const bool q8 = props[i].net->act == IBMC_ACT_RELU_Q8;
             S.level_k[t] = k;
-            int64_t pts = binom_small(props[i].net->dims[0], k) * ipow64(props[i].n_deltas, k);
+            // the L2 ball: the points of the level the kernel found inside it
+            const bool ball = B.hprops[i].ball != 0;
+            int64_t pts = ball ? (k == 0 ? 1 : (int64_t)pts_acc[slot])
+                               : binom_small(props[i].net->dims[0], k) * ipow64(props[i].n_deltas, k);
             S.points[t] = pts;
             S.cex[t] = (k == 0) ? 0 : (int64_t)cex_acc[slot];
             S.ties[t] = (k == 0) ? (q8 ? B.hprops[i].tie0 : 0) : (int64_t)ties_acc[slot];
@@ -752,6 +847,43 @@ extern "C" ibmc_status ibmc_check_property(ibmc_ctx *ctx, const ibmc_mlp *net, c
     p.k_max = opts->k_max;
     p.k_step = opts->k_step;
     return check_batch_impl(ctx, &p, 1, opts, out, cex_buf, near_tie_buf, false);
+}
+
+extern "C" int32_t ibmc_ball_digits(int64_t radius_sq) { return radius_sq < 0 ? 0 : ball_rd(radius_sq); }
+
+extern "C" ibmc_status ibmc_check_ball(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *image, int32_t n_pixels,
+                                       int64_t radius_sq, const ibmc_check_opts *opts, ibmc_check_summary *out,
+                                       ibmc_cex *cex_buf) {
+    clear_error();
+    if (!net || !opts) return fail(IBMC_E_INVALID, "null net / opts");
+    if (n_pixels != net->dims[0]) return fail(IBMC_E_INVALID, "n_pixels %d != network input %d", n_pixels, net->dims[0]);
+    if (radius_sq < 0) return fail(IBMC_E_INVALID, "negative radius_sq");
+    ibmc_property p{};
+    p.net = net;
+    p.image = image;
+    p.k_min = opts->k_min;
+    p.k_max = opts->k_max;
+    p.k_step = opts->k_step;
+    return check_batch_impl(ctx, &p, 1, opts, out, cex_buf, nullptr, false, &radius_sq);
+}
+
+extern "C" ibmc_status ibmc_check_ball_batch(ibmc_ctx *ctx, const ibmc_ball_property *props, int32_t n_props,
+                                             const ibmc_check_opts *opts, ibmc_check_summary *outs, ibmc_cex *cex_buf) {
+    clear_error();
+    if (!props || n_props < 1) return fail(IBMC_E_INVALID, "no properties");
+    std::vector<ibmc_property> pv(n_props);
+    std::vector<int64_t> r2(n_props);
+    for (int i = 0; i < n_props; ++i) {
+        if (props[i].radius_sq < 0) return fail(IBMC_E_INVALID, "property %d: negative radius_sq", i);
+        pv[i] = ibmc_property{};
+        pv[i].net = props[i].net;
+        pv[i].image = props[i].image;
+        pv[i].k_min = props[i].k_min;
+        pv[i].k_max = props[i].k_max;
+        pv[i].k_step = props[i].k_step;
+        r2[i] = props[i].radius_sq;
+    }
+    return check_batch_impl(ctx, pv.data(), n_props, opts, outs, cex_buf, nullptr, false, r2.data());
 }
 
 extern "C" ibmc_status ibmc_eval_points_f32(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *image,
@@ -824,6 +956,11 @@ extern "C" ibmc_status ibmc_set_variant(ibmc_ctx *ctx, const ibmc_mlp *net, cons
     if (!ctx || !net) return fail(IBMC_E_INVALID, "null argument");
     ibmc_mlp *m = const_cast<ibmc_mlp *>(net);
     if (!variant) { m->forced_variant.clear(); return IBMC_OK; }
+    if (std::string(variant) == kLaneVariantName) {
+        if (!net->lane.ok) return fail(IBMC_E_INVALID, "variant %s does not match the network", variant);
+        m->forced_variant = variant;
+        return IBMC_OK;
+    }
     int nv = 0;
     const EnumVariant *vs = enum_variants(&nv);
     for (int i = 0; i < nv; ++i)
@@ -1193,6 +1330,24 @@ extern "C" ibmc_status ibmc_autotune(ibmc_ctx *ctx, const ibmc_mlp *net, int32_t
     o.k_max = k;
     o.k_step = 1;
     o.cex_capacity = 0;
+    // one candidate: the best of three timed checks with it forced
+    auto time_candidate = [&](const char *name, int occ) -> ibmc_status {
+        m->forced_variant = name;
+        ibmc_check_summary S;
+        double tmin = 1e30;
+        for (int rep = 0; rep < 3; ++rep) {
+            ibmc_status rc = ibmc_check_property(ctx, net, img.data(), n, D.data(), n_deltas, &o, &S, nullptr, nullptr);
+            if (rc < 0 && rc != IBMC_W_TRUNCATED) return rc;
+            tmin = std::min(tmin, ctx->last_kernel_seconds);
+        }
+        const double pps = tmin > 0 ? (double)S.points_total / tmin : 0.0;
+        if (!first) json += ", ";
+        first = false;
+        json += "{\"name\": \"" + std::string(name) + "\", \"kernel_s\": " + std::to_string(tmin) +
+                ", \"points_per_s\": " + std::to_string(pps) + ", \"occupancy\": " + std::to_string(occ) + "}";
+        if (tmin < best_t) { best_t = tmin; best = name; }
+        return IBMC_OK;
+    };
     for (int i = 0; i < nv; ++i) {
         const EnumVariant &v = vs[i];
         if (!variant_matches(v, net)) continue;
@@ -1200,20 +1355,12 @@ extern "C" ibmc_status ibmc_autotune(ibmc_ctx *ctx, const ibmc_mlp *net, int32_t
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, v.fn, 256, (size_t)enum_lds_bytes(v, net->qd)) !=
                 hipSuccess || occ < 1)
             continue;
-        m->forced_variant = v.name;
-        ibmc_check_summary S;
-        double tmin = 1e30;
-        for (int rep = 0; rep < 3; ++rep) {
-            ibmc_status rc = ibmc_check_property(ctx, net, img.data(), n, D.data(), n_deltas, &o, &S, nullptr, nullptr);
-            if (rc < 0 && rc != IBMC_W_TRUNCATED) { m->forced_variant = saved; return rc; }
-            tmin = std::min(tmin, ctx->last_kernel_seconds);
-        }
-        const double pps = tmin > 0 ? (double)S.points_total / tmin : 0.0;
-        if (!first) json += ", ";
-        first = false;
-        json += "{\"name\": \"" + std::string(v.name) + "\", \"kernel_s\": " + std::to_string(tmin) +
-                ", \"points_per_s\": " + std::to_string(pps) + ", \"occupancy\": " + std::to_string(occ) + "}";
-        if (tmin < best_t) { best_t = tmin; best = v.name; }
+        const ibmc_status rc = time_candidate(v.name, occ);
+        if (rc < 0) { m->forced_variant = saved; return rc; }
+    }
+    if (net->lane.ok) {
+        const ibmc_status rc = time_candidate(kLaneVariantName, lane_enum_grid(net->lane, ctx->n_cu) / ctx->n_cu);
+        if (rc < 0) { m->forced_variant = saved; return rc; }
     }
     m->forced_variant = saved;
     if (best.empty()) return fail(IBMC_E_UNIMPL, "no kernel instance for %s", shape_key(net).c_str());

@@ -15,6 +15,7 @@
 #include "kernels_cov.h"
 #include "kernels_prop.h"
 #include "kernels_sort.h"
+#include "kernels_lane.h"
 
 namespace ibmc {
 
@@ -123,6 +124,7 @@ struct ibmc_mlp {
     ibmc::QNetDev qd;
     ibmc::FwdExtra fx;
     ibmc::FNetDev fd;
+    ibmc::LaneNetDev lane{};           // integer nets the lane kernels serve (lane.ok)
     std::string forced_variant;
     ~ibmc_mlp();
 };
@@ -131,8 +133,12 @@ namespace ibmc {
 std::string shape_key(const ibmc_mlp *m);
 PropParams prop_views(const ibmc_proposer *p);
 const EnumVariant *pick_variant(ibmc_ctx *ctx, const ibmc_mlp *net);
+bool use_lane(ibmc_ctx *ctx, const ibmc_mlp *net, bool allowed);
+// ball_r2 (nullable): per property the squared radius of the L2-ball domain,
+// or -1 for its delta set.
 ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props, int32_t n_props, const ibmc_check_opts *o,
-                             ibmc_check_summary *outs, ibmc_cex *cex_buf, ibmc_cex *tie_buf, bool images_on_device);
+                             ibmc_check_summary *outs, ibmc_cex *cex_buf, ibmc_cex *tie_buf, bool images_on_device,
+                             const int64_t *ball_r2 = nullptr);
 // Looks up, once per device and with that device current, the address of
 // the allocation-free entry point's fixed scratch array.
 ibmc_status noalloc_setup(int device);

@@ -197,6 +197,73 @@ ibmc_mlp::~ibmc_mlp() {
 
 extern "C" void ibmc_free_mlp(ibmc_mlp *net) { delete net; }
 
+// Compact layouts of the lane-per-point kernels (see LaneNetDev), for the
+// networks they serve.
+static ibmc_status build_lane(ibmc_mlp *m, hipStream_t s) {
+    LaneNetDev &ln = m->lane;
+    memset(&ln, 0, sizeof(ln));
+    const int L = m->L;
+    if (!lane_eligible(m->dims.data(), L)) return IBMC_OK;
+    const int n = m->dims[0], h1 = m->dims[1], h2 = (L == 3) ? m->dims[2] : 0, nc = m->dims[L];
+    ln.L = L;
+    ln.n = n;
+    ln.nc = nc;
+    ln.LH1 = lane_width(h1);
+    ln.LH2 = (L == 3) ? lane_width(h2) : 0;
+    ln.s1 = m->shift[0];
+    ln.s2 = (L == 3) ? m->shift[1] : 0;
+    const int H1 = ln.LH1, H2 = ln.LH2, HL = (L == 3) ? H2 : H1, hl = (L == 3) ? h2 : h1;
+    std::vector<int8_t> w1c((size_t)n * H1, 0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < h1; ++j) w1c[(size_t)i * H1 + j] = m->Wq[0][(size_t)j * n + i];
+    std::vector<int32_t> q1(H1, -1);
+    for (int qpos = 0; qpos < m->qd.H[1]; ++qpos) {
+        const int unit = sigma64(qpos);
+        if (unit < h1) q1[unit] = qpos;
+    }
+    // [NO / 8][NI / 4][8] words of four int8 weights of inputs 4w..4w+3
+    auto words = [](const std::vector<int8_t> &W, int nout, int nin, int NO, int NI) {
+        std::vector<int32_t> out((size_t)NO * NI / 4, 0);
+        for (int st = 0; st < NO / 8; ++st)
+            for (int w = 0; w < NI / 4; ++w)
+                for (int t = 0; t < 8; ++t) {
+                    const int o = st * 8 + t;
+                    uint32_t v = 0;
+                    for (int z = 0; z < 4; ++z) {
+                        const int i = 4 * w + z;
+                        const int8_t x = (o < nout && i < nin) ? W[(size_t)o * nin + i] : 0;
+                        v |= (uint32_t)(uint8_t)x << (8 * z);
+                    }
+                    out[((size_t)st * (NI / 4) + w) * 8 + t] = (int32_t)v;
+                }
+        return out;
+    };
+    auto padded = [](const std::vector<int32_t> &b, int nout, int NO) {
+        std::vector<int32_t> out(NO, 0);
+        for (int j = 0; j < nout; ++j) out[j] = b[j];
+        return out;
+    };
+    IBMC_TRY(m->buf.emplace_back().upload(w1c.data(), w1c.size(), s));
+    ln.W1C = (const int8_t *)m->buf.back().p;
+    IBMC_TRY(m->buf.emplace_back().upload(q1.data(), q1.size() * 4, s));
+    ln.q1 = (const int32_t *)m->buf.back().p;
+    if (L == 3) {
+        const std::vector<int32_t> w2 = words(m->Wq[1], h2, h1, H2, H1), b2 = padded(m->bq[1], h2, H2);
+        IBMC_TRY(m->buf.emplace_back().upload(w2.data(), w2.size() * 4, s));
+        ln.W2S = (const int32_t *)m->buf.back().p;
+        IBMC_TRY(m->buf.emplace_back().upload(b2.data(), b2.size() * 4, s));
+        ln.b2 = (const int32_t *)m->buf.back().p;
+    }
+    const std::vector<int32_t> wo = words(m->Wq[L - 1], nc, hl, 16, HL), bo = padded(m->bq[L - 1], nc, 16);
+    IBMC_TRY(m->buf.emplace_back().upload(wo.data(), wo.size() * 4, s));
+    ln.WOS = (const int32_t *)m->buf.back().p;
+    IBMC_TRY(m->buf.emplace_back().upload(bo.data(), bo.size() * 4, s));
+    ln.bo = (const int32_t *)m->buf.back().p;
+    HIP_OK(hipStreamSynchronize(s));   // the staging vectors go out of scope
+    ln.ok = 1;
+    return IBMC_OK;
+}
+
 static ibmc_status build_q8(ibmc_ctx *ctx, ibmc_mlp *m) {
     const int L = m->L;
     QNetDev &q = m->qd;
@@ -404,6 +471,7 @@ static ibmc_status build_q8(ibmc_ctx *ctx, ibmc_mlp *m) {
         IBMC_TRY(m->buf.emplace_back().upload(m->bq[l - 1].data(), m->bq[l - 1].size() * 4, s));
         q.bd[l] = (const int32_t *)m->buf.back().p;
     }
+    IBMC_TRY(build_lane(m, s));
     HIP_OK(hipStreamSynchronize(s));
     return IBMC_OK;
 }

@@ -119,7 +119,32 @@ struct PropDev {
     int32_t n;             // pixels
     int32_t tie0;          // clean image has an exact top-2 tie (written by the clean pass)
     int32_t clean_done;    // first-layer slices of the integer clean pass finished; 0 when uploaded
+    int32_t ball;          // 1: the L2-ball domain (deltas unused), 0: the delta set
+    int32_t ball_rd;       // ball: offsets -rd..-1, 1..rd as digits 0..2 rd - 1 (m = 2 rd)
+    int32_t ball_r2;       // ball: squared radius
     int16_t deltas[kMaxDeltas];
+};
+
+// Offset of digit i in the L2-ball domain's encoding.
+__host__ __device__ inline int ball_offset(int i, int rd) { return i < rd ? i - rd : i - rd + 1; }
+
+// Integer network in the compact layouts of the lane-per-point kernels (one
+// or two hidden layers of at most 64 units, at most 16 classes): widths
+// padded to the instance widths LH1 in {16, 32, 64} and LH2 in {0 (one
+// hidden layer), 16, 32, 64}; 16 classes.  Padding units have zero weights
+// and biases (activation 0), padding classes are never read.
+struct LaneNetDev {
+    int ok;                            // the network has these layouts
+    int L, n, nc;
+    int LH1, LH2;
+    int s1, s2;                        // shifts of the hidden layers
+    const int8_t *W1C;                 // [n][LH1] first-layer columns, natural unit order
+    const int32_t *q1;                 // [LH1] position of unit j in the clean pass's (sigma) order, -1: padding
+    const int32_t *W2S;                // L == 3: [LH2 / 8][LH1 / 4][8] words of 4 int8 weights (inputs
+                                       // 4w..4w+3 of unit 8s + t)
+    const int32_t *b2;                 // L == 3: [LH2]
+    const int32_t *WOS;                // [2][LHL / 4][8] output words, LHL the last hidden width
+    const int32_t *bo;                 // [16]
 };
 
 // Ordering of the last perturbed element inside a segment.

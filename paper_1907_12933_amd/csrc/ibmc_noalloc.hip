@@ -51,7 +51,9 @@ static ibmc_status scratch_need(ibmc_ctx *ctx, const ibmc_mlp *net, int32_t n_de
     const int64_t cap = o->cex_capacity, tcap = o->near_tie_capacity;
     int64_t rec_slots = cap;
     int64_t h1 = 64;
-    if (net->act == IBMC_ACT_RELU_Q8) {
+    if (net->act == IBMC_ACT_RELU_Q8 && use_lane(ctx, net, o->resume_cursor == 0 && o->chunk_budget == 0)) {
+        h1 = std::max<int64_t>(h1, net->qd.H[1]);    // the lane kernel writes records without spare blocks
+    } else if (net->act == IBMC_ACT_RELU_Q8) {
         const EnumVariant *v = pick_variant(ctx, net);
         if (!v) return fail(IBMC_E_UNIMPL, "no enumeration kernel for network %s", shape_key(net).c_str());
         int occ = 0;
@@ -65,7 +67,7 @@ static ibmc_status scratch_need(ibmc_ctx *ctx, const ibmc_mlp *net, int32_t n_de
     size_t b = 0;
     b += al256((size_t)((n + 15) / 16 * 16));                       // image
     b += al256(sizeof(PropDev));                                     // property
-    b += al256((size_t)(8 + 1 + 2 * levels + kQueueStride + kF32Queues * kQueueStride) * 8);  // counters, queues
+    b += al256((size_t)(8 + 1 + 3 * levels + kQueueStride + kF32Queues * kQueueStride) * 8);  // counters, queues
     b += al256((size_t)std::max<int64_t>(tcap, 1) * sizeof(DevRec)); // near-tie slots
     b += al256((size_t)h1 * 4) + 2 * al256(4);                       // u0, u0 index, property ids
     b += al256((size_t)std::max(levels, 1) * n * 8);                 // prefix tables

@@ -77,6 +77,11 @@ class ibmc_property(C.Structure):
                 ("n_deltas", C.c_int32), ("k_min", C.c_int32), ("k_max", C.c_int32), ("k_step", C.c_int32)]
 
 
+class ibmc_ball_property(C.Structure):
+    _fields_ = [("net", C.c_void_p), ("image", C.c_void_p), ("radius_sq", C.c_int64), ("k_min", C.c_int32),
+                ("k_max", C.c_int32), ("k_step", C.c_int32), ("reserved", C.c_int32)]
+
+
 class ibmc_cov_params(C.Structure):
     _fields_ = [("dist_sq_min", C.c_int64), ("ratio_num", C.c_int32), ("ratio_den", C.c_int32), ("P", C.c_double)]
 
@@ -140,6 +145,9 @@ SIGNATURES = {
     "ibmc_proposer_score_dev": (I32, [VP, VP, VP, VP, I32, I32, P_I16, I32, VP]),
     "ibmc_label_candidates": (I32, [VP, I32, I32, P_CEX, I64, P_F32]),
     "ibmc_count_candidates": (I32, [VP, I32, I32, P_CEX, I64, P_F32]),
+    "ibmc_ball_digits": (I32, [I64]),
+    "ibmc_check_ball": (I32, [VP, VP, P_U8, I32, I64, P_OPTS, P_SUM, P_CEX]),
+    "ibmc_check_ball_batch": (I32, [VP, C.POINTER(ibmc_ball_property), I32, P_OPTS, P_SUM, P_CEX]),
     "ibmc_check_property_ranked": (I32, [VP, VP, VP, P_U8, I32, I32, I32, P_I16, I32, P_OPTS, P_SUM, P_CEX]),
     "ibmc_autotune": (I32, [VP, VP, I32, I32, C.c_char_p, I64]),
     "ibmc_set_variant": (I32, [VP, VP, C.c_char_p]),
@@ -411,6 +419,52 @@ def ibmc_check_batch(ctx, props, stop_at_first=False, cex_capacity=1 << 20, near
     if records_on_device:
         return sums, cex_buf[:tot * rsz], tie_dev[:ttot * rsz], rc
     return sums, cex_buf[:tot], ties[:ttot].copy(), rc
+
+
+def ibmc_ball_digits(radius_sq):
+    """Digits per pixel side of the L2-ball encoding (n_deltas = 2 * this)."""
+    return int(lib().ibmc_ball_digits(int(radius_sq)))
+
+
+def ball_deltas(radius_sq):
+    """The implicit delta set of the L2-ball encoding: -rd..-1, 1..rd."""
+    rd = ibmc_ball_digits(radius_sq)
+    return np.array(list(range(-rd, 0)) + list(range(1, rd + 1)), np.int16)
+
+
+def ibmc_check_ball(ctx, net, image, radius_sq, k_min=1, k_max=2, k_step=1, stop_at_first=False,
+                    cex_capacity=1 << 20):
+    """Check the images within squared L2 distance radius_sq of image, level k
+    = support size.  Returns (summary dict, cex records)."""
+    image = np.ascontiguousarray(image, np.uint8)
+    cex = np.empty(max(cex_capacity, 1), CEX_DTYPE)
+    o = _opts(k_min, k_max, k_step, stop_at_first, cex_capacity, 0, 0.0)
+    s = ibmc_check_summary()
+    rc = _ck(lib().ibmc_check_ball(ctx.handle, net.handle, _ptr(image, P_U8), image.size, int(radius_sq),
+                                   C.byref(o), C.byref(s), cex.ctypes.data_as(P_CEX)))
+    sd = summary_dict(s)
+    sd["status"] = rc
+    return sd, cex[:min(sd["cex_total"], cex_capacity)].copy()
+
+
+def ibmc_check_ball_batch(ctx, props, stop_at_first=False, cex_capacity=1 << 20):
+    """props: list of (net, image, radius_sq, k_min, k_max[, k_step]).  Returns
+    (list of summary dicts, cex records tagged with their property)."""
+    n = len(props)
+    arr = (ibmc_ball_property * n)()
+    keep = []
+    for i, pr in enumerate(props):
+        net, img, r2, kmin, kmax = pr[:5]
+        img = np.ascontiguousarray(img, np.uint8)
+        keep.append(img)
+        arr[i] = ibmc_ball_property(net.handle, img.ctypes.data, int(r2), kmin, kmax, pr[5] if len(pr) > 5 else 1, 0)
+    outs = (ibmc_check_summary * n)()
+    cex = np.empty(max(cex_capacity, 1), CEX_DTYPE)
+    o = _opts(0, 0, 1, stop_at_first, cex_capacity, 0, 0.0)
+    _ck(lib().ibmc_check_ball_batch(ctx.handle, arr, n, C.byref(o), outs, cex.ctypes.data_as(P_CEX)))
+    sums = summary_dicts(outs, n)
+    del keep
+    return sums, cex[:min(sum(s["cex_total"] for s in sums), cex_capacity)].copy()
 
 
 def ibmc_check_batch_dev(ctx, props, **kw):

@@ -39,7 +39,7 @@ def test_struct_sizes_match_header_layout(tmp_path):
     import subprocess
     probe = tmp_path / "probe.c"
     structs = ["ibmc_mlp_desc", "ibmc_check_opts", "ibmc_cex", "ibmc_check_summary", "ibmc_property",
-               "ibmc_cov_params", "ibmc_cov_summary", "ibmc_train_opts"]
+               "ibmc_ball_property", "ibmc_cov_params", "ibmc_cov_summary", "ibmc_train_opts"]
     body = "\n".join(f'printf("{s} %zu\\n", sizeof({s}));' for s in structs)
     body += '\nprintf("off_points %zu\\n", offsetof(ibmc_check_summary, points));'
     body += '\nprintf("off_seconds %zu\\n", offsetof(ibmc_check_summary, seconds));'
