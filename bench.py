@@ -24,6 +24,7 @@ MI355X_HBM_PEAK_GBS = 8000.0
 MI355X_SPEC_CLOCK_GHZ = 2.4
 HERE = os.path.dirname(os.path.abspath(__file__))
 # enumeration kernel sources whose hash keys the profile record
+TUNE_TABLE = os.path.join(HERE, "paper_1907_12933_amd", "tune_gfx950.json")
 KERNEL_SOURCES = ["paper_1907_12933_amd/csrc/enum_q8_impl.h", "paper_1907_12933_amd/csrc/enum_common.h",
                   "paper_1907_12933_amd/csrc/ibmc_internal.h"]
 
@@ -231,8 +232,11 @@ def batch_leg(ctx, ibmc, inputs):
     fdev = fs[0]["seconds"]
     fpts = sum(s["points_total"] for s in fs)
     fflops = sum(float(s["points_total"]) * f32_flops(fn[p.net_index].dims) for s, p in zip(fs, fp))
+    launches, replays = ibmc.ibmc_graph_stats(ctx)
     return dict(properties=len(props), networks=len(nets), points=pts, seconds=round(t, 4),
                 device_seconds=round(dev, 4), points_per_s=pts / t,
+                kernels={"_".join(map(str, n.dims)): ibmc.ibmc_chosen_variant(ctx, m) for n, m in zip(nets, ms)},
+                graph_launches=launches, graph_replays=replays,
                 counterexamples=int(sum(s["cex_total"] for s in sums)),
                 int8_roofline=dict(bound="mfma", achieved=round(ops / dev / 1e12, 2), peak=MI355X_INT8_PEAK_TOPS,
                                    unit="TOP/s", frac=round(ops / dev / 1e12 / MI355X_INT8_PEAK_TOPS, 4),
@@ -267,6 +271,36 @@ def glyph_leg(ctx, ibmc, inputs):
                 counterexamples=int(sum(s["cex_total"] for s in sums)))
 
 
+def ball_leg(ctx, ibmc, inputs):
+    """The paper's own domain (Sec. III-C, Eq. (9)): every image within L2
+    distance gamma * 255 of each of the ten 7x5 glyphs of the 35-16-5 net,
+    levels k = 1, 2 by support size, for the two smallest proximities of
+    Table III (gamma = 0.3 and 0.5), as one batch per radius."""
+    g = inputs.workload_glyph35()
+    m = ibmc.Mlp(ctx, g.net)
+    out = {}
+    for gamma in (0.3, 0.5):
+        r2 = int((gamma * 255) ** 2)
+        P = [(m, x, r2, 1, 2) for x in g.images]
+        ibmc.ibmc_check_ball_batch(ctx, P, cex_capacity=1 << 22)
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            sums, cex = ibmc.ibmc_check_ball_batch(ctx, P, cex_capacity=1 << 22)
+            ts.append(time.perf_counter() - t0)
+        t = float(np.median(ts))
+        pts = sum(s["points_total"] for s in sums)
+        m_d = 2 * ibmc.ibmc_ball_digits(r2)
+        enumerated = len(P) * (35 * m_d + 595 * m_d * m_d)
+        out[f"gamma_{gamma}"] = dict(radius_sq=r2, points_in_ball=int(pts), digit_points_enumerated=int(enumerated),
+                                     seconds=round(t, 6), points_per_s=pts / t,
+                                     us_per_image=round(t / len(P) * 1e6, 2),
+                                     counterexamples=int(sum(s["cex_total"] for s in sums)),
+                                     unsafe_images=int(sum(1 for s in sums if s["cex_total"] > 0)))
+    out["workload"] = "glyph35 net 35-16-5, 10 glyphs, images within gamma * 255 (L2), k = 1..2"
+    return out
+
+
 def per_image(ibmc, ctx, net, w, sums):
     pots, labels = ibmc.ibmc_forward(ctx, net, w.images)
     z = np.sort(pots[:, -w.net.dims[-1]:].astype(np.int64), axis=1)
@@ -293,6 +327,10 @@ def main():
 
     w = inputs.workload_blob784(count=args.images)
     ctx = ibmc.Context(0, torch.cuda.current_stream())
+    # the tuning table of this GPU (kernel choice per network shape), when shipped
+    tuned = 0
+    if os.path.exists(TUNE_TABLE):
+        tuned = ibmc.ibmc_tune_load(ctx, TUNE_TABLE)
     net = ibmc.Mlp(ctx, w.net)
     if args.variant:
         ibmc.ibmc_set_variant(ctx, net, args.variant)
@@ -360,6 +398,7 @@ def main():
                                f"images, k=1..2 pixels, deltas +-8/+-16/+-32, all counterexamples returned",
                    "points_per_step": points, "images": args.images},
         "roofline": roof,
+        "kernel": ibmc.ibmc_chosen_variant(ctx, net), "tuning_table_entries": tuned,
         "counterexamples_per_step": n_cex, "unsafe_images": unsafe,
         # per image: counterexamples and the clean top-2 logit margin
         "per_image": per_image(ibmc, ctx, net, w, sums),
@@ -367,6 +406,8 @@ def main():
     if not args.no_extras:
         log("[bench] glyph leg")
         out["glyph35"] = glyph_leg(ctx, ibmc, inputs)
+        log("[bench] L2-ball leg")
+        out["ball"] = ball_leg(ctx, ibmc, inputs)
         log("[bench] proposer leg")
         out["ttfc"] = proposer_leg(ctx, ibmc, inputs, w, net, cex, args)
         log("[bench] coverage leg")

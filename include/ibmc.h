@@ -216,6 +216,8 @@ ibmc_status ibmc_device_info(ibmc_ctx *ctx, int32_t *n_cu, int32_t *arch_major, 
  * Errors: IBMC_E_INVALID (shape), IBMC_E_RANGE (int32 headroom),
  * IBMC_E_UNIMPL (wider than the kernels accept). */
 ibmc_status ibmc_load_mlp(ibmc_ctx *ctx, const ibmc_mlp_desc *desc, ibmc_mlp **out);
+/* Frees the network's device memory; allowed before or after its context
+ * is destroyed (it is only used with that context). */
 void ibmc_free_mlp(ibmc_mlp *net);
 
 /* ---- the check (Sec. II-B bound loop around the Sec. III-C property) ---- */
@@ -464,12 +466,31 @@ ibmc_status ibmc_check_property_ranked(ibmc_ctx *ctx, const ibmc_mlp *net,
 
 /* ---- tuning ------------------------------------------------------------ */
 
-/* Time the kernel variants (points per wave, waves per workgroup, weights
- * staged in LDS or read through L2) for a network on a synthetic image and
- * remember the fastest for that network shape in the context.  json_out
- * (nullable, json_cap bytes) receives the measurements as JSON. */
+/* Time the kernel variants of an integer network (matrix-core instances:
+ * points per wave, weights staged in LDS or read through L2; the
+ * lane-per-point kernel where the shape allows it) on a synthetic image,
+ * delta set of n_deltas and level k, and remember the fastest for that
+ * network shape in the context (every later check of the shape, single or
+ * batched, launches it).  json_out (nullable, json_cap bytes) receives the
+ * measurements as JSON. */
 ibmc_status ibmc_autotune(ibmc_ctx *ctx, const ibmc_mlp *net, int32_t k, int32_t n_deltas,
                           char *json_out, int64_t json_cap);
+/* The context's tuning table (shape key -> variant name, as a flat JSON
+ * object): save it to a file, or merge a saved one into the context
+ * (n_loaded: entries read).  IBMC_E_INVALID when the file cannot be
+ * written / read or is malformed. */
+ibmc_status ibmc_tune_save(ibmc_ctx *ctx, const char *path);
+ibmc_status ibmc_tune_load(ibmc_ctx *ctx, const char *path, int32_t *n_loaded);
+/* Name of the enumeration kernel a (non-resumable) check of the network
+ * launches now: a forced variant, else the tuned one for its shape, else the
+ * built-in choice ("f32" for float networks); written NUL-terminated into
+ * out (cap bytes). */
+ibmc_status ibmc_chosen_variant(ibmc_ctx *ctx, const ibmc_mlp *net, char *out, int64_t cap);
+/* Batches over several networks run as one HIP graph; a batch whose
+ * launches match the previous one's (same plans, buffers and counter
+ * layout) replays its instantiated graph.  Graph launches and replays so
+ * far in the context. */
+ibmc_status ibmc_graph_stats(ibmc_ctx *ctx, int64_t *launches, int64_t *reuses);
 /* Force a variant by its name (as listed by the tuner's JSON); NULL resets
  * to the built-in choice. */
 ibmc_status ibmc_set_variant(ibmc_ctx *ctx, const ibmc_mlp *net, const char *variant);

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <chrono>
 #include <cstring>
@@ -85,9 +86,12 @@ const EnumVariant *pick_variant(ibmc_ctx *ctx, const ibmc_mlp *net) {
     return best;
 }
 
-// Integer networks the lane kernels serve run there unless a matrix-core
-// variant is forced or tuned for the shape (and always for resumable calls,
-// which only the matrix-core kernel implements, where allowed is false).
+// The lane kernel serves an integer network when forced or tuned for its
+// shape; untuned, it takes the networks with one hidden layer (where 16x16
+// matrix-core tiles are mostly padding), while two hidden layers go to the
+// matrix cores (their second layer is a dense product the dot4 path pays
+// h1 h2 / 4 instructions per point for).  Never for resumable calls, which
+// only the matrix-core kernel implements (allowed false).
 bool use_lane(ibmc_ctx *ctx, const ibmc_mlp *net, bool allowed) {
     if (!allowed || !net->lane.ok) return false;
     std::string want = net->forced_variant;
@@ -95,7 +99,8 @@ bool use_lane(ibmc_ctx *ctx, const ibmc_mlp *net, bool allowed) {
         auto it = ctx->tuned.find(shape_key(net));
         if (it != ctx->tuned.end()) want = it->second;
     }
-    return want.empty() || want == kLaneVariantName;
+    if (!want.empty()) return want == kLaneVariantName;
+    return net->L == 2;
 }
 
 struct Level {
@@ -518,6 +523,47 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
         if (!ctx->fork_ev) HIP_OK(hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
         hipStream_t cs = ctx->side[0];  // capture origin: a private stream, never the caller's
         HIP_OK(hipStreamWaitEvent(cs, ctx->ek0, 0));
+        // Every value the captured launches read: the plans, the buffers
+        // (addresses only: their contents are uploaded before each launch)
+        // and the counter layout.  A batch with the same signature replays
+        // the graph instantiated for the previous one.
+        std::string sig;
+        auto put = [&sig](const void *p, size_t n) { sig.append(reinterpret_cast<const char *>(p), n); };
+        for (const NetPlan &pl : plans) {
+            const size_t nid = pl.ids.size();
+            put(&pl.net, sizeof(pl.net));
+            put(&pl.lane, sizeof(pl.lane));
+            put(&pl.v, sizeof(pl.v));
+            put(&pl.total, sizeof(pl.total));
+            put(&pl.limit, sizeof(pl.limit));
+            put(&pl.batch, sizeof(pl.batch));
+            put(&pl.job_off, sizeof(pl.job_off));
+            put(&pl.n_jobs, sizeof(pl.n_jobs));
+            put(&pl.grid, sizeof(pl.grid));
+            put(&pl.packed, sizeof(pl.packed));
+            put(&pl.vb_lo, sizeof(pl.vb_lo));
+            put(&pl.vb_hi, sizeof(pl.vb_hi));
+            put(&nid, sizeof(nid));
+        }
+        const void *bufs[] = {ctx->jobs.p, ctx->counters.p, ctx->recs.p, ctx->ties.p, ctx->u0.p, ctx->u0_index.p,
+                              ctx->prop_ids.p, ctx->props.p, ctx->qcum.p, ctx->flags_dev};
+        put(bufs, sizeof(bufs));
+        const int64_t scal[] = {n_ctr, rec_slots, tcap, max_h1, resume, sc0, st0, sp0, fq0, (int64_t)NN};
+        put(scal, sizeof(scal));
+        const float tie_rel = o->near_tie_rel;
+        put(&tie_rel, sizeof(tie_rel));
+        if (ctx->graph_exec && sig == ctx->graph_sig) {
+            const hipError_t le = hipGraphLaunch(ctx->graph_exec, cs);
+            if (le == hipSuccess) {
+                HIP_OK(hipEventRecord(ctx->side_ev[0], cs));
+                HIP_OK(hipStreamWaitEvent(s, ctx->side_ev[0], 0));
+            }
+            HIP_OK(hipStreamSynchronize(cs));
+            HIP_OK(le);
+            ctx->graph_launches++;
+            ctx->graph_reuses++;
+            goto graph_done;
+        }
         HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         ibmc_status cst = IBMC_OK;
         hipError_t ce = launch_fill_u64(ctr, n_ctr, 0ull, cs);
@@ -543,16 +589,24 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
         const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         HIP_OK(ie);
+        if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+        ctx->graph_exec = exec;
+        ctx->graph_sig.swap(sig);
         const hipError_t le = hipGraphLaunch(exec, cs);
         if (le == hipSuccess) {
             HIP_OK(hipEventRecord(ctx->side_ev[0], cs));
             HIP_OK(hipStreamWaitEvent(s, ctx->side_ev[0], 0));
         }
         HIP_OK(hipStreamSynchronize(cs));
-        (void)hipGraphExecDestroy(exec);
+        if (le != hipSuccess) {
+            (void)hipGraphExecDestroy(ctx->graph_exec);
+            ctx->graph_exec = nullptr;
+            ctx->graph_sig.clear();
+        }
         HIP_OK(le);
         ctx->graph_launches++;
     }
+graph_done:
     if (!time_enum) {
         HIP_OK(hipEventRecord(ctx->ek1, s));
         timed = true;
@@ -971,6 +1025,77 @@ extern "C" ibmc_status ibmc_set_variant(ibmc_ctx *ctx, const ibmc_mlp *net, cons
             return IBMC_OK;
         }
     return fail(IBMC_E_INVALID, "unknown variant %s", variant);
+}
+
+extern "C" ibmc_status ibmc_chosen_variant(ibmc_ctx *ctx, const ibmc_mlp *net, char *out, int64_t cap) {
+    clear_error();
+    if (!ctx || !net || !out || cap < 1) return fail(IBMC_E_INVALID, "null argument");
+    std::string name;
+    if (net->act != IBMC_ACT_RELU_Q8) {
+        name = "f32";
+    } else if (use_lane(ctx, net, true)) {
+        name = kLaneVariantName;
+    } else {
+        const EnumVariant *v = pick_variant(ctx, net);
+        if (!v) return fail(IBMC_E_UNIMPL, "no enumeration kernel for network %s", shape_key(net).c_str());
+        name = v->name;
+    }
+    const size_t n = std::min<size_t>(name.size(), (size_t)cap - 1);
+    memcpy(out, name.data(), n);
+    out[n] = 0;
+    return IBMC_OK;
+}
+
+extern "C" ibmc_status ibmc_graph_stats(ibmc_ctx *ctx, int64_t *launches, int64_t *reuses) {
+    clear_error();
+    if (!ctx) return fail(IBMC_E_INVALID, "ctx is null");
+    if (launches) *launches = ctx->graph_launches;
+    if (reuses) *reuses = ctx->graph_reuses;
+    return IBMC_OK;
+}
+
+// Tuning table: one "shape key": "variant name" pair per network shape, as
+// a flat JSON object.
+extern "C" ibmc_status ibmc_tune_save(ibmc_ctx *ctx, const char *path) {
+    clear_error();
+    if (!ctx || !path) return fail(IBMC_E_INVALID, "null ctx / path");
+    FILE *f = fopen(path, "w");
+    if (!f) return fail(IBMC_E_INVALID, "cannot write %s", path);
+    fprintf(f, "{");
+    bool first = true;
+    for (const auto &kv : ctx->tuned) {
+        fprintf(f, "%s\n  \"%s\": \"%s\"", first ? "" : ",", kv.first.c_str(), kv.second.c_str());
+        first = false;
+    }
+    fprintf(f, "\n}\n");
+    const bool ok = fclose(f) == 0;
+    return ok ? IBMC_OK : fail(IBMC_E_INVALID, "cannot write %s", path);
+}
+
+extern "C" ibmc_status ibmc_tune_load(ibmc_ctx *ctx, const char *path, int32_t *n_loaded) {
+    clear_error();
+    if (!ctx || !path) return fail(IBMC_E_INVALID, "null ctx / path");
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(IBMC_E_INVALID, "cannot read %s", path);
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+    fclose(f);
+    // the quoted strings in order: key, value, key, value, ...
+    std::vector<std::string> strs;
+    for (size_t i = 0; i < text.size(); ++i) {
+        if (text[i] != '"') continue;
+        const size_t j = text.find('"', i + 1);
+        if (j == std::string::npos) return fail(IBMC_E_INVALID, "%s: unterminated string", path);
+        strs.push_back(text.substr(i + 1, j - i - 1));
+        i = j;
+    }
+    if (strs.size() % 2) return fail(IBMC_E_INVALID, "%s: a key without a value", path);
+    int32_t n = 0;
+    for (size_t i = 0; i < strs.size(); i += 2, ++n) ctx->tuned[strs[i]] = strs[i + 1];
+    if (n_loaded) *n_loaded = n;
+    return IBMC_OK;
 }
 
 // ---------------------------------------------------------------------------

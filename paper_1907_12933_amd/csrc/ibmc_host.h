@@ -104,6 +104,11 @@ struct ibmc_ctx {
     std::vector<hipEvent_t> side_ev;
     hipEvent_t fork_ev = nullptr;
     int64_t graph_launches = 0;
+    // the instantiated graph of the last multi-network batch and the
+    // signature of every value its launches were captured with
+    hipGraphExec_t graph_exec = nullptr;
+    std::string graph_sig;
+    int64_t graph_reuses = 0;
     bool force_int32_layer1 = false;   // testing aid: take the general first-layer path
     double last_kernel_seconds = 0.0;
     int last_kernel_launches = 0;
@@ -112,6 +117,7 @@ struct ibmc_ctx {
 
 struct ibmc_mlp {
     ibmc_ctx *ctx = nullptr;
+    int device = -1;
     int act = 0;
     int L = 0;
     std::vector<int> dims;

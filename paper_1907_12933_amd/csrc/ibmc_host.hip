@@ -160,6 +160,8 @@ ibmc_ctx::~ibmc_ctx() {
     for (hipStream_t st : side) (void)hipStreamDestroy(st);
     for (hipEvent_t ev : side_ev) (void)hipEventDestroy(ev);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    (void)hipGetLastError();
 }
 
 extern "C" void ibmc_ctx_destroy(ibmc_ctx *ctx) { delete ctx; }
@@ -192,7 +194,10 @@ extern "C" ibmc_status ibmc_last_kernel_time(ibmc_ctx *ctx, double *seconds, int
 // ---------------------------------------------------------------------------
 
 ibmc_mlp::~ibmc_mlp() {
-    if (ctx) (void)hipSetDevice(ctx->device);
+    // the device is kept here, not read from the context, which may be gone
+    if (device >= 0) (void)hipSetDevice(device);
+    buf.clear();
+    (void)hipGetLastError();   // an ignored teardown error must not reach the next launch's check
 }
 
 extern "C" void ibmc_free_mlp(ibmc_mlp *net) { delete net; }
@@ -553,6 +558,7 @@ extern "C" ibmc_status ibmc_load_mlp(ibmc_ctx *ctx, const ibmc_mlp_desc *d, ibmc
     HIP_OK(hipSetDevice(ctx->device));
     std::unique_ptr<ibmc_mlp> m(new ibmc_mlp());
     m->ctx = ctx;
+    m->device = ctx->device;
     m->act = d->act;
     m->L = L;
     m->dims.assign(d->dims, d->dims + L + 1);

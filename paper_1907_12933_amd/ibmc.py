@@ -151,6 +151,10 @@ SIGNATURES = {
     "ibmc_check_property_ranked": (I32, [VP, VP, VP, P_U8, I32, I32, I32, P_I16, I32, P_OPTS, P_SUM, P_CEX]),
     "ibmc_autotune": (I32, [VP, VP, I32, I32, C.c_char_p, I64]),
     "ibmc_set_variant": (I32, [VP, VP, C.c_char_p]),
+    "ibmc_tune_save": (I32, [VP, C.c_char_p]),
+    "ibmc_tune_load": (I32, [VP, C.c_char_p, P_I32]),
+    "ibmc_graph_stats": (I32, [VP, P_I64, P_I64]),
+    "ibmc_chosen_variant": (I32, [VP, VP, C.c_char_p, I64]),
     "ibmc_last_kernel_time": (I32, [VP, C.POINTER(C.c_double), P_I32]),
 }
 
@@ -518,6 +522,28 @@ def ibmc_abort(ctx):
 
 def ibmc_set_variant(ctx, net, name):
     _ck(lib().ibmc_set_variant(ctx.handle, net.handle, name.encode() if name else None))
+
+
+def ibmc_tune_save(ctx, path):
+    _ck(lib().ibmc_tune_save(ctx.handle, str(path).encode()))
+
+
+def ibmc_tune_load(ctx, path):
+    n = I32()
+    _ck(lib().ibmc_tune_load(ctx.handle, str(path).encode(), C.byref(n)))
+    return n.value
+
+
+def ibmc_chosen_variant(ctx, net):
+    buf = C.create_string_buffer(256)
+    _ck(lib().ibmc_chosen_variant(ctx.handle, net.handle, buf, len(buf)))
+    return buf.value.decode()
+
+
+def ibmc_graph_stats(ctx):
+    a, b = I64(), I64()
+    _ck(lib().ibmc_graph_stats(ctx.handle, C.byref(a), C.byref(b)))
+    return a.value, b.value
 
 
 def ibmc_last_kernel_time(ctx):

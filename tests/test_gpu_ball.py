@@ -38,8 +38,9 @@ SHAPES = [
 
 @pytest.mark.parametrize("seed,dims,shift", SHAPES)
 def test_lane_kernel_delta_domain(ctx, orc, seed, dims, shift):
-    """The lane kernel (chosen by default for these shapes) and a forced
-    matrix-core variant return the oracle's records."""
+    """The default kernel for the shape (the lane kernel for one hidden
+    layer, the matrix cores for two) and the lane kernel forced both return
+    the oracle's records."""
     from paper_1907_12933_amd import ibmc
     g = I.rng(700 + seed)
     net = I.random_qnet(g, dims, shift=shift, wmax=40, bmax=300)

@@ -111,3 +111,50 @@ def test_records_on_device_match_host(ctx, small_batch):
         assert len(host) == len(c1) == min(cap, sum(s["cex_total"] for s in s1))
         if cap > 5:
             assert np.array_equal(host, c1)
+
+
+def test_tuning_table_drives_the_batch_and_the_graph_replays(ctx, orc, tmp_path):
+    """Tuned choices are saved, loaded into a fresh context and launched by
+    the batched check (the chosen kernel is the table's, including a table
+    that sends a two-layer network to the lane kernel); a repeated batch
+    replays its instantiated graph; every call returns the oracle's records."""
+    from paper_1907_12933_amd import ibmc
+    import json
+    g = I.rng(57)
+    n1 = I.random_qnet(g, [35, 16, 5], shift=4, wmax=40, bmax=300)
+    n2 = I.random_qnet(g, [30, 40, 30, 6], shift=[5, 4], wmax=40, bmax=300)
+    c1 = ibmc.Context(0)
+    m1, m2 = ibmc.Mlp(c1, n1), ibmc.Mlp(c1, n2)
+    best = {}
+    for m in (m1, m2):
+        rep = json.loads(ibmc.ibmc_autotune(c1, m, k=2, n_deltas=6))
+        best[rep["shape"]] = rep["best"]
+        assert ibmc.ibmc_chosen_variant(c1, m) == rep["best"]
+    path = tmp_path / "tune.json"
+    ibmc.ibmc_tune_save(c1, path)
+    del m1, m2
+    c1.close()
+    assert json.loads(path.read_text()) == best
+    D = np.array([-90, -30, 30, 90], np.int16)
+    xs = [g.integers(0, 255, size=35, endpoint=True).astype(np.uint8) for _ in range(2)]
+    ys = [g.integers(0, 255, size=30, endpoint=True).astype(np.uint8) for _ in range(2)]
+    refs = [orc.q8_check(n1, xs[0], D, 1, 2), orc.q8_check(n2, ys[0], D, 1, 2), orc.q8_check(n1, xs[1], D, 1, 2),
+            orc.q8_check(n2, ys[1], D, 1, 2)]
+    assert sum(r["cex_total"] > 0 for r in refs) >= 2
+    for table in (best, {k: ("lane" if k.startswith("q8_30_") else v) for k, v in best.items()}):
+        path.write_text(json.dumps(table))
+        c2 = ibmc.Context(0)
+        assert ibmc.ibmc_tune_load(c2, path) == 2
+        a1, a2 = ibmc.Mlp(c2, n1), ibmc.Mlp(c2, n2)
+        assert [ibmc.ibmc_chosen_variant(c2, a) for a in (a1, a2)] == list(table.values())
+        props = [(a1, xs[0], D, 1, 2), (a2, ys[0], D, 1, 2), (a1, xs[1], D, 1, 2), (a2, ys[1], D, 1, 2)]
+        l0, r0 = ibmc.ibmc_graph_stats(c2)
+        outs = [ibmc.ibmc_check_batch(c2, props, cex_capacity=1 << 20) for _ in range(3)]
+        l1, r1 = ibmc.ibmc_graph_stats(c2)
+        assert l1 - l0 == 3 and r1 - r0 == 2
+        for sums, cex, _, _ in outs:
+            for i, r in enumerate(refs):
+                c = cex[cex["prop"] == i]
+                assert list(sums[i]["cex"]) == [int(v) for v in r["cex"]]
+                assert np.array_equal(c["rank"], r["cex_rank"]) and np.array_equal(c["new_label"], r["cex_label"])
+        c2.close()

@@ -151,3 +151,20 @@ def test_k_step_two(ctx, orc, seed, dims, kmin, kmax):
     assert np.array_equal(cex["k"], r["cex_k"]) and np.array_equal(cex["rank"], r["cex_rank"])
     assert np.array_equal(cex["new_label"], r["cex_label"])
     assert r["cex_total"] > 0
+
+
+def test_network_outlives_its_context():
+    """A network freed after its context (the order a garbage collector may
+    pick) leaves no error behind for the next context's calls."""
+    from paper_1907_12933_amd import ibmc
+    g = I.rng(9)
+    net = I.random_qnet(g, [20, 16, 5], shift=5)
+    c = ibmc.Context(0)
+    m = ibmc.Mlp(c, net)
+    c.close()
+    m.close()
+    c2 = ibmc.Context(0)
+    m2 = ibmc.Mlp(c2, net)
+    x = g.integers(0, 255, size=20, endpoint=True).astype(np.uint8)
+    s, _, _ = ibmc.ibmc_check_property(c2, m2, x, np.array([-40, 40], np.int16), 1, 2)
+    assert s["points_total"] == 20 * 2 + 190 * 4
