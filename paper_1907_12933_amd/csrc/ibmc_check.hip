@@ -87,10 +87,11 @@ const EnumVariant *pick_variant(ibmc_ctx *ctx, const ibmc_mlp *net) {
 }
 
 // The lane kernel serves an integer network when forced or tuned for its
-// shape; untuned, it takes the networks with one hidden layer (where 16x16
-// matrix-core tiles are mostly padding), while two hidden layers go to the
-// matrix cores (their second layer is a dense product the dot4 path pays
-// h1 h2 / 4 instructions per point for).  Never for resumable calls, which
+// shape; untuned, it takes the networks with one hidden layer of at most 16
+// units, whose 16x16x64 matrix-core tiles are mostly padding.  Wider or
+// deeper networks go to the matrix cores by default (on large workloads the
+// dot4 path pays about h1 + nc h_last / 4 instructions per point and loses,
+// e.g. 64-32-10 at 40 vs 59 G points/s).  Never for resumable calls, which
 // only the matrix-core kernel implements (allowed false).
 bool use_lane(ibmc_ctx *ctx, const ibmc_mlp *net, bool allowed) {
     if (!allowed || !net->lane.ok) return false;
@@ -100,7 +101,7 @@ bool use_lane(ibmc_ctx *ctx, const ibmc_mlp *net, bool allowed) {
         if (it != ctx->tuned.end()) want = it->second;
     }
     if (!want.empty()) return want == kLaneVariantName;
-    return net->L == 2;
+    return net->L == 2 && net->dims[1] <= 16;
 }
 
 struct Level {
@@ -403,13 +404,18 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
     // One network: the enumeration launch alone is bracketed by ek0 / ek1
     // (the kernel time reported for rooflines); several: the whole graph.
     const bool time_enum = NN <= 1;
-    auto launch_net = [&](const NetPlan &pl, size_t id_off, hipStream_t st) -> ibmc_status {
+    // the clean pass of a network's properties, and its enumeration launch
+    auto launch_clean = [&](const NetPlan &pl, size_t id_off, hipStream_t st) -> ibmc_status {
         const ibmc_mlp *net = pl.net;
         const int32_t *ids = ctx->prop_ids.as<int32_t>() + id_off;
         if (net->act == IBMC_ACT_RELU_Q8)
             HIP_OK(launch_clean_q8(net->qd, dprops, ids, (int32_t)pl.ids.size(), ctx->u0.as<int32_t>(), max_h1, st));
         else
             HIP_OK(launch_clean_f32(net->fd, dprops, ids, (int32_t)pl.ids.size(), ctx->u0.as<float>(), max_h1, st));
+        return IBMC_OK;
+    };
+    auto launch_net = [&](const NetPlan &pl, hipStream_t st) -> ibmc_status {
+        const ibmc_mlp *net = pl.net;
         if (pl.n_jobs == 0 || pl.total == 0) return IBMC_OK;
         const int pi = (int)(&pl - plans.data());
         if (pl.lane) {
@@ -505,7 +511,8 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
         HIP_OK(launch_fill_u64(ctr + 2, 1, ~0ull, s));
         size_t id_off = 0;
         for (auto &pl : plans) {
-            IBMC_TRY(launch_net(pl, id_off, s));
+            IBMC_TRY(launch_clean(pl, id_off, s));
+            IBMC_TRY(launch_net(pl, s));
             id_off += pl.ids.size();
             timed = pl.n_jobs > 0 && pl.total > 0;
         }
@@ -568,13 +575,19 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
         ibmc_status cst = IBMC_OK;
         hipError_t ce = launch_fill_u64(ctr, n_ctr, 0ull, cs);
         if (ce == hipSuccess) ce = launch_fill_u64(ctr + 2, 1, ~0ull, cs);
-        if (ce == hipSuccess) ce = hipEventRecord(ctx->fork_ev, cs);
+        // every network's clean pass first, on the origin stream: in a branch
+        // it would queue behind the other branches' persistent grids, which
+        // hold every compute unit until they finish
         size_t id_off = 0;
+        for (int i = 0; i < NN && ce == hipSuccess && cst == IBMC_OK; ++i) {
+            cst = launch_clean(plans[i], id_off, cs);
+            id_off += plans[i].ids.size();
+        }
+        if (ce == hipSuccess) ce = hipEventRecord(ctx->fork_ev, cs);
         for (int i = 0; i < NN && ce == hipSuccess && cst == IBMC_OK; ++i) {
             hipStream_t bs = (i == 0) ? cs : ctx->side[i];
             if (i > 0) ce = hipStreamWaitEvent(bs, ctx->fork_ev, 0);
-            if (ce == hipSuccess) cst = launch_net(plans[i], id_off, bs);
-            id_off += plans[i].ids.size();
+            if (ce == hipSuccess) cst = launch_net(plans[i], bs);
             if (i > 0 && ce == hipSuccess && cst == IBMC_OK) {
                 ce = hipEventRecord(ctx->side_ev[i], bs);
                 if (ce == hipSuccess) ce = hipStreamWaitEvent(cs, ctx->side_ev[i], 0);

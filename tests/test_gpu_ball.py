@@ -39,8 +39,8 @@ SHAPES = [
 @pytest.mark.parametrize("seed,dims,shift", SHAPES)
 def test_lane_kernel_delta_domain(ctx, orc, seed, dims, shift):
     """The default kernel for the shape (the lane kernel for one hidden
-    layer, the matrix cores for two) and the lane kernel forced both return
-    the oracle's records."""
+    layer of at most 16 units, else the matrix cores) and the lane kernel
+    forced both return the oracle's records."""
     from paper_1907_12933_amd import ibmc
     g = I.rng(700 + seed)
     net = I.random_qnet(g, dims, shift=shift, wmax=40, bmax=300)
