@@ -137,10 +137,38 @@ int orc_q8_forward(int L, const int32_t *dims, const int8_t *W, const int32_t *b
     return rc;
 }
 
-/* Double-precision forward of the float network (Eq. (2) on hidden layers). */
+/* Table sigmoid (the paper's CUDA code evaluated the sigmoid from a table,
+ * Sec. IV-D): knots u_i = -8 + i/16, i = 0..256, values sigma(u_i) rounded to
+ * FP32; between knots linear interpolation, outside [-8, 8] the end values. */
+#define ORC_LUT_N 256
+static double lut_value(int i) { return (double)(float)(1.0 / (1.0 + exp(-(-8.0 + i / 16.0)))); }
+
+double orc_lut_sigmoid(double u) {
+    double t = (u + 8.0) * 16.0;
+    if (!(t > 0.0)) return lut_value(0);
+    if (t >= ORC_LUT_N) return lut_value(ORC_LUT_N);
+    int i = (int)floor(t);
+    double f = t - i;
+    double a = lut_value(i), c = lut_value(i + 1);
+    return a + f * (c - a);
+}
+
+/* Double-precision forward of the float network (Eq. (2) on hidden layers;
+ * lut: the table sigmoid instead).  logits (nullable) receives the last
+ * layer. */
+static void f64_forward_ex(int L, const int32_t *dims, const double *W, const double *b,
+                           const uint8_t *x, double *act_a, double *act_b, double *pot,
+                           int32_t *label, double *margin, double *top, int lut, double *logits);
+
 static void f64_forward(int L, const int32_t *dims, const double *W, const double *b,
                         const uint8_t *x, double *act_a, double *act_b, double *pot,
                         int32_t *label, double *margin, double *top) {
+    f64_forward_ex(L, dims, W, b, x, act_a, act_b, pot, label, margin, top, 0, NULL);
+}
+
+static void f64_forward_ex(int L, const int32_t *dims, const double *W, const double *b,
+                           const uint8_t *x, double *act_a, double *act_b, double *pot,
+                           int32_t *label, double *margin, double *top, int lut, double *logits) {
     double *in = act_a, *out = act_b;
     for (int i = 0; i < dims[0]; ++i) in[i] = (double)x[i] / 256.0;
     const double *w = W, *bb = b;
@@ -152,7 +180,7 @@ static void f64_forward(int L, const int32_t *dims, const double *W, const doubl
             const double *row = w + (int64_t)j * nin;
             for (int i = 0; i < nin; ++i) u += row[i] * in[i];
             if (pot) pot[po + j] = u;
-            out[j] = (l < L) ? 1.0 / (1.0 + exp(-u)) : u;
+            out[j] = (l < L) ? (lut ? orc_lut_sigmoid(u) : 1.0 / (1.0 + exp(-u))) : u;
         }
         po += nout;
         w += (int64_t)nout * nin;
@@ -167,6 +195,7 @@ static void f64_forward(int L, const int32_t *dims, const double *W, const doubl
     if (label) *label = best;
     if (margin) *margin = (nc > 1) ? in[best] - second : INFINITY;
     if (top) *top = in[best];
+    if (logits) memcpy(logits, in, sizeof(double) * nc);
 }
 
 int orc_f64_forward(int L, const int32_t *dims, const double *W, const double *b,
@@ -302,19 +331,61 @@ typedef struct {
     const int8_t *Wq; const int32_t *bq; const int32_t *shift;
     const double *Wf; const double *bf;
     double tie_rel;   /* float only: flag when margin <= tie_rel * max(1, |top|) */
+    int lut;          /* float only: the table sigmoid */
+    int literal;      /* 1: the threshold literal with reference value V (below) */
+    double V;
 } net_ref;
 
-/* Evaluate one image; returns label, exact-tie flag (int) or near-tie flag (float). */
-static int eval_image(const net_ref *nr, const uint8_t *xp, void *sa, void *sb,
-                      int32_t *label, int *tie, double *margin) {
+/* The paper's literal l_image_misclassified (Sec. III-C): the desired class
+ * D falls below the reference value V while some other class exceeds it,
+ * (z_D < V) and (max_{i != D} z_i > V).  *eq: how close the two compared
+ * values come to V (0 when one equals it). */
+static int literal_holds(const double *z, int nc, int D, double V, double *closest) {
+    double other = -INFINITY;
+    for (int i = 0; i < nc; ++i) if (i != D && z[i] > other) other = z[i];
+    double a = fabs(z[D] - V), c = fabs(other - V);
+    *closest = a < c ? a : c;
+    return z[D] < V && other > V;
+}
+
+/* Evaluate one image against the clean label `clean` (-1: the clean image
+ * itself).  Returns the label, *viol (the property's violation: the label
+ * changes, or the literal holds), *tie (integer: exact top-2 tie, or with
+ * the literal a compared value equal to V; float: the near-tie flag of the
+ * decision taken) and the float margin. */
+static int eval_image(const net_ref *nr, const uint8_t *xp, void *sa, void *sb, int32_t clean,
+                      int32_t *label, int *viol, int *tie, double *margin) {
+    int nc = nr->dims[nr->L];
+    double z[1024];
     if (!nr->is_float) {
         *margin = 0.0;
-        return q8_forward(nr->L, nr->dims, nr->Wq, nr->bq, nr->shift, xp, sa, sb, NULL, label, tie);
+        int64_t *in_last;
+        int rc = q8_forward(nr->L, nr->dims, nr->Wq, nr->bq, nr->shift, xp, sa, sb, NULL, label, tie);
+        if (rc) return rc;
+        /* the logits sit in the buffer the last layer wrote */
+        in_last = (nr->L % 2) ? (int64_t *)sb : (int64_t *)sa;
+        if (nr->literal) {
+            for (int i = 0; i < nc; ++i) z[i] = (double)in_last[i];
+            double closest;
+            *viol = clean >= 0 && literal_holds(z, nc, clean, nr->V, &closest);
+            *tie = clean >= 0 ? closest == 0.0 : *tie;
+        } else {
+            *viol = clean >= 0 && *label != clean;
+        }
+        return ORC_OK;
     }
     double top;
-    f64_forward(nr->L, nr->dims, nr->Wf, nr->bf, xp, sa, sb, NULL, label, margin, &top);
+    f64_forward_ex(nr->L, nr->dims, nr->Wf, nr->bf, xp, sa, sb, NULL, label, margin, &top, nr->lut, z);
+    if (nr->literal && clean >= 0) {
+        double closest;
+        *viol = literal_holds(z, nc, clean, nr->V, &closest);
+        double scale = fabs(nr->V) > 1.0 ? fabs(nr->V) : 1.0;
+        *tie = closest <= nr->tie_rel * scale;
+        return ORC_OK;
+    }
     double scale = fabs(top) > 1.0 ? fabs(top) : 1.0;
     *tie = *margin <= nr->tie_rel * scale;
+    *viol = clean >= 0 && *label != clean;
     return ORC_OK;
 }
 
@@ -332,10 +403,10 @@ static int enum_first(const net_ref *nr, const uint8_t *x, const int16_t *D, int
         for (int j = 0; j < k; ++j) dig[j] = 0;
         do {
             apply_point(x, n, D, k, pix, dig, xp);
-            int32_t lab; int tie; double margin;
-            int rc = eval_image(nr, xp, sa, sb, &lab, &tie, &margin);
+            int32_t lab; int tie, viol; double margin;
+            int rc = eval_image(nr, xp, sa, sb, clean, &lab, &viol, &tie, &margin);
             if (rc) return rc;
-            if (lab != clean) {
+            if (viol) {
                 rc = rec_push(cex, k, rank, lab, margin);
                 if (rc) return rc;
             }
@@ -391,11 +462,11 @@ static int enum_first_ball(const net_ref *nr, const uint8_t *x, int64_t r2, int 
                 xp[pix[j]] = (uint8_t)(v < 0 ? 0 : v > 255 ? 255 : v);
             }
             if (inside && sq <= r2) {
-                int32_t lab; int tie; double margin;
-                int rc = eval_image(nr, xp, sa, sb, &lab, &tie, &margin);
+                int32_t lab; int tie, viol; double margin;
+                int rc = eval_image(nr, xp, sa, sb, clean, &lab, &viol, &tie, &margin);
                 if (rc) return rc;
                 (*n_points)++;
-                if (lab != clean) {
+                if (viol) {
                     rc = rec_push(cex, k, rank, lab, margin);
                     if (rc) return rc;
                 }
@@ -426,8 +497,9 @@ static int check_impl(const net_ref *nr, const uint8_t *x, const int16_t *D, int
     size_t elt = nr->is_float ? sizeof(double) : sizeof(int64_t);
     void *sa = malloc(elt * mw), *sb = malloc(elt * mw);
     if (!sa || !sb) { free(sa); free(sb); return ORC_E_OOM; }
-    int32_t clean; int tie0; double mg0;
-    int rc = eval_image(nr, x, sa, sb, &clean, &tie0, &mg0);
+    int32_t clean; int tie0, viol0; double mg0;
+    int rc = eval_image(nr, x, sa, sb, -1, &clean, &viol0, &tie0, &mg0);
+    if (!rc && nr->literal) rc = eval_image(nr, x, sa, sb, clean, &clean, &viol0, &tie0, &mg0);
     free(sa); free(sb);
     if (rc) return rc;
     *clean_label = clean;
@@ -517,7 +589,7 @@ int orc_q8_check(int L, const int32_t *dims, const int8_t *W, const int32_t *b,
                  int32_t *out_k, int64_t *out_rank, int32_t *out_label, int64_t *n_out,
                  int nthreads) {
     if (L < 1 || !dims || !W || !b || !x || !D) return ORC_E_INVALID;
-    net_ref nr = {0, L, dims, W, b, shift, NULL, NULL, 0.0};
+    net_ref nr = {0, L, dims, W, b, shift, NULL, NULL, 0.0, 0, 0, 0.0};
     return check_impl(&nr, x, D, m, -1, k_min, k_max, k_step, stop_at_first, cap, points, cex_count,
                       tie_count, clean_label, first_unsafe_k, out_k, out_rank, out_label, n_out,
                       0, NULL, NULL, NULL, NULL, nthreads);
@@ -534,7 +606,7 @@ int orc_q8_ball_check(int L, const int32_t *dims, const int8_t *W, const int32_t
                       int32_t *out_k, int64_t *out_rank, int32_t *out_label, int64_t *n_out,
                       int nthreads) {
     if (L < 1 || !dims || !W || !b || !x || r2 < 0) return ORC_E_INVALID;
-    net_ref nr = {0, L, dims, W, b, shift, NULL, NULL, 0.0};
+    net_ref nr = {0, L, dims, W, b, shift, NULL, NULL, 0.0, 0, 0, 0.0};
     return check_impl(&nr, x, NULL, 0, r2, k_min, k_max, k_step, stop_at_first, cap, points, cex_count,
                       tie_count, clean_label, first_unsafe_k, out_k, out_rank, out_label, n_out,
                       0, NULL, NULL, NULL, NULL, nthreads);
@@ -551,10 +623,49 @@ int orc_f64_check(int L, const int32_t *dims, const double *W, const double *b,
                   int64_t tie_cap, int32_t *tie_k, int64_t *tie_rank, double *tie_margin,
                   int64_t *n_tie_out, int nthreads) {
     if (L < 1 || !dims || !W || !b || !x || !D) return ORC_E_INVALID;
-    net_ref nr = {1, L, dims, NULL, NULL, NULL, W, b, tie_rel};
+    net_ref nr = {1, L, dims, NULL, NULL, NULL, W, b, tie_rel, 0, 0, 0.0};
     return check_impl(&nr, x, D, m, -1, k_min, k_max, k_step, stop_at_first, cap, points, cex_count,
                       tie_count, clean_label, first_unsafe_k, out_k, out_rank, out_label, n_out,
                       tie_cap, tie_k, tie_rank, tie_margin, n_tie_out, nthreads);
+}
+
+/* The float check with the table sigmoid (lut != 0) and / or the threshold
+ * literal (literal != 0, reference value V): with the literal a point is a
+ * counterexample when (z_D < V) and (max_{i != D} z_i > V), D the clean
+ * label, and it is flagged when z_D or the largest other logit lies within
+ * tie_rel * max(1, |V|) of V.  Otherwise as orc_f64_check. */
+int orc_f64_check_ex(int L, const int32_t *dims, const double *W, const double *b,
+                     const uint8_t *x, const int16_t *D, int m,
+                     int k_min, int k_max, int k_step, int stop_at_first, int64_t cap,
+                     double tie_rel, int lut, int literal, double V,
+                     int64_t *points, int64_t *cex_count, int64_t *tie_count,
+                     int32_t *clean_label, int32_t *first_unsafe_k,
+                     int32_t *out_k, int64_t *out_rank, int32_t *out_label, int64_t *n_out,
+                     int64_t tie_cap, int32_t *tie_k, int64_t *tie_rank, double *tie_margin,
+                     int64_t *n_tie_out, int nthreads) {
+    if (L < 1 || !dims || !W || !b || !x || !D) return ORC_E_INVALID;
+    net_ref nr = {1, L, dims, NULL, NULL, NULL, W, b, tie_rel, lut != 0, literal != 0, V};
+    return check_impl(&nr, x, D, m, -1, k_min, k_max, k_step, stop_at_first, cap, points, cex_count,
+                      tie_count, clean_label, first_unsafe_k, out_k, out_rank, out_label, n_out,
+                      tie_cap, tie_k, tie_rank, tie_margin, n_tie_out, nthreads);
+}
+
+/* The integer check with the threshold literal, reference value V (an
+ * integer logit value): a point is a counterexample when (z_D < V) and
+ * (max_{i != D} z_i > V); ties count the points where one of the two equals
+ * V.  Otherwise as orc_q8_check. */
+int orc_q8_check_literal(int L, const int32_t *dims, const int8_t *W, const int32_t *b,
+                         const int32_t *shift, const uint8_t *x, const int16_t *D, int m, int64_t V,
+                         int k_min, int k_max, int k_step, int stop_at_first, int64_t cap,
+                         int64_t *points, int64_t *cex_count, int64_t *tie_count,
+                         int32_t *clean_label, int32_t *first_unsafe_k,
+                         int32_t *out_k, int64_t *out_rank, int32_t *out_label, int64_t *n_out,
+                         int nthreads) {
+    if (L < 1 || !dims || !W || !b || !x || !D) return ORC_E_INVALID;
+    net_ref nr = {0, L, dims, W, b, shift, NULL, NULL, 0.0, 0, 1, (double)V};
+    return check_impl(&nr, x, D, m, -1, k_min, k_max, k_step, stop_at_first, cap, points, cex_count,
+                      tie_count, clean_label, first_unsafe_k, out_k, out_rank, out_label, n_out,
+                      0, NULL, NULL, NULL, NULL, nthreads);
 }
 
 /* Replay / sample: decode each (k, rank), build the perturbed image and run

@@ -46,6 +46,16 @@ def lib():
         L.orc_q8_ball_check.argtypes = [C.c_int, I32P, I8P, I32P, I32P, U8P, C.c_int64,
                                         C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, I64P, I64P, I64P,
                                         I32P, I32P, I32P, I64P, I32P, I64P, C.c_int]
+        L.orc_lut_sigmoid.argtypes = [C.c_double]
+        L.orc_lut_sigmoid.restype = C.c_double
+        L.orc_f64_check_ex.argtypes = [C.c_int, I32P, F64P, F64P, U8P, I16P, C.c_int,
+                                       C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, C.c_double,
+                                       C.c_int, C.c_int, C.c_double,
+                                       I64P, I64P, I64P, I32P, I32P, I32P, I64P, I32P, I64P,
+                                       C.c_int64, I32P, I64P, F64P, I64P, C.c_int]
+        L.orc_q8_check_literal.argtypes = [C.c_int, I32P, I8P, I32P, I32P, U8P, I16P, C.c_int, C.c_int64,
+                                           C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64,
+                                           I64P, I64P, I64P, I32P, I32P, I32P, I64P, I32P, I64P, C.c_int]
         L.orc_f64_check.argtypes = [C.c_int, I32P, F64P, F64P, U8P, I16P, C.c_int,
                                     C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, C.c_double,
                                     I64P, I64P, I64P, I32P, I32P, I32P, I64P, I32P, I64P,
@@ -190,8 +200,40 @@ def q8_ball_check(net, x, r2, k_min=1, k_max=2, k_step=1, stop_at_first=False, c
                 cex_k=ok[:w].copy(), cex_rank=orr[:w].copy(), cex_label=ol[:w].copy(), m=2 * ball_digits(r2))
 
 
+def lut_sigmoid(u):
+    """The table sigmoid (knots -8 + i/16, FP32 values, linear between)."""
+    return float(lib().orc_lut_sigmoid(float(u)))
+
+
+def q8_check_literal(net, x, deltas, V, k_min=1, k_max=2, k_step=1, stop_at_first=False, cap=1 << 22,
+                     nthreads=None):
+    """Integer check of the threshold literal (z_D < V and max_{i != D} z_i > V)."""
+    dims, W, b, sh = _flat_q8(net)
+    x = np.ascontiguousarray(x, np.uint8)
+    D = np.ascontiguousarray(deltas, np.int16)
+    nl = _levels(k_min, k_max, k_step)
+    pts = np.zeros(nl, np.int64); cx = np.zeros(nl, np.int64); ti = np.zeros(nl, np.int64)
+    cl = np.zeros(1, np.int32); fu = np.zeros(1, np.int32)
+    ok = np.zeros(cap, np.int32); orr = np.zeros(cap, np.int64); ol = np.zeros(cap, np.int32)
+    nout = np.zeros(1, np.int64)
+    lev = _ck(lib().orc_q8_check_literal(len(dims) - 1, _p(dims, I32P), _p(W, I8P), _p(b, I32P), _p(sh, I32P),
+                                         _p(x, U8P), _p(D, I16P), len(D), int(V), k_min, k_max, k_step,
+                                         int(stop_at_first), cap, _p(pts, I64P), _p(cx, I64P), _p(ti, I64P),
+                                         _p(cl, I32P), _p(fu, I32P), _p(ok, I32P), _p(orr, I64P), _p(ol, I32P),
+                                         _p(nout, I64P), _threads(nthreads)))
+    n = int(nout[0]); w = min(n, cap)
+    return dict(levels=list(range(k_min, k_max + 1, k_step))[:lev], points=pts[:lev], cex=cx[:lev],
+                ties=ti[:lev], clean_label=int(cl[0]), first_unsafe_k=int(fu[0]), cex_total=n,
+                cex_k=ok[:w].copy(), cex_rank=orr[:w].copy(), cex_label=ol[:w].copy())
+
+
 def f64_check(net, x, deltas, k_min=1, k_max=2, k_step=1, stop_at_first=False, cap=1 << 22,
-              tie_rel=4e-5, tie_cap=1 << 22, nthreads=None):
+              tie_rel=4e-5, tie_cap=1 << 22, nthreads=None, lut=False, literal_v=None):
+    """Double-precision float check; lut: the table sigmoid; literal_v: check
+    the threshold literal with this reference value instead of the label."""
+    if lut or literal_v is not None:
+        return _f64_check_ex(net, x, deltas, k_min, k_max, k_step, stop_at_first, cap, tie_rel, tie_cap,
+                             nthreads, lut, literal_v)
     dims, W, b = _flat_f64(net)
     x = np.ascontiguousarray(x, np.uint8)
     D = np.ascontiguousarray(deltas, np.int16)
@@ -207,6 +249,32 @@ def f64_check(net, x, deltas, k_min=1, k_max=2, k_step=1, stop_at_first=False, c
                                   _p(cl, I32P), _p(fu, I32P), _p(ok, I32P), _p(orr, I64P), _p(ol, I32P),
                                   _p(nout, I64P), tie_cap, _p(tk, I32P), _p(tr, I64P), _p(tm, F64P),
                                   _p(ntie, I64P), _threads(nthreads)))
+    n = int(nout[0]); w = min(n, cap)
+    nt = int(ntie[0]); wt = min(nt, tie_cap)
+    return dict(levels=list(range(k_min, k_max + 1, k_step))[:lev], points=pts[:lev], cex=cx[:lev],
+                ties=ti[:lev], clean_label=int(cl[0]), first_unsafe_k=int(fu[0]), cex_total=n,
+                cex_k=ok[:w].copy(), cex_rank=orr[:w].copy(), cex_label=ol[:w].copy(),
+                tie_total=nt, tie_k=tk[:wt].copy(), tie_rank=tr[:wt].copy(), tie_margin=tm[:wt].copy())
+
+
+def _f64_check_ex(net, x, deltas, k_min, k_max, k_step, stop_at_first, cap, tie_rel, tie_cap, nthreads, lut,
+                  literal_v):
+    dims, W, b = _flat_f64(net)
+    x = np.ascontiguousarray(x, np.uint8)
+    D = np.ascontiguousarray(deltas, np.int16)
+    nl = _levels(k_min, k_max, k_step)
+    pts = np.zeros(nl, np.int64); cx = np.zeros(nl, np.int64); ti = np.zeros(nl, np.int64)
+    cl = np.zeros(1, np.int32); fu = np.zeros(1, np.int32)
+    ok = np.zeros(cap, np.int32); orr = np.zeros(cap, np.int64); ol = np.zeros(cap, np.int32)
+    tk = np.zeros(tie_cap, np.int32); tr = np.zeros(tie_cap, np.int64); tm = np.zeros(tie_cap, np.float64)
+    nout = np.zeros(1, np.int64); ntie = np.zeros(1, np.int64)
+    lev = _ck(lib().orc_f64_check_ex(len(dims) - 1, _p(dims, I32P), _p(W, F64P), _p(b, F64P), _p(x, U8P),
+                                     _p(D, I16P), len(D), k_min, k_max, k_step, int(stop_at_first), cap,
+                                     float(tie_rel), int(bool(lut)), int(literal_v is not None),
+                                     float(literal_v or 0.0), _p(pts, I64P), _p(cx, I64P), _p(ti, I64P),
+                                     _p(cl, I32P), _p(fu, I32P), _p(ok, I32P), _p(orr, I64P), _p(ol, I32P),
+                                     _p(nout, I64P), tie_cap, _p(tk, I32P), _p(tr, I64P), _p(tm, F64P),
+                                     _p(ntie, I64P), _threads(nthreads)))
     n = int(nout[0]); w = min(n, cap)
     nt = int(ntie[0]); wt = min(nt, tie_cap)
     return dict(levels=list(range(k_min, k_max + 1, k_step))[:lev], points=pts[:lev], cex=cx[:lev],
