@@ -129,7 +129,30 @@ typedef struct {
  * it checked.  Calling again with resume_cursor = next_cursor (same network,
  * image, deltas, k range and library build) continues the check; the union
  * of the calls' records and the sums of their counts equal one uninterrupted
- * call's. */
+ * call's.
+ * property: IBMC_PROPERTY_LABEL (0) — a point violates the property when its
+ * label differs from the clean label; IBMC_PROPERTY_LITERAL (1) — the
+ * paper's literal l_image_misclassified (Sec. III-C): with D the clean
+ * label and V = literal_v, a point violates it when z_D < V and some other
+ * logit z_i > V (records still carry the point's label).  Integer networks:
+ * V must be an integer in the int32 range, exact ties then count the points
+ * where z_D or the largest other logit equals V; float networks: a point is
+ * a near tie when one of the two lies within near_tie_rel * max(1, |V|) of
+ * V.  Level 0 counts no ties under the literal.
+ * sigmoid (float networks): IBMC_SIGMOID_EXP (0) — 1/(1 + e^-u);
+ * IBMC_SIGMOID_TABLE (1) — the table sigmoid the paper's CUDA code used
+ * (Sec. IV-D): knots -8 + i/16, i = 0..256, holding sigma in FP32, linear
+ * between knots, the end values outside [-8, 8].
+ * The literal and the table run on the lane-per-point kernels only: integer
+ * networks with 1-2 hidden layers of at most 64 units and at most 16
+ * classes, float networks with hidden widths up to 128 (else IBMC_E_UNIMPL);
+ * neither combines with resume_cursor / chunk_budget or the ordered search
+ * (IBMC_E_UNIMPL).  All-zero fields keep the label property and the
+ * exponential. */
+#define IBMC_PROPERTY_LABEL 0
+#define IBMC_PROPERTY_LITERAL 1
+#define IBMC_SIGMOID_EXP 0
+#define IBMC_SIGMOID_TABLE 1
 typedef struct {
     int32_t k_min, k_max, k_step, stop_at_first;
     int64_t cex_capacity;
@@ -138,6 +161,9 @@ typedef struct {
     int32_t records_on_device;
     int64_t resume_cursor;
     int64_t chunk_budget;
+    int32_t property;
+    int32_t sigmoid;
+    double literal_v;
 } ibmc_check_opts;
 
 /* One counterexample (or near tie): decode with ibmc_decode_point.  prop is

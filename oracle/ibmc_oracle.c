@@ -512,8 +512,9 @@ static int check_impl(const net_ref *nr, const uint8_t *x, const int16_t *D, int
         cex_count[level] = 0;
         tie_count[level] = 0;
         if (k == 0) {
-            /* the empty perturbation is the clean image itself */
-            tie_count[level] = tie0;
+            /* the empty perturbation is the clean image itself (no tie count
+             * under the literal) */
+            tie_count[level] = nr->literal ? 0 : tie0;
             continue;
         }
         if (ball && rd == 0) continue;   /* no nonzero offset fits: the level is empty */

@@ -189,8 +189,20 @@ __global__ void __launch_bounds__(256) enum_lane_kernel(LaneParams P) {
             int cnt = 0;
 #pragma unroll
             for (int j = 0; j < 16; ++j) cnt += (j < nc && z[j] == top) ? 1 : 0;
-            const bool viol = valid && best != label0;
-            const bool tie = valid && cnt > 1;
+            bool viol = valid && best != label0;
+            bool tie = valid && cnt > 1;
+            if (P.literal) {
+                // the threshold literal: the desired (clean) class below V,
+                // another above; ties: one of the two equals V
+                int zd = z[0], other = INT32_MIN;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    if (j == label0) zd = z[j];
+                    else if (j < nc) other = max(other, z[j]);
+                }
+                viol = valid && zd < P.lit_v && other > P.lit_v;
+                tie = valid && (zd == P.lit_v || other == P.lit_v);
+            }
             const unsigned long long mv = __ballot(viol);
             if (mv) {
                 unsigned long long rb = 0;

@@ -42,6 +42,31 @@ __device__ __forceinline__ float sigmoid_f32(float u) {
     return __builtin_amdgcn_rcpf(1.0f + e);
 }
 
+// The table sigmoid: knots u_i = -8 + i/16 holding sigma(u_i) in FP32 (tab,
+// kLutIntervals + 1 values), linear between knots, the end values outside.
+__device__ __forceinline__ float table_sigmoid(float u, const float *tab) {
+    const float t = (u + 8.0f) * 16.0f;
+    if (!(t > 0.0f)) return tab[0];
+    if (t >= (float)kLutIntervals) return tab[kLutIntervals];
+    const int i = (int)t;
+    const float a = tab[i];
+    return fmaf(t - (float)i, tab[i + 1] - a, a);
+}
+
+// Hidden-layer activation: the exponential form, or the table (use_tab).
+__device__ __forceinline__ float act_f32(float u, bool use_tab, const float *tab) {
+    return use_tab ? table_sigmoid(u, tab) : sigmoid_f32(u);
+}
+
+// Stage the table sigmoid's knots in LDS (every thread of the block takes
+// part; tab: the block's LDS copy).  Returns whether the table is used.
+__device__ __forceinline__ bool stage_table(const float *lut, float *tab) {
+    if (!lut) return false;
+    for (int i = threadIdx.x; i <= kLutIntervals; i += blockDim.x) tab[i] = lut[i];
+    __syncthreads();
+    return true;
+}
+
 // Cross-lane exchange through this wave's LDS: earlier writes complete
 // before later reads.
 __device__ __forceinline__ void wave_lds_sync() {
@@ -191,7 +216,7 @@ constexpr int kLaneWaves = 4;  // waves per workgroup of the lane kernels
 // own column.
 template <int H1, int H2, int NCP>
 __device__ __forceinline__ void lane_upper(const FNetDev &net, const float (&a1)[H1], float *a2w, int lane,
-                                           float (&z)[NCP]) {
+                                           float (&z)[NCP], bool use_tab, const float *tab) {
     if constexpr (H2 == 0) {
         const float *W = opaque(net.WP[2]);
         const float *B = opaque(net.bP[2]);
@@ -241,7 +266,7 @@ __device__ __forceinline__ void lane_upper(const FNetDev &net, const float (&a1)
                 for (int jj = 0; jj < 8; ++jj) tot[jj] += part[jj];
             }
 #pragma unroll
-            for (int jj = 0; jj < 8; ++jj) a2w[(jb + jj) * 64 + lane] = sigmoid_f32(tot[jj]);
+            for (int jj = 0; jj < 8; ++jj) a2w[(jb + jj) * 64 + lane] = act_f32(tot[jj], use_tab, tab);
         }
         const float *W3 = opaque(net.WP[3]);
         const float *B3 = opaque(net.bP[3]);
@@ -312,6 +337,8 @@ __global__ void __launch_bounds__(256) enum_f32_lane_kernel(FEnumParams P) {
     constexpr int CH = kF32LaneChunk;
     __shared__ float a2s[kLaneWaves][H2 > 0 ? H2 : NCP][64];
     __shared__ __attribute__((aligned(16))) float bases[kLaneWaves][H1];
+    __shared__ float tab[kLutIntervals + 1];
+    const bool use_tab = stage_table(P.lut, tab);
     const int lane = __lane_id();
     float *a2w = &a2s[threadIdx.x >> 6][0][0];
     float *base = &bases[threadIdx.x >> 6][0];
@@ -357,18 +384,30 @@ __global__ void __launch_bounds__(256) enum_f32_lane_kernel(FEnumParams P) {
 #pragma unroll
         for (int j4 = 0; j4 < H1 / 4; ++j4) {
             const float4 b = *reinterpret_cast<const float4 *>(base + 4 * j4);
-            a1[4 * j4 + 0] = sigmoid_f32(fmaf(e, wrow[j4].x, b.x));
-            a1[4 * j4 + 1] = sigmoid_f32(fmaf(e, wrow[j4].y, b.y));
-            a1[4 * j4 + 2] = sigmoid_f32(fmaf(e, wrow[j4].z, b.z));
-            a1[4 * j4 + 3] = sigmoid_f32(fmaf(e, wrow[j4].w, b.w));
+            a1[4 * j4 + 0] = act_f32(fmaf(e, wrow[j4].x, b.x), use_tab, tab);
+            a1[4 * j4 + 1] = act_f32(fmaf(e, wrow[j4].y, b.y), use_tab, tab);
+            a1[4 * j4 + 2] = act_f32(fmaf(e, wrow[j4].z, b.z), use_tab, tab);
+            a1[4 * j4 + 3] = act_f32(fmaf(e, wrow[j4].w, b.w), use_tab, tab);
         }
         float z[NCP];
-        lane_upper<H1, H2, NCP>(P.net, a1, a2w, lane, z);
+        lane_upper<H1, H2, NCP>(P.net, a1, a2w, lane, z, use_tab, tab);
         int best;
         float top, margin;
         decide_f32<NCP>(z, nc, best, top, margin);
-        const bool near = valid && margin <= P.tie_rel * fmaxf(1.0f, fabsf(top));
-        const bool viol = valid && best != label0;
+        bool near = valid && margin <= P.tie_rel * fmaxf(1.0f, fabsf(top));
+        bool viol = valid && best != label0;
+        if (P.literal) {
+            // the threshold literal: the desired (clean) class below V, another above
+            float zd = z[0], other = -INFINITY;
+#pragma unroll
+            for (int j = 0; j < NCP; ++j) {
+                if (j == label0) zd = z[j];
+                else if (j < nc) other = fmaxf(other, z[j]);
+            }
+            const float V = P.lit_v;
+            viol = valid && zd < V && other > V;
+            near = valid && fminf(fabsf(zd - V), fabsf(other - V)) <= P.tie_rel * fmaxf(1.0f, fabsf(V));
+        }
         emit_f32(P, c, viol, near, p, i, best);
         cur++;
         if (cur < end) seg_new = cursor_next<CH, FEnumParams>(c, P);
@@ -380,6 +419,8 @@ __global__ void __launch_bounds__(256) enum_f32_lane_kernel(FEnumParams P) {
 template <int H1, int H2, int NCP>
 __global__ void __launch_bounds__(256) eval_f32_lane_kernel(F32EvalParams E) {
     __shared__ float a2s[kLaneWaves][H2 > 0 ? H2 : NCP][64];
+    __shared__ float tab[kLutIntervals + 1];
+    const bool use_tab = stage_table(E.lut, tab);
     const int lane = __lane_id();
     float *a2w = &a2s[threadIdx.x >> 6][0][0];
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -407,9 +448,10 @@ __global__ void __launch_bounds__(256) eval_f32_lane_kernel(F32EvalParams E) {
     const float *w1 = E.net.W1P + (int64_t)p * H1;
     float a1[H1];
 #pragma unroll
-    for (int j = 0; j < H1; ++j) a1[j] = sigmoid_f32(fmaf(e, w1[j], prefix_potential<H1>(E.net, u0, np, pp, ee, j)));
+    for (int j = 0; j < H1; ++j)
+        a1[j] = act_f32(fmaf(e, w1[j], prefix_potential<H1>(E.net, u0, np, pp, ee, j)), use_tab, tab);
     float z[NCP];
-    lane_upper<H1, H2, NCP>(E.net, a1, a2w, lane, z);
+    lane_upper<H1, H2, NCP>(E.net, a1, a2w, lane, z, use_tab, tab);
     const int nc = E.net.dims[E.net.L];
     int best;
     float top, margin;

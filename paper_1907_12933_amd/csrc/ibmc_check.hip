@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -318,7 +319,8 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
         const ibmc_mlp *net = pl.net;
         const bool q8 = net->act == IBMC_ACT_RELU_Q8;
         int CH = q8 ? 0 : enum_f32_chunk(net->fd);
-        bool need_lane = false;   // an L2-ball property runs on the lane kernel only
+        // an L2-ball property, or the literal, runs on the lane kernel only
+        bool need_lane = o->property == IBMC_PROPERTY_LITERAL;
         for (int pid : pl.ids) need_lane |= B.hprops[pid].ball != 0;
         if (q8) pl.lane = need_lane || use_lane(ctx, net, resume == 0 && budget == 0);
         if (pl.lane) {
@@ -401,6 +403,18 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
     HIP_OK(hipStreamSynchronize(s));  // host staging vectors may go now
 
     PropDev *dprops = ctx->props.as<PropDev>();
+    // the table sigmoid's knots: sigma(-8 + i/16) rounded to FP32
+    const float *lut = nullptr;
+    if (o->sigmoid == IBMC_SIGMOID_TABLE) {
+        if (!ctx->lut.p) {
+            std::vector<float> knots(kLutIntervals + 1);
+            for (int i = 0; i <= kLutIntervals; ++i) knots[i] = (float)(1.0 / (1.0 + std::exp(-(-8.0 + i / 16.0))));
+            IBMC_TRY(ctx->lut.upload(knots.data(), knots.size() * 4, s));
+            HIP_OK(hipStreamSynchronize(s));
+        }
+        lut = ctx->lut.as<float>();
+    }
+    const bool literal = o->property == IBMC_PROPERTY_LITERAL;
     // One network: the enumeration launch alone is bracketed by ek0 / ek1
     // (the kernel time reported for rooflines); several: the whole graph.
     const bool time_enum = NN <= 1;
@@ -411,7 +425,8 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
         if (net->act == IBMC_ACT_RELU_Q8)
             HIP_OK(launch_clean_q8(net->qd, dprops, ids, (int32_t)pl.ids.size(), ctx->u0.as<int32_t>(), max_h1, st));
         else
-            HIP_OK(launch_clean_f32(net->fd, dprops, ids, (int32_t)pl.ids.size(), ctx->u0.as<float>(), max_h1, st));
+            HIP_OK(launch_clean_f32(net->fd, dprops, ids, (int32_t)pl.ids.size(), ctx->u0.as<float>(), max_h1, st,
+                                    lut));
         return IBMC_OK;
     };
     auto launch_net = [&](const NetPlan &pl, hipStream_t st) -> ibmc_status {
@@ -439,6 +454,8 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
             P.slot_points = ctr + sp0;
             P.stop_flag = reinterpret_cast<volatile int32_t *>(ctr + 4);
             P.abort_host = ctx->flags_dev;
+            P.literal = literal ? 1 : 0;
+            P.lit_v = literal ? (int32_t)o->literal_v : 0;
             if (time_enum) HIP_OK(hipEventRecord(ctx->ek0, st));
             HIP_OK(launch_enum_lane(pl.grid, P, st));
             if (time_enum) HIP_OK(hipEventRecord(ctx->ek1, st));
@@ -495,6 +512,9 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
             P.slot_ties = ctr + st0;
             P.stop_flag = reinterpret_cast<volatile int32_t *>(ctr + 4);
             P.abort_host = ctx->flags_dev;
+            P.lut = lut;
+            P.literal = literal ? 1 : 0;
+            P.lit_v = (float)o->literal_v;
             if (time_enum) HIP_OK(hipEventRecord(ctx->ek0, st));
             HIP_OK(launch_enum_f32(pl.grid, P, st));
             if (time_enum) HIP_OK(hipEventRecord(ctx->ek1, st));
@@ -559,6 +579,9 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
         put(scal, sizeof(scal));
         const float tie_rel = o->near_tie_rel;
         put(&tie_rel, sizeof(tie_rel));
+        put(&o->property, sizeof(o->property));
+        put(&lut, sizeof(lut));
+        put(&o->literal_v, sizeof(o->literal_v));
         if (ctx->graph_exec && sig == ctx->graph_sig) {
             const hipError_t le = hipGraphLaunch(ctx->graph_exec, cs);
             if (le == hipSuccess) {
@@ -700,6 +723,29 @@ ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props_in, int32
     if (o->near_tie_capacity > 0 && !tie_buf) return fail(IBMC_E_INVALID, "near_tie_buf is null with capacity > 0");
     const bool resumable = o->resume_cursor != 0 || o->chunk_budget != 0;
     if (o->resume_cursor < 0 || o->chunk_budget < 0) return fail(IBMC_E_INVALID, "negative resume cursor or budget");
+    // the threshold literal and the table sigmoid: lane-per-point kernels only
+    if (o->property != IBMC_PROPERTY_LABEL && o->property != IBMC_PROPERTY_LITERAL)
+        return fail(IBMC_E_INVALID, "unknown property %d", o->property);
+    if (o->sigmoid != IBMC_SIGMOID_EXP && o->sigmoid != IBMC_SIGMOID_TABLE)
+        return fail(IBMC_E_INVALID, "unknown sigmoid %d", o->sigmoid);
+    const bool literal = o->property == IBMC_PROPERTY_LITERAL, table = o->sigmoid == IBMC_SIGMOID_TABLE;
+    if (literal || table) {
+        if (resumable) return fail(IBMC_E_UNIMPL, "resume / budget with the literal or the table sigmoid");
+        for (int i = 0; i < n_props; ++i) {
+            const ibmc_mlp *net = props[i].net;
+            if (net->act == IBMC_ACT_RELU_Q8) {
+                if (table) return fail(IBMC_E_INVALID, "property %d: the table sigmoid is for float networks", i);
+                if (!net->lane.ok)
+                    return fail(IBMC_E_UNIMPL, "property %d: the literal runs on the lane kernel (1-2 hidden layers "
+                                "of at most 64 units, at most 16 classes)", i);
+                if (o->literal_v != std::floor(o->literal_v) || std::fabs(o->literal_v) > 2147483647.0)
+                    return fail(IBMC_E_INVALID, "literal_v %g is not an int32 value (integer network)", o->literal_v);
+            } else if (net->fd.kind != F32_LANE) {
+                return fail(IBMC_E_UNIMPL, "property %d: the literal and the table sigmoid run on the float lane "
+                            "kernel (hidden widths up to 128)", i);
+            }
+        }
+    }
     if (resumable) {
         if (any_ball) return fail(IBMC_E_UNIMPL, "resume / budget with the L2-ball domain");
         if (o->stop_at_first) return fail(IBMC_E_UNIMPL, "resume / budget with stop_at_first");
@@ -850,7 +896,7 @@ ibmc_status check_batch_impl(ibmc_ctx *ctx, const ibmc_property *props_in, int32
                                : binom_small(props[i].net->dims[0], k) * ipow64(props[i].n_deltas, k);
             S.points[t] = pts;
             S.cex[t] = (k == 0) ? 0 : (int64_t)cex_acc[slot];
-            S.ties[t] = (k == 0) ? (q8 ? B.hprops[i].tie0 : 0) : (int64_t)ties_acc[slot];
+            S.ties[t] = (k == 0) ? (q8 && !literal ? B.hprops[i].tie0 : 0) : (int64_t)ties_acc[slot];
             S.points_total += pts;
             S.cex_total += S.cex[t];
             if (!q8) S.near_ties_total += S.ties[t];
@@ -1124,6 +1170,8 @@ ibmc_status ordered_search(ibmc_ctx *ctx, const ibmc_mlp *net, const ibmc_propos
                            ibmc_cex *cex_buf) {
     using clk = std::chrono::steady_clock;
     const auto t0 = clk::now();
+    if (o->property != IBMC_PROPERTY_LABEL || o->sigmoid != IBMC_SIGMOID_EXP)
+        return fail(IBMC_E_UNIMPL, "the ordered search checks the label property with the exponential sigmoid");
     HIP_OK(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     const int n = net->dims[0];

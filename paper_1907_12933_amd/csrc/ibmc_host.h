@@ -87,6 +87,7 @@ struct ibmc_ctx {
     // scratch of the check driver (grow-only)
     ibmc::DevBuf images, props, jobs, qcum, u0, u0_index, prop_ids, counters, recs, ties, order;
     ibmc::DevBuf u0f, sortbuf;
+    ibmc::DevBuf lut;                  // the table sigmoid's knots (built on first use)
     ibmc::DevBuf recout;  // sorted records in the public layout, on their way to a host buffer
     ibmc::DevBuf prop_scratch, prop_feat, prop_scores, shell_cum;  // ranked search
     int64_t shell_cum_n = -1, shell_cum_ch = -1;                   // shell_cum holds this plan

@@ -237,7 +237,13 @@ struct FEnumParams {
     unsigned long long *slot_ties;
     volatile int32_t *stop_flag;
     volatile int32_t *abort_host;
+    const float *lut;                  // the table sigmoid's 257 knot values, or null (exponential)
+    int32_t literal;                   // the threshold literal instead of the label change
+    float lit_v;                       // its reference value V
 };
+
+// Knots of the table sigmoid: u = -8 + i / 16, i = 0..kLutIntervals.
+constexpr int kLutIntervals = 256;
 
 // Binomial coefficient for the small k used here (exact in int64 for n <= 1024, r <= 8).
 __host__ __device__ inline int64_t binom_small(int64_t n, int r) {

@@ -56,6 +56,7 @@ struct F32EvalParams {
     float *logits;                  // nullable: [n][classes]
     int32_t *labels;                // nullable: [n]
     float *margins;                 // nullable: [n]
+    const float *lut;               // the table sigmoid's knots, or null (exponential)
 };
 
 hipError_t launch_forward_f32(const FNetDev &net, const uint8_t *images, int64_t n_images,
@@ -66,7 +67,8 @@ hipError_t launch_replay_f32(const FNetDev &net, const uint8_t *clean, const int
 // with zeros) of every listed property, then its clean label through the
 // enumeration arithmetic.
 hipError_t launch_clean_f32(const FNetDev &net, PropDev *props, const int32_t *prop_ids,
-                            int32_t n_ids, float *u0_store, int64_t u0_stride, hipStream_t s);
+                            int32_t n_ids, float *u0_store, int64_t u0_stride, hipStream_t s,
+                            const float *lut = nullptr);
 hipError_t launch_eval_f32(const F32EvalParams &E, hipStream_t s);
 // Persistent enumeration; grid (in waves) from f32_enum_grid.
 hipError_t launch_enum_f32(int grid_waves, const FEnumParams &P, hipStream_t s);

@@ -430,7 +430,7 @@ hipError_t launch_eval_f32(const F32EvalParams &E, hipStream_t s) {
 }
 
 hipError_t launch_clean_f32(const FNetDev &net, PropDev *props, const int32_t *prop_ids, int32_t n_ids,
-                            float *u0_store, int64_t u0_stride, hipStream_t s) {
+                            float *u0_store, int64_t u0_stride, hipStream_t s, const float *lut) {
     if (n_ids <= 0) return hipSuccess;
     hipLaunchKernelGGL(clean_u0_f32_kernel, dim3(std::min(n_ids, 4096)), dim3(256), 0, s, net, props, prop_ids, n_ids,
                        u0_store, u0_stride);
@@ -446,6 +446,8 @@ hipError_t launch_clean_f32(const FNetDev &net, PropDev *props, const int32_t *p
     E.n = n_ids;
     E.u0f = u0_store;
     E.u0_stride = (int32_t)u0_stride;
+    E.lut = lut;
+    if (lut && net.kind != F32_LANE) return hipErrorInvalidValue;
     return launch_eval_f32(E, s);
 }
 

@@ -29,6 +29,8 @@ struct LaneParams {
     unsigned long long *slot_points;   // per slot: points of the domain visited
     volatile int32_t *stop_flag;
     volatile int32_t *abort_host;
+    int32_t literal;                   // the threshold literal instead of the label change
+    int32_t lit_v;                     // its reference value V
 };
 
 // The network has the compact layouts (see LaneNetDev).

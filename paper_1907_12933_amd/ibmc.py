@@ -50,7 +50,8 @@ class ibmc_check_opts(C.Structure):
     _fields_ = [("k_min", C.c_int32), ("k_max", C.c_int32), ("k_step", C.c_int32),
                 ("stop_at_first", C.c_int32), ("cex_capacity", C.c_int64),
                 ("near_tie_capacity", C.c_int64), ("near_tie_rel", C.c_float), ("records_on_device", C.c_int32),
-                ("resume_cursor", C.c_int64), ("chunk_budget", C.c_int64)]
+                ("resume_cursor", C.c_int64), ("chunk_budget", C.c_int64), ("property", C.c_int32),
+                ("sigmoid", C.c_int32), ("literal_v", C.c_double)]
 
 
 class ibmc_cex(C.Structure):
@@ -283,9 +284,17 @@ def ibmc_decode_point(n_pixels, n_deltas, k, rank):
 # check
 # ---------------------------------------------------------------------------
 
-def _opts(k_min, k_max, k_step, stop_at_first, cap, tie_cap, tie_rel, on_device=False, resume=0, budget=0):
+IBMC_PROPERTY_LABEL, IBMC_PROPERTY_LITERAL = 0, 1
+IBMC_SIGMOID_EXP, IBMC_SIGMOID_TABLE = 0, 1
+
+
+def _opts(k_min, k_max, k_step, stop_at_first, cap, tie_cap, tie_rel, on_device=False, resume=0, budget=0,
+          literal_v=None, table_sigmoid=False):
     return ibmc_check_opts(int(k_min), int(k_max), int(k_step), int(bool(stop_at_first)), int(cap), int(tie_cap),
-                           float(tie_rel), int(bool(on_device)), int(resume), int(budget))
+                           float(tie_rel), int(bool(on_device)), int(resume), int(budget),
+                           IBMC_PROPERTY_LITERAL if literal_v is not None else IBMC_PROPERTY_LABEL,
+                           IBMC_SIGMOID_TABLE if table_sigmoid else IBMC_SIGMOID_EXP,
+                           float(literal_v) if literal_v is not None else 0.0)
 
 
 def summary_dict(s: ibmc_check_summary):
@@ -318,16 +327,17 @@ def summary_dicts(outs, n):
 
 def ibmc_check_property(ctx, net, image, deltas, k_min=1, k_max=2, k_step=1, stop_at_first=False,
                         cex_capacity=1 << 20, near_tie_capacity=0, near_tie_rel=0.0, resume_cursor=0,
-                        chunk_budget=0, _entry="ibmc_check_property"):
+                        chunk_budget=0, literal_v=None, table_sigmoid=False, _entry="ibmc_check_property"):
     """Returns (summary dict, cex records, near-tie records) as numpy structured arrays.  With
     chunk_budget the call may stop early (status IBMC_W_PARTIAL, summary next_cursor >= 0);
-    resume_cursor continues such a call."""
+    resume_cursor continues such a call.  literal_v: check the threshold literal with this
+    reference value; table_sigmoid: float networks evaluate the table sigmoid."""
     image = np.ascontiguousarray(image, np.uint8)
     D = np.ascontiguousarray(deltas, np.int16)
     cex = np.empty(max(cex_capacity, 1), CEX_DTYPE)
     ties = np.empty(max(near_tie_capacity, 1), CEX_DTYPE)
     o = _opts(k_min, k_max, k_step, stop_at_first, cex_capacity, near_tie_capacity, near_tie_rel,
-              resume=resume_cursor, budget=chunk_budget)
+              resume=resume_cursor, budget=chunk_budget, literal_v=literal_v, table_sigmoid=table_sigmoid)
     s = ibmc_check_summary()
     rc = _ck(getattr(lib(), _entry)(ctx.handle, net.handle, _ptr(image, P_U8), image.size, _ptr(D, P_I16),
                                     D.size, C.byref(o), C.byref(s), cex.ctypes.data_as(P_CEX),
