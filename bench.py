@@ -301,6 +301,35 @@ def ball_leg(ctx, ibmc, inputs):
     return out
 
 
+def table_leg(ctx, ibmc, inputs):
+    """The paper's threat to validity (Sec. IV-D: its CUDA code took the
+    sigmoid from a table): the float version of the glyph35 net over the ten
+    glyphs, deltas -16..16, k <= 2, checked with the exponential sigmoid and
+    with the table sigmoid; the table's false counterexamples (records of the
+    table check that the exponential check neither records nor flags as a
+    near tie) and missed ones, and the two checks' times."""
+    g = inputs.workload_glyph35()
+    m = ibmc.Mlp(ctx, inputs.fnet_from_qnet(g.net))
+    P = [(m, x, g.deltas, 1, 2) for x in g.images]
+    out = {}
+    recs = {}
+    for name, tab in (("exp", False), ("table", True)):
+        kw = dict(cex_capacity=1 << 22, near_tie_capacity=1 << 20, table_sigmoid=tab)
+        ibmc.ibmc_check_batch(ctx, P, **kw)
+        t0 = time.perf_counter()
+        sums, cex, ties, _ = ibmc.ibmc_check_batch(ctx, P, **kw)
+        t = time.perf_counter() - t0
+        recs[name] = (set(zip(cex["prop"].tolist(), cex["k"].tolist(), cex["rank"].tolist())),
+                      set(zip(ties["prop"].tolist(), ties["k"].tolist(), ties["rank"].tolist())))
+        out[name] = dict(seconds=round(t, 6), points_per_s=sum(s["points_total"] for s in sums) / t,
+                         counterexamples=len(recs[name][0]), near_ties=len(recs[name][1]))
+    (e_rec, e_tie), (t_rec, t_tie) = recs["exp"], recs["table"]
+    out["table_false_counterexamples"] = len(t_rec - e_rec - e_tie)
+    out["table_missed_counterexamples"] = len(e_rec - t_rec - e_tie)
+    out["workload"] = "glyph35 net as float sigmoid (W/64, b/16384), 10 glyphs, deltas -16..16, k = 1..2"
+    return out
+
+
 def per_image(ibmc, ctx, net, w, sums):
     pots, labels = ibmc.ibmc_forward(ctx, net, w.images)
     z = np.sort(pots[:, -w.net.dims[-1]:].astype(np.int64), axis=1)
@@ -408,6 +437,8 @@ def main():
         out["glyph35"] = glyph_leg(ctx, ibmc, inputs)
         log("[bench] L2-ball leg")
         out["ball"] = ball_leg(ctx, ibmc, inputs)
+        log("[bench] table sigmoid leg")
+        out["table_sigmoid"] = table_leg(ctx, ibmc, inputs)
         log("[bench] proposer leg")
         out["ttfc"] = proposer_leg(ctx, ibmc, inputs, w, net, cex, args)
         log("[bench] coverage leg")

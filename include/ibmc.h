@@ -406,6 +406,26 @@ ibmc_status ibmc_coverage_from_potentials(ibmc_ctx *ctx, int32_t n_layers, const
                                           int32_t criterion, const ibmc_cov_params *params,
                                           ibmc_cov_summary *out, uint64_t *covered_bits);
 
+/* Coverage-guided test generation (tests chosen by the covers of Sec. III-B,
+ * which the paper leaves as future work in Sec. IV-C): every point of level
+ * k of the delta-set domain of `image` is a candidate test x'; each pair
+ * (image, x') covers a set of neuron pairs under `criterion` (as
+ * ibmc_coverage computes for one pair).  Tests are taken greedily: each
+ * time the candidate that covers the most pairs not covered by the tests
+ * taken so far (the lowest rank among equals), until no candidate adds a
+ * pair or max_tests are taken.  tests[i] (room for max_tests): the i-th
+ * test as a point (k, rank, its label; prop 0), gains[i] (nullable) the
+ * pairs it added; *n_tests the number taken; out: the coverage of all tests
+ * together; covered_bits (nullable): their covered pairs in ibmc_coverage's
+ * layout.  Integer networks whose non-input layers have at most 64 units,
+ * at most 4,096 neuron pairs and at most 2^26 candidates (else
+ * IBMC_E_UNIMPL). */
+ibmc_status ibmc_coverage_search(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *image, int32_t n_pixels,
+                                 const int16_t *delta_set, int32_t n_deltas, int32_t k, int32_t criterion,
+                                 const ibmc_cov_params *params, int32_t max_tests, ibmc_cex *tests,
+                                 int64_t *gains, int32_t *n_tests, ibmc_cov_summary *out,
+                                 uint64_t *covered_bits);
+
 /* ---- learned proposal network ------------------------------------------ */
 /* A two-layer scorer s = w2 . relu(W1 f + b1) + c over 32 features of a
  * candidate (pixel, delta), trained with a positive-weighted logistic loss

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "ibmc_host.h"
+#include "kernels_covsearch.h"
 
 namespace ibmc {
 
@@ -216,4 +217,133 @@ extern "C" ibmc_status ibmc_coverage_from_potentials(ibmc_ctx *ctx, int32_t n_la
         HIP_OK(hipStreamSynchronize(s));
     }
     return cov_finish(ctx, R, criterion, 1, P, out, covered_bits, 0.f);
+}
+
+// ---------------------------------------------------------------------------
+// coverage-guided test generation
+// ---------------------------------------------------------------------------
+
+extern "C" ibmc_status ibmc_coverage_search(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *image,
+                                            int32_t n_pixels, const int16_t *delta_set, int32_t n_deltas,
+                                            int32_t k, int32_t criterion, const ibmc_cov_params *params,
+                                            int32_t max_tests, ibmc_cex *tests, int64_t *gains, int32_t *n_tests,
+                                            ibmc_cov_summary *out, uint64_t *covered_bits) {
+    clear_error();
+    if (!ctx || !net || !image || !delta_set || !n_tests || !out || max_tests < 0 || (max_tests > 0 && !tests))
+        return fail(IBMC_E_INVALID, "bad argument");
+    if (net->act != IBMC_ACT_RELU_Q8) return fail(IBMC_E_UNIMPL, "coverage runs on integer networks");
+    if (n_pixels != net->dims[0]) return fail(IBMC_E_INVALID, "n_pixels %d != network input %d", n_pixels, net->dims[0]);
+    if (n_deltas < 1 || n_deltas > kMaxDeltas) return fail(IBMC_E_INVALID, "n_deltas %d", n_deltas);
+    if (criterion < 0 || criterion > 3) return fail(IBMC_E_INVALID, "criterion %d", criterion);
+    const int n = net->dims[0], L = net->L;
+    if (k < 1 || k > n || k > kMaxK) return fail(IBMC_E_INVALID, "k %d", k);
+    for (int l = 1; l <= L; ++l)
+        if (net->dims[l] > 64) return fail(IBMC_E_UNIMPL, "test generation needs non-input layers of <= 64 units");
+    const CovLayout lay = make_layout(L, net->dims.data() + 1);
+    const int words = (int)((lay.total_pairs + 63) / 64);
+    if (words > kCovSearchMaxWords || words < 1)
+        return fail(IBMC_E_UNIMPL, "%lld neuron pairs: test generation handles up to %d", (long long)lay.total_pairs,
+                    64 * kCovSearchMaxWords);
+    __int128 cands = binom_small(n, k);
+    for (int t = 0; t < k; ++t) cands *= n_deltas;
+    if (cands > ((__int128)1 << 26)) return fail(IBMC_E_UNIMPL, "level %d has more than 2^26 candidates", k);
+    const int64_t nc = (int64_t)cands;
+    CovParams cp;
+    double P;
+    IBMC_TRY(params_of(params, cp, P));
+    HIP_OK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    HIP_OK(hipEventRecord(ctx->ev0, s));
+    // the clean image's potentials
+    IBMC_TRY(ctx->cov_img.reserve((size_t)(n + 63) / 64 * 64 + (size_t)kMaxDeltas * 2));
+    uint8_t *dimg = ctx->cov_img.as<uint8_t>();
+    int16_t *ddel = reinterpret_cast<int16_t *>(dimg + ((n + 63) / 64) * 64);
+    HIP_OK(hipMemcpyAsync(dimg, image, (size_t)n, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(ddel, delta_set, (size_t)n_deltas * 2, hipMemcpyHostToDevice, s));
+    const size_t mask_bytes = (size_t)nc * words * 8;
+    // [potentials | masks | labels | covered (kCovSearchMaxWords words) | best key], 256-byte aligned parts
+    const size_t need = ((size_t)lay.U * 4 + 255) / 256 * 256 + (mask_bytes + 255) / 256 * 256 +
+                        ((size_t)nc * 4 + 255) / 256 * 256 + (size_t)(kCovSearchMaxWords + 1) * 8;
+    IBMC_TRY(ctx->cov_pots.reserve(need));
+    char *base = ctx->cov_pots.as<char>();
+    int32_t *pot0 = reinterpret_cast<int32_t *>(base);
+    unsigned long long *masks = reinterpret_cast<unsigned long long *>(base + (((size_t)lay.U * 4 + 255) / 256) * 256);
+    int32_t *labels = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(masks) + ((mask_bytes + 255) / 256) * 256);
+    unsigned long long *covered =
+        reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(labels) + (((size_t)nc * 4 + 255) / 256) * 256);
+    unsigned long long *key = covered + kCovSearchMaxWords;
+    HIP_OK(launch_fwd_pots_q8(net->qd, net->fx, dimg, 1, pot0, lay.U, nullptr, s));
+    CovCandParams cpar{};
+    cpar.net = net->qd;
+    cpar.image = dimg;
+    cpar.deltas = ddel;
+    cpar.m = n_deltas;
+    cpar.k = k;
+    cpar.pot0 = pot0;
+    cpar.rank0 = 0;
+    cpar.n_cand = nc;
+    cpar.crit = criterion;
+    cpar.words = words;
+    cpar.cp = cp;
+    cpar.masks = masks;
+    cpar.labels = labels;
+    HIP_OK(launch_cov_cand(cpar, s));
+    HIP_OK(launch_fill_u64(covered, kCovSearchMaxWords + 1, 0ull, s));
+    // greedy: the candidate adding the most uncovered pairs (lowest rank on
+    // ties), until none adds any or max_tests are taken
+    int32_t taken = 0;
+    std::vector<CexRec> picked;
+    std::vector<int64_t> gain_v;
+    while (taken < max_tests) {
+        HIP_OK(launch_fill_u64(key, 1, 0ull, s));
+        HIP_OK(launch_cov_gain(masks, nc, words, covered, key, s));
+        HIP_OK(launch_cov_take(masks, words, key, covered, s));
+        unsigned long long hk = 0;
+        HIP_OK(hipMemcpyAsync(&hk, key, 8, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        if (!hk) break;
+        const int64_t c = (int64_t)(((1ull << 40) - 1ull) - (hk & ((1ull << 40) - 1ull)));
+        int32_t lab = 0;
+        HIP_OK(hipMemcpy(&lab, labels + c, 4, hipMemcpyDeviceToHost));
+        picked.push_back(CexRec{0, k, c, lab, 0});
+        gain_v.push_back((int64_t)(hk >> 40));
+        ++taken;
+    }
+    std::vector<unsigned long long> cov(words);
+    HIP_OK(hipMemcpyAsync(cov.data(), covered, (size_t)words * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipEventRecord(ctx->ev1, s));
+    HIP_OK(hipStreamSynchronize(s));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    if (taken) memcpy(tests, picked.data(), picked.size() * sizeof(CexRec));
+    if (gains && taken) memcpy(gains, gain_v.data(), gain_v.size() * 8);
+    *n_tests = taken;
+    if (covered_bits) memcpy(covered_bits, cov.data(), (size_t)words * 8);
+    // summary: covered pairs, and the neurons (of the non-input layers) in any covered pair
+    int64_t pairs = 0, neurons = 0;
+    std::vector<char> hit(lay.U, 0);
+    int64_t boff = 0;
+    for (int l = 0; l + 1 < lay.nl; ++l) {
+        const int h0 = lay.width[l], h1 = lay.width[l + 1];
+        for (int i = 0; i < h0; ++i)
+            for (int j = 0; j < h1; ++j) {
+                const int64_t b = boff + (int64_t)i * h1 + j;
+                if ((cov[b >> 6] >> (b & 63)) & 1ull) {
+                    ++pairs;
+                    hit[lay.uoff[l] + i] = 1;
+                    hit[lay.uoff[l + 1] + j] = 1;
+                }
+            }
+        boff += (int64_t)h0 * h1;
+    }
+    for (char h : hit) neurons += h;
+    memset(out, 0, sizeof(*out));
+    out->covered_pairs = pairs;
+    out->total_pairs = lay.total_pairs;
+    out->covered_neurons = neurons;
+    out->total_neurons = lay.U;
+    out->fraction = lay.U ? (double)neurons / lay.U : 0.0;
+    out->literal = out->fraction >= P;
+    out->seconds = ms * 1e-3;
+    return IBMC_OK;
 }

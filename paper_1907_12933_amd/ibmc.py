@@ -146,6 +146,8 @@ SIGNATURES = {
     "ibmc_proposer_score_dev": (I32, [VP, VP, VP, VP, I32, I32, P_I16, I32, VP]),
     "ibmc_label_candidates": (I32, [VP, I32, I32, P_CEX, I64, P_F32]),
     "ibmc_count_candidates": (I32, [VP, I32, I32, P_CEX, I64, P_F32]),
+    "ibmc_coverage_search": (I32, [VP, VP, P_U8, I32, P_I16, I32, I32, I32, C.POINTER(ibmc_cov_params), I32,
+                                   P_CEX, P_I64, P_I32, C.POINTER(ibmc_cov_summary), P_U64]),
     "ibmc_ball_digits": (I32, [I64]),
     "ibmc_check_ball": (I32, [VP, VP, P_U8, I32, I64, P_OPTS, P_SUM, P_CEX]),
     "ibmc_check_ball_batch": (I32, [VP, C.POINTER(ibmc_ball_property), I32, P_OPTS, P_SUM, P_CEX]),
@@ -397,7 +399,7 @@ def _props(props, on_device):
 
 def ibmc_check_batch(ctx, props, stop_at_first=False, cex_capacity=1 << 20, near_tie_capacity=0,
                      near_tie_rel=0.0, on_device=False, cex_buf=None, records_on_device=False, resume_cursor=0,
-                     chunk_budget=0, allow_abort=False):
+                     chunk_budget=0, allow_abort=False, literal_v=None, table_sigmoid=False):
     """props: list of (net, image, deltas, k_min, k_max[, k_step]); with on_device the images are
     torch device tensors (uint8).  cex_buf: optional preallocated buffer of at least cex_capacity
     records, reused across calls: a CEX_DTYPE array, or with records_on_device a torch uint8
@@ -421,7 +423,7 @@ def ibmc_check_batch(ctx, props, stop_at_first=False, cex_capacity=1 << 20, near
         ties = np.empty(max(near_tie_capacity, 1), CEX_DTYPE)
         cex_ptr, tie_ptr = cex_buf.ctypes.data_as(P_CEX), ties.ctypes.data_as(P_CEX)
     o = _opts(0, 0, 1, stop_at_first, cex_capacity, near_tie_capacity, near_tie_rel, records_on_device,
-              resume=resume_cursor, budget=chunk_budget)
+              resume=resume_cursor, budget=chunk_budget, literal_v=literal_v, table_sigmoid=table_sigmoid)
     fn = lib().ibmc_check_batch_dev if on_device else lib().ibmc_check_batch
     rc = fn(ctx.handle, arr, n, C.byref(o), outs, cex_ptr, tie_ptr)
     if not (allow_abort and rc == IBMC_E_ABORTED):
@@ -433,6 +435,30 @@ def ibmc_check_batch(ctx, props, stop_at_first=False, cex_capacity=1 << 20, near
     if records_on_device:
         return sums, cex_buf[:tot * rsz], tie_dev[:ttot * rsz], rc
     return sums, cex_buf[:tot], ties[:ttot].copy(), rc
+
+
+def ibmc_coverage_search(ctx, net, image, deltas, k, criterion, max_tests=64, **params):
+    """Greedy coverage-guided tests among the points of level k.  Returns
+    (tests: cex records (k, rank, label), gains per test, coverage dict with
+    'bits')."""
+    image = np.ascontiguousarray(image, np.uint8)
+    D = np.ascontiguousarray(deltas, np.int16)
+    crit = CRITERIA[criterion] if isinstance(criterion, str) else int(criterion)
+    tests = np.empty(max(max_tests, 1), CEX_DTYPE)
+    gains = np.zeros(max(max_tests, 1), np.int64)
+    nt = I32()
+    out = ibmc_cov_summary()
+    widths = net.dims[1:]
+    tp = sum(widths[i] * widths[i + 1] for i in range(len(widths) - 1))
+    bits = np.zeros(max((tp + 63) // 64, 1), np.uint64)
+    p = _covp(**params)
+    _ck(lib().ibmc_coverage_search(ctx.handle, net.handle, _ptr(image, P_U8), image.size, _ptr(D, P_I16), D.size,
+                                   int(k), crit, C.byref(p), int(max_tests), tests.ctypes.data_as(P_CEX),
+                                   _ptr(gains, P_I64), C.byref(nt), C.byref(out), _ptr(bits, P_U64)))
+    n = nt.value
+    d = cov_dict(out)
+    d["bits"] = bits[:(tp + 63) // 64]
+    return tests[:n].copy(), gains[:n].copy(), d
 
 
 def ibmc_ball_digits(radius_sq):
