@@ -57,6 +57,7 @@
 #define ORC_E_INVALID (-1)
 #define ORC_E_RANGE (-2)
 #define ORC_E_OOM (-3)
+#define ORC_TRAIN_MAX_LAYERS 16
 
 /* ------------------------------------------------------------------------ */
 /* network shapes (the oracle's own flat layout)                            */
@@ -667,6 +668,75 @@ int orc_q8_check_literal(int L, const int32_t *dims, const int8_t *W, const int3
     return check_impl(&nr, x, D, m, -1, k_min, k_max, k_step, stop_at_first, cap, points, cex_count,
                       tie_count, clean_label, first_unsafe_k, out_k, out_rank, out_label, n_out,
                       0, NULL, NULL, NULL, NULL, nthreads);
+}
+
+/* Training loss of the float network (the networks are trained on labelled
+ * examples by backpropagation, Sec. II-A): the mean over the n images of the
+ * cross-entropy of the softmax of the logits against each image's label,
+ * and its gradient with respect to theta = for each layer l in turn, W_l
+ * row-major [dims[l]][dims[l-1]] then b_l [dims[l]].  Sigmoid hidden
+ * layers, linear logits, a0 = x / 256, all in double.  Plain chain rule:
+ * dL/du_L = (softmax - onehot) / n; dL/dW_l = dL/du_l a_{l-1}^T;
+ * dL/db_l = dL/du_l; dL/du_{l-1} = (W_l^T dL/du_l) * a (1 - a). */
+int orc_f64_loss_grad(int L, const int32_t *dims, const double *W, const double *b, const uint8_t *images,
+                      const int32_t *labels, int64_t n_img, double *grad, double *loss) {
+    if (L < 1 || L > ORC_TRAIN_MAX_LAYERS || !dims || !W || !b || !images || !labels || !grad || !loss || n_img < 1)
+        return ORC_E_INVALID;
+    /* per layer: offsets of its activations, its W and b, its theta block */
+    int64_t a_off[ORC_TRAIN_MAX_LAYERS + 1], w_off[ORC_TRAIN_MAX_LAYERS + 1], b_off[ORC_TRAIN_MAX_LAYERS + 1];
+    int64_t t_off[ORC_TRAIN_MAX_LAYERS + 1];
+    int64_t U = dims[0], P = 0, nw = 0, nb = 0;
+    a_off[0] = 0;
+    for (int l = 1; l <= L; ++l) {
+        a_off[l] = U; w_off[l] = nw; b_off[l] = nb; t_off[l] = P;
+        U += dims[l]; nw += (int64_t)dims[l] * dims[l - 1]; nb += dims[l];
+        P += (int64_t)dims[l] * dims[l - 1] + dims[l];
+    }
+    const int n = dims[0], nc = dims[L];
+    double *act = malloc(sizeof(double) * U);   /* a0 | a1 | ... | aL (aL = logits) */
+    double *del = malloc(sizeof(double) * U);   /* dL/du per unit, same layout */
+    if (!act || !del) { free(act); free(del); return ORC_E_OOM; }
+    for (int64_t t = 0; t < P; ++t) grad[t] = 0.0;
+    double total = 0.0;
+    int rc = ORC_OK;
+    for (int64_t s = 0; s < n_img && rc == ORC_OK; ++s) {
+        const int y = labels[s];
+        if (y < 0 || y >= nc) { rc = ORC_E_INVALID; break; }
+        for (int i = 0; i < n; ++i) act[i] = images[s * n + i] / 256.0;
+        for (int l = 1; l <= L; ++l) {
+            const int nin = dims[l - 1], nout = dims[l];
+            for (int j = 0; j < nout; ++j) {
+                double u = b[b_off[l] + j];
+                for (int i = 0; i < nin; ++i) u += W[w_off[l] + (int64_t)j * nin + i] * act[a_off[l - 1] + i];
+                act[a_off[l] + j] = (l < L) ? 1.0 / (1.0 + exp(-u)) : u;
+            }
+        }
+        const double *z = act + a_off[L];
+        double zmax = z[0];
+        for (int c = 1; c < nc; ++c) if (z[c] > zmax) zmax = z[c];
+        double sum = 0.0;
+        for (int c = 0; c < nc; ++c) sum += exp(z[c] - zmax);
+        total += log(sum) - (z[y] - zmax);
+        for (int c = 0; c < nc; ++c) del[a_off[L] + c] = (exp(z[c] - zmax) / sum - (c == y ? 1.0 : 0.0)) / n_img;
+        for (int l = L; l >= 1; --l) {
+            const int nin = dims[l - 1], nout = dims[l];
+            for (int j = 0; j < nout; ++j) {
+                const double dj = del[a_off[l] + j];
+                for (int i = 0; i < nin; ++i) grad[t_off[l] + (int64_t)j * nin + i] += dj * act[a_off[l - 1] + i];
+                grad[t_off[l] + (int64_t)nout * nin + j] += dj;
+            }
+            if (l == 1) break;
+            for (int i = 0; i < nin; ++i) {
+                double da = 0.0;
+                for (int j = 0; j < nout; ++j) da += W[w_off[l] + (int64_t)j * nin + i] * del[a_off[l] + j];
+                const double a = act[a_off[l - 1] + i];
+                del[a_off[l - 1] + i] = da * a * (1.0 - a);
+            }
+        }
+    }
+    if (rc == ORC_OK) *loss = total / n_img;
+    free(act); free(del);
+    return rc;
 }
 
 /* Replay / sample: decode each (k, rank), build the perturbed image and run

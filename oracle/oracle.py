@@ -56,6 +56,7 @@ def lib():
         L.orc_q8_check_literal.argtypes = [C.c_int, I32P, I8P, I32P, I32P, U8P, I16P, C.c_int, C.c_int64,
                                            C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64,
                                            I64P, I64P, I64P, I32P, I32P, I32P, I64P, I32P, I64P, C.c_int]
+        L.orc_f64_loss_grad.argtypes = [C.c_int, I32P, F64P, F64P, U8P, I32P, C.c_int64, F64P, F64P]
         L.orc_f64_check.argtypes = [C.c_int, I32P, F64P, F64P, U8P, I16P, C.c_int,
                                     C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, C.c_double,
                                     I64P, I64P, I64P, I32P, I32P, I32P, I64P, I32P, I64P,
@@ -198,6 +199,20 @@ def q8_ball_check(net, x, r2, k_min=1, k_max=2, k_step=1, stop_at_first=False, c
     return dict(levels=list(range(k_min, k_max + 1, k_step))[:lev], points=pts[:lev], cex=cx[:lev],
                 ties=ti[:lev], clean_label=int(cl[0]), first_unsafe_k=int(fu[0]), cex_total=n,
                 cex_k=ok[:w].copy(), cex_rank=orr[:w].copy(), cex_label=ol[:w].copy(), m=2 * ball_digits(r2))
+
+
+def f64_loss_grad(net, images, labels):
+    """Mean softmax cross-entropy of the float network on labelled images and
+    its gradient over theta (per layer W row-major, then b)."""
+    dims, W, b = _flat_f64(net)
+    images = np.ascontiguousarray(images, np.uint8).reshape(-1, net.dims[0])
+    labels = np.ascontiguousarray(labels, np.int32)
+    P = sum(net.dims[l] * net.dims[l - 1] + net.dims[l] for l in range(1, len(net.dims)))
+    g = np.zeros(P, np.float64)
+    loss = np.zeros(1, np.float64)
+    _ck(lib().orc_f64_loss_grad(len(dims) - 1, _p(dims, I32P), _p(W, F64P), _p(b, F64P), _p(images, U8P),
+                                _p(labels, I32P), len(labels), _p(g, F64P), _p(loss, F64P)))
+    return float(loss[0]), g
 
 
 def lut_sigmoid(u):
