@@ -426,6 +426,48 @@ ibmc_status ibmc_coverage_search(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8
                                  int64_t *gains, int32_t *n_tests, ibmc_cov_summary *out,
                                  uint64_t *covered_bits);
 
+/* ---- training of the float networks ------------------------------------ */
+/* The networks the checks run on are trained on labelled examples (Sec.
+ * II-A); the verifier's counterexamples, each labelled with its clean
+ * image's label, can be added to that training set (Sec. VI) and the
+ * retrained network checked again.  Float (IBMC_ACT_SIGMOID_F32) networks
+ * only (else IBMC_E_UNIMPL).  The loss of a labelled set is the mean over its
+ * images of the cross-entropy of the softmax of the logits against the
+ * label, with a_0 = x / 256, sigmoid hidden layers and linear logits as in
+ * the checks.  theta, the flat parameter vector: for each layer l in turn,
+ * W_l row-major [dims[l]][dims[l-1]] then b_l [dims[l]] (sum over layers of
+ * dims[l] * (dims[l-1] + 1) floats).  images: host uint8 [n][dims[0]];
+ * labels: host int32 [n], each in [0, classes) (else IBMC_E_INVALID). */
+
+/* Loss (nullable, host double) and gradient (nullable, host float
+ * [n_params] in theta's layout) of the net on n >= 1 labelled images. */
+ibmc_status ibmc_mlp_loss_grad(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *images,
+                               const int32_t *labels, int64_t n, float *grad, double *loss);
+
+/* Mini-batch Adam (Kingma and Ba): each epoch visits the n images in an
+ * order, in consecutive batches of `batch` (the last one smaller); each
+ * batch takes one Adam step on its mean loss.  order (nullable, host int64
+ * [epochs][n], each entry in [0, n)): the images of epoch e in order; NULL:
+ * a Fisher-Yates shuffle per epoch from `seed` (splitmix64).  beta1, beta2,
+ * eps of 0 take 0.9, 0.999, 1e-8. */
+typedef struct {
+    int32_t epochs;                       /* >= 1 */
+    int32_t batch;                        /* >= 1 */
+    float lr, beta1, beta2, eps;
+    uint64_t seed;
+    const int64_t *order;
+} ibmc_fit_opts;
+
+/* Train a copy of `net` from its parameters on n labelled images; *out
+ * receives the trained network (a new handle, freed with ibmc_free_mlp;
+ * `net` is left as it was), theta_out (nullable, host float [n_params]) its
+ * parameters, epoch_loss (nullable, host double [epochs]) the mean loss of
+ * each epoch's batches before their steps.  IBMC_E_RANGE if a parameter
+ * becomes non-finite. */
+ibmc_status ibmc_fit_mlp(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8_t *images,
+                         const int32_t *labels, int64_t n, const ibmc_fit_opts *opts,
+                         ibmc_mlp **out, float *theta_out, double *epoch_loss);
+
 /* ---- learned proposal network ------------------------------------------ */
 /* A two-layer scorer s = w2 . relu(W1 f + b1) + c over 32 features of a
  * candidate (pixel, delta), trained with a positive-weighted logistic loss

@@ -215,6 +215,54 @@ def f64_loss_grad(net, images, labels):
     return float(loss[0]), g
 
 
+def f64_fit(net, images, labels, order, batch, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Mini-batch Adam (Kingma and Ba, Algorithm 1) on the mean loss of each
+    batch: epoch e visits images order[e] in consecutive batches of `batch`.
+    Returns (W list, b list, mean loss of each epoch's batches before their
+    steps), all in double."""
+    dims = list(net.dims)
+    W = [np.asarray(w, np.float64).copy() for w in net.W]
+    b = [np.asarray(x, np.float64).copy() for x in net.b]
+    theta = np.concatenate([np.concatenate([w.reshape(-1), x]) for w, x in zip(W, b)])
+    images = np.ascontiguousarray(images, np.uint8).reshape(-1, dims[0])
+    labels = np.asarray(labels, np.int32)
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    t = 0
+    losses = []
+
+    def unflat(th):
+        Ws, bs, o = [], [], 0
+        for l in range(1, len(dims)):
+            nw = dims[l] * dims[l - 1]
+            Ws.append(th[o:o + nw].reshape(dims[l], dims[l - 1]))
+            o += nw
+            bs.append(th[o:o + dims[l]])
+            o += dims[l]
+        return Ws, bs
+
+    class _Net:
+        pass
+    for ord_e in np.asarray(order, np.int64):
+        total = 0.0
+        for b0 in range(0, len(ord_e), batch):
+            idx = ord_e[b0:b0 + batch]
+            cur = _Net()
+            cur.dims = dims
+            cur.W, cur.b = unflat(theta)
+            loss, g = f64_loss_grad(cur, images[idx], labels[idx])
+            total += loss * len(idx)
+            t += 1
+            m = beta1 * m + (1 - beta1) * g
+            v = beta2 * v + (1 - beta2) * g * g
+            mhat = m / (1 - beta1 ** t)
+            vhat = v / (1 - beta2 ** t)
+            theta = theta - lr * mhat / (np.sqrt(vhat) + eps)
+        losses.append(total / len(ord_e))
+    Ws, bs = unflat(theta)
+    return [w.copy() for w in Ws], [x.copy() for x in bs], np.array(losses)
+
+
 def lut_sigmoid(u):
     """The table sigmoid (knots -8 + i/16, FP32 values, linear between)."""
     return float(lib().orc_lut_sigmoid(float(u)))

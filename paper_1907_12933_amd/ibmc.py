@@ -98,6 +98,11 @@ class ibmc_train_opts(C.Structure):
                 ("beta2", C.c_float), ("eps", C.c_float), ("pos_weight", C.c_float), ("seed", C.c_uint64)]
 
 
+class ibmc_fit_opts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64), ("order", C.POINTER(C.c_int64))]
+
+
 VP = C.c_void_p
 I32 = C.c_int32
 I64 = C.c_int64
@@ -148,6 +153,9 @@ SIGNATURES = {
     "ibmc_count_candidates": (I32, [VP, I32, I32, P_CEX, I64, P_F32]),
     "ibmc_coverage_search": (I32, [VP, VP, P_U8, I32, P_I16, I32, I32, I32, C.POINTER(ibmc_cov_params), I32,
                                    P_CEX, P_I64, P_I32, C.POINTER(ibmc_cov_summary), P_U64]),
+    "ibmc_mlp_loss_grad": (I32, [VP, VP, P_U8, P_I32, I64, P_F32, C.POINTER(C.c_double)]),
+    "ibmc_fit_mlp": (I32, [VP, VP, P_U8, P_I32, I64, C.POINTER(ibmc_fit_opts), C.POINTER(VP), P_F32,
+                           C.POINTER(C.c_double)]),
     "ibmc_ball_digits": (I32, [I64]),
     "ibmc_check_ball": (I32, [VP, VP, P_U8, I32, I64, P_OPTS, P_SUM, P_CEX]),
     "ibmc_check_ball_batch": (I32, [VP, C.POINTER(ibmc_ball_property), I32, P_OPTS, P_SUM, P_CEX]),
@@ -254,6 +262,22 @@ class Mlp:
         h = VP()
         _ck(lib().ibmc_load_mlp(ctx.handle, C.byref(d), C.byref(h)))
         self.handle = h
+
+    @classmethod
+    def _from_handle(cls, ctx, handle, dims, W, b):
+        """A float network the library created (e.g. by training)."""
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        self.dims = [int(d) for d in dims]
+        self.act = IBMC_ACT_SIGMOID_F32
+        self._W, self._b = W, b
+        self.handle = handle
+        return self
+
+    @property
+    def params(self):
+        """(W list, b list) as loaded (host copies)."""
+        return self._W, self._b
 
     def close(self):
         if self.handle:
@@ -459,6 +483,65 @@ def ibmc_coverage_search(ctx, net, image, deltas, k, criterion, max_tests=64, **
     d = cov_dict(out)
     d["bits"] = bits[:(tp + 63) // 64]
     return tests[:n].copy(), gains[:n].copy(), d
+
+
+# ---------------------------------------------------------------------------
+# training of the float networks
+# ---------------------------------------------------------------------------
+
+def n_params(dims):
+    return sum(int(dims[l]) * (int(dims[l - 1]) + 1) for l in range(1, len(dims)))
+
+
+def split_theta(dims, theta):
+    """Flat theta (per layer W row-major, then b) -> (W list, b list)."""
+    W, b, t = [], [], 0
+    for l in range(1, len(dims)):
+        nw = int(dims[l]) * int(dims[l - 1])
+        W.append(np.ascontiguousarray(theta[t:t + nw].reshape(dims[l], dims[l - 1]), np.float32))
+        t += nw
+        b.append(np.ascontiguousarray(theta[t:t + dims[l]], np.float32))
+        t += int(dims[l])
+    return W, b
+
+
+def ibmc_mlp_loss_grad(ctx, net, images, labels):
+    """(mean softmax cross-entropy, gradient over flat theta) on labelled images."""
+    images = np.ascontiguousarray(images, np.uint8).reshape(-1, net.dims[0])
+    labels = np.ascontiguousarray(labels, np.int32)
+    if len(labels) != len(images):
+        raise ValueError("one label per image")
+    g = np.zeros(n_params(net.dims), np.float32)
+    loss = C.c_double()
+    _ck(lib().ibmc_mlp_loss_grad(ctx.handle, net.handle, _ptr(images, P_U8), _ptr(labels, P_I32), len(labels),
+                                 _ptr(g, P_F32), C.byref(loss)))
+    return loss.value, g
+
+
+def ibmc_fit_mlp(ctx, net, images, labels, epochs=10, batch=64, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                 seed=0, order=None):
+    """Train a copy of a float network with mini-batch Adam.  order (optional,
+    int64 [epochs][n]): the images of each epoch in order.  Returns (the
+    trained Mlp, the mean loss of each epoch)."""
+    images = np.ascontiguousarray(images, np.uint8).reshape(-1, net.dims[0])
+    labels = np.ascontiguousarray(labels, np.int32)
+    if len(labels) != len(images):
+        raise ValueError("one label per image")
+    n = len(labels)
+    ordp = None
+    if order is not None:
+        order = np.ascontiguousarray(order, np.int64)
+        if order.shape != (epochs, n):
+            raise ValueError("order must be [epochs][n]")
+        ordp = _ptr(order, P_I64)
+    o = ibmc_fit_opts(int(epochs), int(batch), float(lr), float(beta1), float(beta2), float(eps), int(seed), ordp)
+    theta = np.zeros(n_params(net.dims), np.float32)
+    losses = np.zeros(max(int(epochs), 1), np.float64)
+    h = VP()
+    _ck(lib().ibmc_fit_mlp(ctx.handle, net.handle, _ptr(images, P_U8), _ptr(labels, P_I32), n, C.byref(o),
+                           C.byref(h), _ptr(theta, P_F32), losses.ctypes.data_as(C.POINTER(C.c_double))))
+    W, b = split_theta(net.dims, theta)
+    return Mlp._from_handle(ctx, h, net.dims, W, b), losses[:int(epochs)].copy()
 
 
 def ibmc_ball_digits(radius_sq):

@@ -90,6 +90,35 @@ def glyph_images(g: np.random.Generator, count: int, rows: int, cols: int, p_on=
     return np.where(on, 255, 0).astype(np.uint8)
 
 
+def labelled_glyphs(g: np.random.Generator, classes: int, count: int, rows: int = 7, cols: int = 5,
+                    p_on=0.4, p_flip=0.05, proto_flip=None):
+    """A labelled glyph set: `classes` random binary prototypes (as
+    glyph_images; with proto_flip, one such base glyph with each pixel
+    flipped with probability proto_flip per class, so that classes lie a
+    few pixels apart); each sample copies a uniformly drawn prototype, flips
+    each pixel with probability p_flip and takes the prototype's index as
+    label.  Returns (prototypes [classes][rows*cols], images
+    [count][rows*cols], labels int32 [count])."""
+    if proto_flip is None:
+        proto = glyph_images(g, classes, rows, cols, p_on)
+    else:
+        base = glyph_images(g, 1, rows, cols, p_on)[0]
+        pf = g.random((classes, rows * cols)) < proto_flip
+        proto = np.where(pf, 255 - base[None, :], base[None, :]).astype(np.uint8)
+    labels = g.integers(0, classes - 1, size=count, endpoint=True).astype(np.int32)
+    flip = g.random((count, rows * cols)) < p_flip
+    imgs = np.where(flip, 255 - proto[labels], proto[labels]).astype(np.uint8)
+    return proto, imgs, labels
+
+
+def random_fnet(g: np.random.Generator, dims, scale=1.0) -> FNet:
+    """Float32 network with weights normal(0, scale / sqrt(fan_in)) and zero biases."""
+    W = [(g.standard_normal((dims[l + 1], dims[l])) * (scale / np.sqrt(dims[l]))).astype(np.float32)
+         for l in range(len(dims) - 1)]
+    b = [np.zeros(dims[l + 1], np.float32) for l in range(len(dims) - 1)]
+    return FNet(list(dims), W, b)
+
+
 def blob_images(g: np.random.Generator, count: int, side: int = 28, noise_std=20.0) -> np.ndarray:
     """28x28-shaped images: 1-3 Gaussian blobs plus uniform noise of the given std.
 

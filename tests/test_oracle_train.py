@@ -11,7 +11,10 @@ verifier's counterexamples to the training set, Sec. VI):
   - a hidden layer with zero first-layer weights feeds the constant
     sigmoid(b_1) (scipy's expit) to the logits;
   - invariants: shifting every last-layer bias by one constant leaves the
-    loss unchanged, and the last-layer bias gradient sums to zero."""
+    loss unchanged, and the last-layer bias gradient sums to zero;
+  - Adam: its first step moves every parameter with a nonzero gradient by
+    lr against the gradient's sign (bias-corrected m / sqrt(v) = g / |g|),
+    and training on a separable set drives the loss down."""
 import numpy as np
 import pytest
 from scipy.special import expit, softmax
@@ -120,3 +123,25 @@ def test_invariants(orc):
     assert orc.f64_loss_grad(shifted, imgs, labs)[0] == pytest.approx(loss, rel=1e-12)
     with pytest.raises(Exception):
         orc.f64_loss_grad(net, imgs, np.array([0, 1, 2, 3, 4, 5, 0], np.int32))
+
+
+def test_adam_first_step_and_descent(orc):
+    g = I.rng(9)
+    dims = [10, 6, 3]
+    net = f64net(dims, g)
+    imgs = g.integers(0, 256, size=(12, 10)).astype(np.uint8)
+    labs = g.integers(0, 3, size=12).astype(np.int32)
+    _, grad = orc.f64_loss_grad(net, imgs, labs)
+    W, b, losses = orc.f64_fit(net, imgs, labs, [np.arange(12)], batch=12, lr=1e-3, eps=1e-12)
+    step = flat(I.FNet(dims, W, b)) - flat(net)
+    nz = np.abs(grad) > 1e-9
+    assert np.allclose(step[nz], -1e-3 * np.sign(grad[nz]), rtol=1e-6, atol=0)
+    assert losses[0] == pytest.approx(orc.f64_loss_grad(net, imgs, labs)[0], rel=1e-12)
+    # a linearly separable set: two prototypes, labels by prototype
+    proto = g.integers(0, 2, size=(2, 10)) * 255
+    lab2 = g.integers(0, 2, size=40).astype(np.int32)
+    img2 = proto[lab2].astype(np.uint8)
+    net2 = f64net([10, 6, 2], g, scale=0.1)
+    order = np.stack([g.permutation(40) for _ in range(30)])
+    W2, b2, l2 = orc.f64_fit(net2, img2, lab2, order, batch=8, lr=3e-2)
+    assert l2[-1] < 0.1 * l2[0]
