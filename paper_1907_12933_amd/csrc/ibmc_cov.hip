@@ -151,11 +151,16 @@ static ibmc_status coverage_impl(ibmc_ctx *ctx, const ibmc_mlp *net, const uint8
             d1 = ctx->cov_img.as<uint8_t>();
             d2 = d1 + (size_t)n_pairs * n;
         }
-        IBMC_TRY(ctx->cov_pots.reserve((size_t)2 * n_pairs * lay.U * 4));
-        int32_t *p1 = ctx->cov_pots.as<int32_t>(), *p2 = p1 + (size_t)n_pairs * lay.U;
-        HIP_OK(launch_fwd_pots_q8(net->qd, net->fx, d1, n_pairs, p1, lay.U, nullptr, s));
-        HIP_OK(launch_fwd_pots_q8(net->qd, net->fx, d2, n_pairs, p2, lay.U, nullptr, s));
-        HIP_OK(launch_cov_pred_i32(p1, p2, n_pairs, lay, cp, R.bits, s));
+        CovPairParams cpp{};
+        cpp.net = net->qd;
+        cpp.fx = net->fx;
+        cpp.lay = lay;
+        cpp.cp = cp;
+        cpp.bits = R.bits;
+        cpp.x1 = d1;
+        cpp.x2 = d2;
+        cpp.n_pairs = n_pairs;
+        HIP_OK(launch_cov_pair(cpp, ctx->n_cu, s));
     }
     if (!on_device) HIP_OK(hipStreamSynchronize(s));  // host images may be released after return
     return cov_finish(ctx, R, first_crit, n_crit, P, outs, covered_bits, 0.f);

@@ -48,10 +48,27 @@ struct CovSums {
     int64_t colmask_stride;
 };
 
+// One pass over input pairs: forward of both images on int8 MFMA (x2's first
+// layer as the rank-r update of x1's), the per-neuron tests and the covered
+// rows, with no potentials in memory.  x1 / x2: device [n_pairs][dims[0]].
+struct CovPairParams {
+    QNetDev net;
+    FwdExtra fx;
+    CovLayout lay;
+    CovParams cp;
+    CovBits bits;
+    const uint8_t *x1, *x2;
+    int64_t n_pairs;
+    // LDS plan (cov_pair_plan): activation row stride, per-pair nibble
+    // offsets of each layer, byte offsets of the regions
+    int act_stride, nib_stride, off_nib, off_dist, off_diff;
+    int nib_off[kMaxLayers + 2];
+};
+
+hipError_t launch_cov_pair(CovPairParams P, int n_cu, hipStream_t s);
+
 hipError_t launch_fwd_pots_q8(const QNetDev &net, const FwdExtra &fx, const uint8_t *images, int64_t n_images,
                               int32_t *pots, int64_t pot_stride, int32_t *labels, hipStream_t s);
-hipError_t launch_cov_pred_i32(const int32_t *p1, const int32_t *p2, int64_t n_pairs, const CovLayout &lay,
-                               const CovParams &cp, const CovBits &bits, hipStream_t s);
 hipError_t launch_cov_pred_i64(const int64_t *p1, const int64_t *p2, int64_t n_pairs, const CovLayout &lay,
                                const CovParams &cp, const CovBits &bits, hipStream_t s);
 hipError_t launch_cov_summary(const CovLayout &lay, const CovBits &bits, const CovSums &sums, hipStream_t s);

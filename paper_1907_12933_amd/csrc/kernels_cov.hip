@@ -1,10 +1,13 @@
-// Coverage kernels (the SS / DS / SV / DV neuron-pair covers):
+// Coverage kernels (the SS / DS / SV / DV neuron-pair covers; pairs of
+// images go through the one-pass kernel of kernels_covpair.hip):
 //  1. fwd_pots_q8_kernel: every layer's exact potentials of a batch of
 //     images on int8 MFMA (natural K order; activations staged in LDS, the
-//     output tiles split over a workgroup's waves);
-//  2. cov_pred_kernel: per input pair, sign / value change masks of every
-//     layer as wavefront ballots, sign-change counts by popcount, the layer
-//     distance, then the covered rows OR-ed into device bitmasks;
+//     output tiles split over a workgroup's waves), for the forward entry
+//     point and the clean image of test generation;
+//  2. cov_pred_kernel: per pair of given potentials (int64, from the host),
+//     sign / value change masks of every layer as wavefront ballots,
+//     sign-change counts by popcount, the layer distance, then the covered
+//     rows OR-ed into device bitmasks;
 //  3. cov_sum_kernel / cov_expand_kernel: covered pairs, covered neurons and
 //     the caller's packed bit layout.
 #include "kernels_cov.h"
@@ -320,14 +323,6 @@ hipError_t launch_fwd_pots_q8(const QNetDev &net, const FwdExtra &fx, const uint
     const int grid = (int)std::min<int64_t>(tiles, 8192);
     hipLaunchKernelGGL(fwd_pots_q8_kernel, dim3(grid), dim3(64 * kFwdWaves), 0, s, net, fx, images, n_images, pots,
                        pot_stride, labels);
-    return hipGetLastError();
-}
-
-hipError_t launch_cov_pred_i32(const int32_t *p1, const int32_t *p2, int64_t n_pairs, const CovLayout &lay,
-                               const CovParams &cp, const CovBits &bits, hipStream_t s) {
-    if (n_pairs <= 0) return hipSuccess;
-    const int grid = (int)std::min<int64_t>(n_pairs, 16384);
-    hipLaunchKernelGGL(cov_pred_kernel<int32_t>, dim3(grid), dim3(64), 0, s, p1, p2, n_pairs, lay, cp, bits);
     return hipGetLastError();
 }
 

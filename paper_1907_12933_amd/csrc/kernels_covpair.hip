@@ -1,0 +1,313 @@
+// Pair coverage in one pass (the SS / DS / SV / DV covers of Sec. III-B,
+// Eqs. (3)-(6), over input pairs (x1, x2)): a workgroup takes 16 pairs,
+// runs both images of every pair through the network on int8 MFMA and tests
+// every neuron of every layer on the fly, so that no potential ever goes to
+// memory.
+//
+// Columns of the MFMA B operand: N-tile 0 holds x1 of the 16 pairs, N-tile 1
+// x2 of the same pairs, so the accumulators of a pair's
+// two images for the same four neurons sit in the same lane.  x2's first
+// layer is the rank-r update of x1's (Eq. (1)): u1(x2) = u1(x1) + sum over
+// the r pixels where x2 differs of (x2_p - x1_p) W1[:, p], r <= kPairRank
+// (else the whole tile runs x2's first layer on the matrix cores too).
+//
+// Every wave (eight per workgroup) owns up to eight 16-row M-tiles of each
+// layer and keeps their accumulators for both N-tiles in registers (each
+// weight tile loaded once feeds two MFMAs, each activation fragment read
+// from LDS feeds up to eight).  (32 pairs per workgroup, four N-tiles, made
+// the compiler spill at 256 registers.)  After a layer: the sign / value changes of every neuron as 4-bit
+// nibbles per pair in LDS, the squared distance as per-wave partial sums,
+// and (hidden layers) the requantised activations written back over the
+// layer's inputs.  At the end every pair's counts, first sign change and
+// distance decide its covered rows, which are OR-ed into the device masks
+// exactly as the potential-based predicate kernel does.
+#include <algorithm>
+
+#include "kernels_cov.h"
+
+namespace ibmc {
+
+constexpr int kPairWaves = 8;
+constexpr int kPairRank = 16;
+constexpr int kPairMaxMt = 8;   // M-tiles per wave (widths <= 1024)
+
+__device__ __forceinline__ unsigned long long sat_add(unsigned long long a, unsigned long long b) {
+    const unsigned long long s = a + b;
+    return s < a ? ~0ull : s;
+}
+
+__device__ __forceinline__ int pair_requant_byte(int acc_minus_off, int s) {
+    const int lim = 64 << s;
+    const int v = min(max(acc_minus_off, -lim), lim - 1);
+    return (v >> s) & 0xff;
+}
+
+template <int NX>
+__global__ void __launch_bounds__(64 * kPairWaves) cov_pair_kernel(CovPairParams P) {
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    constexpr int NC = 2 * NX;          // N-tiles
+    constexpr int NP = 16 * NX;         // pairs per tile
+    const QNetDev &net = P.net;
+    const FwdExtra &fx = P.fx;
+    const CovLayout &lay = P.lay;
+    const int L = net.L, n = net.dims[0];
+    const int RS = P.act_stride;        // bytes per activation row
+    int8_t *act = reinterpret_cast<int8_t *>(smem);                       // [NC * 16][RS]
+    uint8_t *nib = reinterpret_cast<uint8_t *>(smem + P.off_nib);         // [NP][nib_stride]
+    unsigned long long *dist = reinterpret_cast<unsigned long long *>(smem + P.off_dist);  // [L][NP][waves]
+    int *dlist = reinterpret_cast<int *>(smem + P.off_diff);              // [NP][kPairRank]
+    int *dcount = dlist + NP * kPairRank;                                 // [NP]
+    int *flags = dcount + NP;                                             // [1]: dense
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j16 = lane & 15, g = lane >> 4;
+    const int K0 = fx.K0;
+    for (int64_t tile = blockIdx.x; tile * NP < P.n_pairs; tile += gridDim.x) {
+        const int64_t pair0 = tile * NP;
+        if (threadIdx.x == 0) flags[0] = 0;
+        __syncthreads();
+        // stage x - 128 of both images (zeros past the last pair and past n)
+        for (int t = threadIdx.x; t < NC * 16 * K0; t += blockDim.x) {
+            const int col = t / K0, pix = t - col * K0;
+            const int pr = col % NP;
+            const int64_t pg = pair0 + pr;
+            int8_t v = 0;
+            if (pg < P.n_pairs && pix < n) v = (int8_t)((int)(col < NP ? P.x1 : P.x2)[pg * n + pix] - 128);
+            act[col * RS + pix] = v;
+        }
+        // x2 - x1: the changed pixels of each pair (one wave per pair)
+        for (int pr = wave; pr < NP; pr += kPairWaves) {
+            const int64_t pg = pair0 + pr;
+            int cnt = 0;
+            if (pg < P.n_pairs) {
+                const uint8_t *a = P.x1 + pg * n, *b = P.x2 + pg * n;
+                for (int p0 = 0; p0 < n; p0 += 64) {
+                    const int p = p0 + lane;
+                    const int d = p < n ? (int)b[p] - (int)a[p] : 0;
+                    const unsigned long long m = __ballot(d != 0);
+                    const int slot = cnt + __popcll(m & ((1ull << lane) - 1ull));
+                    if (d != 0 && slot < kPairRank) dlist[pr * kPairRank + slot] = (p << 16) | (d & 0xffff);
+                    cnt += __popcll(m);
+                }
+            }
+            if (lane == 0) {
+                dcount[pr] = cnt;
+                if (cnt > kPairRank) flags[0] = 1;
+            }
+        }
+        __syncthreads();
+        const bool dense = flags[0] != 0;
+        for (int l = 1; l <= L; ++l) {
+            const int KB = (l == 1) ? K0 / 64 : net.H[l - 1] / 64;
+            const int MT = net.H[l] / 16;
+            const int8_t *tiles = (l == 1) ? net.W1tile : fx.Wn[l];
+            const int32_t *init = fx.init[l];
+            const bool hidden = l < L;
+            const int s = hidden ? net.shift[l - 1] : 0;
+            const int off = hidden ? (64 << s) : 0;
+            // x2's first layer comes from the rank-r update unless the tile is dense
+            const int ncm = (l == 1 && !dense) ? NX : NC;
+            v4i acc[kPairMaxMt][NC];
+#pragma unroll
+            for (int i = 0; i < kPairMaxMt; ++i) {
+                const int mt = wave + kPairWaves * i;
+                if (mt < MT) {
+                    const int4 b = *reinterpret_cast<const int4 *>(init + mt * 16 + g * 4);
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) acc[i][c] = v4i{b.x, b.y, b.z, b.w};
+                }
+            }
+            if (wave < MT) {
+                for (int kb = 0; kb < KB; ++kb) {
+                    v4i A[kPairMaxMt];
+#pragma unroll
+                    for (int i = 0; i < kPairMaxMt; ++i) {
+                        const int mt = wave + kPairWaves * i;
+                        if (mt < MT) A[i] = reinterpret_cast<const v4i *>(tiles)[((int64_t)mt * KB + kb) * 64 + lane];
+                    }
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        if (c < ncm) {
+                            const v4i B = *reinterpret_cast<const v4i *>(act + (c * 16 + j16) * RS + kb * 64 + g * 16);
+#pragma unroll
+                            for (int i = 0; i < kPairMaxMt; ++i)
+                                if (wave + kPairWaves * i < MT)
+                                    acc[i][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[i], B, acc[i][c], 0, 0, 0);
+                        }
+                    }
+                }
+                if (l == 1 && !dense) {
+                    // u1(x2) = u1(x1) + sum (x2_p - x1_p) W1[:, p]; W1T rows are in
+                    // sigma order, where neurons 16 mt + 4 g + 0..3 are four
+                    // consecutive bytes
+#pragma unroll
+                    for (int c = 0; c < NX; ++c) {
+                        const int pr = c * 16 + j16;
+                        const int cnt = dcount[pr];
+#pragma unroll
+                        for (int i = 0; i < kPairMaxMt; ++i) {
+                            const int mt = wave + kPairWaves * i;
+                            if (mt < MT) {
+                                v4i u = acc[i][c];
+                                const int q = sigma64(mt * 16 + g * 4);
+                                for (int e = 0; e < cnt; ++e) {
+                                    const int ent = dlist[pr * kPairRank + e];
+                                    const int p = ent >> 16, d = (int)(short)(ent & 0xffff);
+                                    const int w4 = *reinterpret_cast<const int *>(net.W1T + (int64_t)p * net.H[1] + q);
+                                    u[0] += d * (int)(int8_t)(w4 & 0xff);
+                                    u[1] += d * (int)(int8_t)((w4 >> 8) & 0xff);
+                                    u[2] += d * (int)(int8_t)((w4 >> 16) & 0xff);
+                                    u[3] += d * (int)(int8_t)(w4 >> 24);
+                                }
+                                acc[i][c + NX] = u;
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();   // every wave has read this layer's inputs
+            // the layer's tests: nibbles of sign / value changes, distance partials
+            const int nout = net.dims[l];
+            const int nbo = P.nib_off[l];
+#pragma unroll
+            for (int c = 0; c < NX; ++c) {
+                unsigned long long dsum = 0;
+#pragma unroll
+                for (int i = 0; i < kPairMaxMt; ++i) {
+                    const int mt = wave + kPairWaves * i;
+                    if (mt < MT) {
+                        int sn = 0, vn = 0;
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int r = mt * 16 + g * 4 + t;
+                            if (r < nout) {
+                                const int64_t a = (int64_t)acc[i][c][t] + off, b = (int64_t)acc[i][c + NX][t] + off;
+                                const bool sa = a >= 0, sb = b >= 0;   // sign(0) = 1
+                                const bool sc = sa != sb;
+                                const int64_t aa = a < 0 ? -a : a, bb = b < 0 ? -b : b;
+                                const int64_t mx = aa > bb ? aa : bb, mn = aa > bb ? bb : aa;
+                                const bool vc =
+                                    !sc && mx > 0 && (int64_t)P.cp.ratio_den * mx >= (int64_t)P.cp.ratio_num * mn;
+                                const int64_t dd = a - b;
+                                const unsigned long long ad = (unsigned long long)(dd < 0 ? -dd : dd);
+                                dsum = sat_add(dsum, ad * ad);   // |a - b| < 2^32
+                                sn |= (int)sc << t;
+                                vn |= (int)vc << t;
+                            }
+                        }
+                        nib[(c * 16 + j16) * P.nib_stride + nbo + mt * 4 + g] = (uint8_t)(sn | (vn << 4));
+                    }
+                }
+                dsum = sat_add(dsum, __shfl_xor(dsum, 16));
+                dsum = sat_add(dsum, __shfl_xor(dsum, 32));
+                if (g == 0) dist[((l - 1) * NP + c * 16 + j16) * kPairWaves + wave] = dsum;
+            }
+            if (hidden) {
+#pragma unroll
+                for (int i = 0; i < kPairMaxMt; ++i) {
+                    const int mt = wave + kPairWaves * i;
+                    if (mt < MT) {
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) {
+                            int packed = 0;
+#pragma unroll
+                            for (int t = 0; t < 4; ++t) packed |= pair_requant_byte(acc[i][c][t], s) << (8 * t);
+                            *reinterpret_cast<int *>(act + (c * 16 + j16) * RS + mt * 16 + g * 4) = packed;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // per pair: counts, first sign change and distance of every layer, then
+        // the covered rows (one wave per pair)
+        for (int pr = wave; pr < NP; pr += kPairWaves) {
+            if (pair0 + pr >= P.n_pairs) continue;
+            const uint8_t *nb = nib + pr * P.nib_stride;
+            // layer by layer: this layer's count, first sign change and
+            // distance; then block l - 1 (rows of layer l - 1, bits of layer l)
+            int pcnt = 0, pfirst = 0;
+            bool pdc = false;
+            for (int l = 0; l < lay.nl; ++l) {
+                const int nbytes = net.H[l + 1] / 4, nbo = P.nib_off[l + 1];
+                if (l > 0 && (pcnt == 1 || pdc)) {
+                    const int W = lay.words[l];
+                    for (int t = lane; t < W; t += 64) {
+                        uint32_t sw = 0, vw = 0;
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) {
+                            const int b = 8 * t + k;
+                            const int v = b < nbytes ? nb[nbo + b] : 0;
+                            sw |= (uint32_t)(v & 15) << (4 * k);
+                            vw |= (uint32_t)(v >> 4) << (4 * k);
+                        }
+                        if (pcnt == 1) {
+                            const int64_t row = lay.rowoff[l - 1] + (int64_t)pfirst * W;
+                            if (sw) atomicOr(P.bits.rows_ss + row + t, sw);
+                            if (vw) atomicOr(P.bits.rows_sv + row + t, vw);
+                        }
+                        if (pdc) {
+                            if (sw) atomicOr(P.bits.all_ds + lay.alloff[l - 1] + t, sw);
+                            if (vw) atomicOr(P.bits.all_dv + lay.alloff[l - 1] + t, vw);
+                        }
+                    }
+                }
+                int cnt = 0, first = 0x7fffffff;
+                for (int b0 = 0; b0 < nbytes; b0 += 64) {
+                    const int b = b0 + lane;
+                    const int v = b < nbytes ? (nb[nbo + b] & 15) : 0;
+                    cnt += __popc(v);
+                    if (v) first = min(first, 4 * b + __ffs(v) - 1);
+                }
+                unsigned long long dsum = lane < kPairWaves ? dist[(l * NP + pr) * kPairWaves + lane] : 0ull;
+#pragma unroll
+                for (int sh = 32; sh >= 1; sh >>= 1) {
+                    cnt += __shfl_xor(cnt, sh);
+                    first = min(first, __shfl_xor(first, sh));
+                    dsum = sat_add(dsum, __shfl_xor(dsum, sh));
+                }
+                pcnt = cnt;
+                pfirst = first;
+                pdc = cnt == 0 && dsum >= (unsigned long long)P.cp.dist_sq_min;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+static bool cov_pair_plan(const QNetDev &net, const FwdExtra &fx, int nx, CovPairParams &P, size_t &lds) {
+    int hmax = fx.K0;
+    for (int l = 1; l < net.L; ++l) hmax = std::max(hmax, net.H[l]);
+    P.act_stride = hmax + 16;
+    int nbo = 0;
+    P.nib_off[0] = 0;
+    for (int l = 1; l <= net.L; ++l) {
+        P.nib_off[l] = nbo;
+        nbo += net.H[l] / 4;
+    }
+    P.nib_off[net.L + 1] = nbo;
+    P.nib_stride = (nbo + 3) & ~3;
+    const int NP = 16 * nx;
+    size_t o = (size_t)2 * NP * P.act_stride;
+    o = (o + 15) & ~(size_t)15;
+    P.off_nib = (int)o;
+    o += (size_t)NP * P.nib_stride;
+    o = (o + 15) & ~(size_t)15;
+    P.off_dist = (int)o;
+    o += (size_t)net.L * NP * kPairWaves * 8;
+    P.off_diff = (int)o;
+    o += (size_t)NP * kPairRank * 4 + NP * 4 + 16;
+    lds = o;
+    return lds <= (size_t)160 * 1024;
+}
+
+hipError_t launch_cov_pair(CovPairParams P, int n_cu, hipStream_t s) {
+    if (P.n_pairs <= 0) return hipSuccess;
+    size_t lds = 0;
+    if (!cov_pair_plan(P.net, P.fx, 1, P, lds)) return hipErrorInvalidValue;
+    const int64_t tiles = (P.n_pairs + 15) / 16;
+    const int grid = (int)std::min<int64_t>(tiles, (int64_t)n_cu * 16);
+    hipLaunchKernelGGL(cov_pair_kernel<1>, dim3(grid), dim3(64 * kPairWaves), lds, s, P);
+    return hipGetLastError();
+}
+
+}  // namespace ibmc

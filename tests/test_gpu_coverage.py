@@ -135,3 +135,30 @@ def test_coverage_invariants(ctx):
         assert np.array_equal(a["bits"], b["bits"])
         z = ibmc.ibmc_coverage(ctx, m, x1, x1, c)
         assert z["covered_pairs"] == 0 and z["covered_neurons"] == 0
+
+
+@pytest.mark.parametrize("ndiff", [[16, 1, 3], [17, 2, 0], [40, 5, 16], [None]])
+def test_pair_rank_update_and_dense_tiles(ctx, orc, ndiff):
+    """x2's first layer is the rank-r update of x1's when every pair of a
+    16-pair tile differs in at most 16 pixels, else the tile's x2 images run
+    the full first layer: pairs differing in 0, 1, 16, 17, 40 or every
+    pixel, mixed within tiles, against the oracle."""
+    from paper_1907_12933_amd import ibmc
+    g = I.rng(300 + len(ndiff) + (ndiff[0] or 0))
+    dims = [50, 70, 33, 9]
+    net = I.random_qnet(g, dims, shift=5, wmax=20, bmax=300)
+    m = ibmc.Mlp(ctx, net)
+    n_pairs = 45
+    x1 = g.integers(0, 255, size=(n_pairs, 50), endpoint=True).astype(np.uint8)
+    x2 = x1.copy()
+    for i in range(n_pairs):
+        k = ndiff[i % len(ndiff)]
+        if k is None:
+            x2[i] = g.integers(0, 255, size=50, endpoint=True)
+            continue
+        pix = g.choice(50, size=k, replace=False)
+        x2[i, pix] = (x1[i, pix].astype(np.int64) + g.integers(1, 255, size=k)) % 256
+    P1 = np.stack([orc.q8_forward(net, x)[0] for x in x1])
+    P2 = np.stack([orc.q8_forward(net, x)[0] for x in x2])
+    for c in CRITS:
+        same(ibmc.ibmc_coverage(ctx, m, x1, x2, c, dist_sq_min=100), orc.coverage(dims[1:], P1, P2, c, dist_sq_min=100))
