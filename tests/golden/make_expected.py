@@ -8,8 +8,10 @@ form (oracle/dense.py); an image already stored by the C oracle is
 recomputed that way and must give the same record digest.
 coverage784_expected.json: SS/DS/SV/DV coverage of the 784-1024-1024-1024-10
 net over its 4,096 seeded pairs (counts and a SHA-256 of the bit array).
+batch_expected.json: per listed property of the batched workload (the
+784-512-512-10 ones at k = 2), the same fields as for blob784.
 
-Usage: python tests/golden/make_expected.py [n_images]
+Usage: python tests/golden/make_expected.py [n_images] [--coverage] [--batch]
 """
 import hashlib
 import json
@@ -95,7 +97,31 @@ def coverage784():
     json.dump(out, open(os.path.join(HERE, "coverage784_expected.json"), "w"), indent=1)
 
 
+# 784-512-512-10 properties at k = 2 of the benchmark's batched workload
+BATCH_PROPS = (225, 226, 245)
+
+
+def batch784():
+    nets, props = I.batch_workload(seed=3)
+    out = dict(workload="batch (seed 3): the 784-512-512-10 properties at k = 2 listed by index", props={})
+    for i in BATCH_PROPS:
+        p = props[i]
+        net = nets[p.net_index]
+        t = time.time()
+        r = dense.q8_check(net, p.image, p.deltas, 1, p.k)
+        out["props"][str(i)] = dict(
+            net_sha256=net.digest(), dims=list(net.dims), image_sha256=I.array_digest(p.image),
+            deltas=[int(d) for d in p.deltas], k=int(p.k), clean_label=r["clean_label"],
+            points=[int(v) for v in r["points"]], cex=[int(v) for v in r["cex"]], ties=[int(v) for v in r["ties"]],
+            records_sha256=rec_digest(r["cex_k"], r["cex_rank"], r["cex_label"]), oracle="dense",
+            oracle_seconds=round(time.time() - t, 1))
+        print(i, out["props"][str(i)]["cex"], out["props"][str(i)]["oracle_seconds"], flush=True)
+    json.dump(out, open(os.path.join(HERE, "batch_expected.json"), "w"), indent=1)
+
+
 if __name__ == "__main__":
+    if "--batch" in sys.argv or not os.path.exists(os.path.join(HERE, "batch_expected.json")):
+        batch784()
     n = int(sys.argv[1]) if len(sys.argv) > 1 and sys.argv[1].isdigit() else 64
     if "--coverage" in sys.argv or not os.path.exists(os.path.join(HERE, "coverage784_expected.json")):
         coverage784()

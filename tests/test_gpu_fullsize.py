@@ -95,3 +95,30 @@ def test_coverage784_full(ctx):
         for key in ("covered_pairs", "total_pairs", "covered_neurons", "total_neurons", "literal"):
             assert r[key] == e[key], (c, key)
         assert hashlib.sha256(r["bits"].tobytes()).hexdigest() == e["bits_sha256"], c
+
+
+def test_batch_workload_wide_properties_match_oracle(ctx):
+    """The benchmark's 256-property batch in its launch configuration (the
+    shipped tuning table, one call for all eight networks): the listed
+    784-512-512-10 properties at k = 2 (1.2-2.8 M points each) compared with
+    the oracle's counts and record lists."""
+    from paper_1907_12933_amd import ibmc
+    exp = json.load(open(os.path.join(GOLD, "batch_expected.json")))
+    table = os.path.join(os.path.dirname(ibmc.__file__), "tune_gfx950.json")
+    if os.path.exists(table):
+        ibmc.ibmc_tune_load(ctx, table)
+    nets, props = I.batch_workload(seed=3)
+    ms = [ibmc.Mlp(ctx, n) for n in nets]
+    P = [(ms[p.net_index], p.image, p.deltas, 1, p.k) for p in props]
+    sums, cex, _, rc = ibmc.ibmc_check_batch(ctx, P, cex_capacity=1 << 24)
+    assert rc == ibmc.IBMC_OK
+    for key, e in exp["props"].items():
+        i = int(key)
+        p = props[i]
+        assert nets[p.net_index].digest() == e["net_sha256"] and I.array_digest(p.image) == e["image_sha256"]
+        assert [int(d) for d in p.deltas] == e["deltas"] and p.k == e["k"]
+        s = sums[i]
+        assert s["clean_label"] == e["clean_label"]
+        assert list(s["points"]) == e["points"] and s["cex"] == e["cex"] and s["ties"] == e["ties"], i
+        sel = cex[cex["prop"] == i]
+        assert rec_digest(sel["k"], sel["rank"], sel["new_label"]) == e["records_sha256"], i
