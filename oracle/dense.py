@@ -61,6 +61,17 @@ class _Net:
             self.dt.append(dt)
             self.WT.append(np.ascontiguousarray(w.T.astype(dt)))
 
+    def potentials(self, X):
+        """Potentials of every layer (int64 [B][sum of widths], layer by
+        layer, Eq. (1)) of a block of images X (uint8 [B][n])."""
+        a, out = X, []
+        for l in range(self.L):
+            u = np.rint(a.astype(self.dt[l]) @ self.WT[l]).astype(np.int64) + self.b[l]
+            out.append(u)
+            if l < self.L - 1:
+                a = np.clip(np.floor_divide(u, 1 << self.shift[l]), 0, 127)
+        return np.concatenate(out, axis=1)
+
     def logits(self, X):
         """Logits (int64 [B][classes]) of a block of images X (uint8 [B][n])."""
         a = X
@@ -129,3 +140,11 @@ def q8_check(net, x, deltas, k_min=1, k_max=2, k_step=1, block=8192):
                 ties=np.array(ties, np.int64), clean_label=clean, first_unsafe_k=first,
                 cex_total=int(sum(cex)), cex_k=cat(rk, np.int32), cex_rank=cat(rr, np.int64),
                 cex_label=cat(rl, np.int32))
+
+
+def q8_potentials(net, X, block=4096):
+    """Every layer's potentials (int64 [B][sum of widths]) of images X."""
+    N = _Net(net)
+    X = np.asarray(X, np.uint8).reshape(-1, net.dims[0])
+    return np.concatenate([N.potentials(X[i:i + block]) for i in range(0, len(X), block)]) if len(X) else \
+        np.zeros((0, sum(net.dims[1:])), np.int64)

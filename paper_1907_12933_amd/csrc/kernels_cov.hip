@@ -40,7 +40,9 @@ __global__ void __launch_bounds__(64 * kFwdWaves) fwd_pots_q8_kernel(QNetDev net
                                                                      int64_t pot_stride, int32_t *labels) {
     __shared__ __attribute__((aligned(16))) int8_t act[2][kFwdTile][kMaxWidth];
     __shared__ int candv[kFwdWaves][kFwdTile], candi[kFwdWaves][kFwdTile];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the wave index as a scalar: the compiler then sees every M-tile
+    // condition as wave-uniform (no exec-masked MFMAs, loads run ahead)
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int j16 = lane & 15, g = lane >> 4;
     const int n = net.dims[0];
     const int K0 = fx.K0;                      // pixels padded to 64

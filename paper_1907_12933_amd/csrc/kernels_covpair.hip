@@ -42,6 +42,39 @@ __device__ __forceinline__ int pair_requant_byte(int acc_minus_off, int s) {
     return (v >> s) & 0xff;
 }
 
+// One layer's MFMAs when every wave owns exactly NMT M-tiles (mt = wave +
+// kPairWaves i): no per-tile conditions, and each K-block's weight tiles are
+// loaded one block ahead of their MFMAs (two register sets, the K loop
+// unrolled by two).  ncm: N-tiles that take MFMAs (wave-uniform).
+template <int NMT, int NC>
+__device__ __forceinline__ void pair_layer_mfma(v4i (&acc)[kPairMaxMt][NC], const v4i *tiles, int wave, int KB,
+                                                int ncm, const int8_t *act, int RS, int j16, int g, int lane) {
+    v4i A0[NMT], A1[NMT];
+    auto load = [&](v4i (&A)[NMT], int kb) {
+#pragma unroll
+        for (int i = 0; i < NMT; ++i) A[i] = tiles[((int64_t)(wave + kPairWaves * i) * KB + kb) * 64 + lane];
+    };
+    auto step = [&](const v4i (&A)[NMT], int kb) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (c < ncm) {
+                const v4i B = *reinterpret_cast<const v4i *>(act + (c * 16 + j16) * RS + kb * 64 + g * 16);
+#pragma unroll
+                for (int i = 0; i < NMT; ++i) acc[i][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[i], B, acc[i][c], 0, 0, 0);
+            }
+        }
+    };
+    load(A0, 0);
+    for (int kb = 0; kb < KB; kb += 2) {
+        if (kb + 1 < KB) load(A1, kb + 1);
+        step(A0, kb);
+        if (kb + 1 < KB) {
+            if (kb + 2 < KB) load(A0, kb + 2);
+            step(A1, kb + 1);
+        }
+    }
+}
+
 template <int NX>
 __global__ void __launch_bounds__(64 * kPairWaves) cov_pair_kernel(CovPairParams P) {
     extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -58,7 +91,9 @@ __global__ void __launch_bounds__(64 * kPairWaves) cov_pair_kernel(CovPairParams
     int *dlist = reinterpret_cast<int *>(smem + P.off_diff);              // [NP][kPairRank]
     int *dcount = dlist + NP * kPairRank;                                 // [NP]
     int *flags = dcount + NP;                                             // [1]: dense
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the wave index as a scalar: the compiler then sees every M-tile
+    // condition as wave-uniform (no exec-masked MFMAs, loads run ahead)
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int j16 = lane & 15, g = lane >> 4;
     const int K0 = fx.K0;
     for (int64_t tile = blockIdx.x; tile * NP < P.n_pairs; tile += gridDim.x) {
@@ -116,7 +151,17 @@ __global__ void __launch_bounds__(64 * kPairWaves) cov_pair_kernel(CovPairParams
                     for (int c = 0; c < NC; ++c) acc[i][c] = v4i{b.x, b.y, b.z, b.w};
                 }
             }
-            if (wave < MT) {
+            const int nmt = (MT % kPairWaves == 0) ? MT / kPairWaves : 0;   // M-tiles of every wave
+            const v4i *tv = reinterpret_cast<const v4i *>(tiles);
+            if (nmt == 8) {
+                pair_layer_mfma<8>(acc, tv, wave, KB, ncm, act, RS, j16, g, lane);
+            } else if (nmt == 4) {
+                pair_layer_mfma<4>(acc, tv, wave, KB, ncm, act, RS, j16, g, lane);
+            } else if (nmt == 2) {
+                pair_layer_mfma<2>(acc, tv, wave, KB, ncm, act, RS, j16, g, lane);
+            } else if (nmt == 1) {
+                pair_layer_mfma<1>(acc, tv, wave, KB, ncm, act, RS, j16, g, lane);
+            } else if (wave < MT) {
                 for (int kb = 0; kb < KB; ++kb) {
                     v4i A[kPairMaxMt];
 #pragma unroll
@@ -135,6 +180,8 @@ __global__ void __launch_bounds__(64 * kPairWaves) cov_pair_kernel(CovPairParams
                         }
                     }
                 }
+            }
+            {
                 if (l == 1 && !dense) {
                     // u1(x2) = u1(x1) + sum (x2_p - x1_p) W1[:, p]; W1T rows are in
                     // sigma order, where neurons 16 mt + 4 g + 0..3 are four

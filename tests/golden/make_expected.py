@@ -10,8 +10,10 @@ coverage784_expected.json: SS/DS/SV/DV coverage of the 784-1024-1024-1024-10
 net over its 4,096 seeded pairs (counts and a SHA-256 of the bit array).
 batch_expected.json: per listed property of the batched workload (the
 784-512-512-10 ones at k = 2), the same fields as for blob784.
+coverage784_65536_expected.json: the same net's coverage over the
+benchmark's 65,536-pair sweep.
 
-Usage: python tests/golden/make_expected.py [n_images] [--coverage] [--batch]
+Usage: python tests/golden/make_expected.py [n_images] [--coverage] [--batch] [--sweep]
 """
 import hashlib
 import json
@@ -97,6 +99,25 @@ def coverage784():
     json.dump(out, open(os.path.join(HERE, "coverage784_expected.json"), "w"), indent=1)
 
 
+def coverage784_sweep(n_pairs=65536):
+    """The benchmark's 65,536-pair sweep: potentials by the block-matrix form
+    of the oracle, coverage by the C oracle's literal predicates."""
+    net, x1, x2 = I.coverage_pairs_blob784(n_pairs=n_pairs)
+    t = time.time()
+    P1 = dense.q8_potentials(net, x1)
+    P2 = dense.q8_potentials(net, x2)
+    out = dict(workload=f"coverage784 (seed 5): 784-1024-1024-1024-10 shift 7, {n_pairs} pairs",
+               net_sha256=net.digest(), pairs_sha256=I.array_digest(x1, x2), criteria={})
+    for c in ("SS", "DS", "SV", "DV"):
+        r = O.coverage(net.dims[1:], P1, P2, c)
+        out["criteria"][c] = dict(covered_pairs=r["covered_pairs"], total_pairs=r["total_pairs"],
+                                  covered_neurons=r["covered_neurons"], total_neurons=r["total_neurons"],
+                                  literal=r["literal"], bits_sha256=hashlib.sha256(r["bits"].tobytes()).hexdigest())
+        print(c, out["criteria"][c], round(time.time() - t, 1), flush=True)
+    out["oracle_seconds"] = round(time.time() - t, 1)
+    json.dump(out, open(os.path.join(HERE, f"coverage784_{n_pairs}_expected.json"), "w"), indent=1)
+
+
 # 784-512-512-10 properties at k = 2 of the benchmark's batched workload
 BATCH_PROPS = (225, 226, 245)
 
@@ -120,6 +141,8 @@ def batch784():
 
 
 if __name__ == "__main__":
+    if "--sweep" in sys.argv:
+        coverage784_sweep()
     if "--batch" in sys.argv or not os.path.exists(os.path.join(HERE, "batch_expected.json")):
         batch784()
     n = int(sys.argv[1]) if len(sys.argv) > 1 and sys.argv[1].isdigit() else 64

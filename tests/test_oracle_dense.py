@@ -71,3 +71,18 @@ def test_dense_matches_c_oracle(orc, seed, dims, wmax, shift, deltas, kmax):
     assert a["cex_total"] > 0 and a["cex_total"] < sum(a["points"])
     want = np.float64 if dims[0] == 784 else np.float32
     assert dense._Net(net).dt[0] == want
+
+
+@pytest.mark.parametrize("dims,shift", [([35, 16, 5], 7), ([60, 130, 70, 40, 7], [5, 4, 3]),
+                                        ([784, 1024, 1024, 1024, 10], 7)])
+def test_dense_potentials_match_c_oracle(orc, dims, shift):
+    """The block-matrix potentials (every layer, Eq. (1)) equal the C
+    oracle's per-image integer forward."""
+    from oracle import dense
+    g = I.rng(77)
+    net = I.random_qnet(g, dims, shift=shift)
+    X = g.integers(0, 255, size=(9, dims[0]), endpoint=True).astype(np.uint8)
+    P = dense.q8_potentials(net, X, block=4)
+    assert P.shape == (9, sum(dims[1:]))
+    for i in range(9):
+        assert np.array_equal(P[i], orc.q8_forward(net, X[i])[0])
