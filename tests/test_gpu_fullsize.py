@@ -122,3 +122,22 @@ def test_batch_workload_wide_properties_match_oracle(ctx):
         assert list(s["points"]) == e["points"] and s["cex"] == e["cex"] and s["ties"] == e["ties"], i
         sel = cex[cex["prop"] == i]
         assert rec_digest(sel["k"], sel["rank"], sel["new_label"]) == e["records_sha256"], i
+
+
+def test_coverage784_sweep_65536(ctx):
+    """The benchmark's 65,536-pair coverage sweep (all four criteria from one
+    pass), bit for bit against the oracle's digests."""
+    import torch
+    from paper_1907_12933_amd import ibmc
+    path = os.path.join(GOLD, "coverage784_65536_expected.json")
+    exp = json.load(open(path))
+    net, x1, x2 = I.coverage_pairs_blob784(n_pairs=65536)
+    assert net.digest() == exp["net_sha256"] and I.array_digest(x1, x2) == exp["pairs_sha256"]
+    m = ibmc.Mlp(ctx, net)
+    d1, d2 = torch.from_numpy(x1).cuda(), torch.from_numpy(x2).cuda()
+    res = ibmc.ibmc_coverage_all_dev(ctx, m, d1, d2)
+    for c, got in zip(["SS", "DS", "SV", "DV"], res):
+        e = exp["criteria"][c]
+        for key in ("covered_pairs", "total_pairs", "covered_neurons", "total_neurons", "literal"):
+            assert got[key] == e[key], (c, key)
+        assert hashlib.sha256(got["bits"].tobytes()).hexdigest() == e["bits_sha256"], c
