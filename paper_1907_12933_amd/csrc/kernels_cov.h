@@ -61,7 +61,7 @@ struct CovPairParams {
     int64_t n_pairs;
     // LDS plan (cov_pair_plan): activation row stride, per-pair nibble
     // offsets of each layer, byte offsets of the regions
-    int act_stride, nib_stride, off_nib, off_dist, off_diff;
+    int act_stride, nib_stride, off_nib, off_dist, off_diff, off_all;
     int nib_off[kMaxLayers + 2];
 };
 

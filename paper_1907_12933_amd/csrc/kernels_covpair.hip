@@ -20,7 +20,9 @@
 // and (hidden layers) the requantised activations written back over the
 // layer's inputs.  At the end every pair's counts, first sign change and
 // distance decide its covered rows, which are OR-ed into the device masks
-// exactly as the potential-based predicate kernel does.
+// as the potential-based predicate kernel does (the all-rows masks of DS /
+// DV, which every pair with a distance change ORs into the same few words,
+// are gathered per tile in LDS and flushed with one atomic per word).
 #include <algorithm>
 
 #include "kernels_cov.h"
@@ -91,6 +93,9 @@ __global__ void __launch_bounds__(64 * kPairWaves) cov_pair_kernel(CovPairParams
     int *dlist = reinterpret_cast<int *>(smem + P.off_diff);              // [NP][kPairRank]
     int *dcount = dlist + NP * kPairRank;                                 // [NP]
     int *flags = dcount + NP;                                             // [1]: dense
+    // the tile's OR of the all-rows (DS, DV) masks, flushed once per tile
+    uint32_t *tds = reinterpret_cast<uint32_t *>(smem + P.off_all);        // [all_words]
+    uint32_t *tdv = tds + lay.all_words;                                   // [all_words]
     // the wave index as a scalar: the compiler then sees every M-tile
     // condition as wave-uniform (no exec-masked MFMAs, loads run ahead)
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -99,15 +104,24 @@ __global__ void __launch_bounds__(64 * kPairWaves) cov_pair_kernel(CovPairParams
     for (int64_t tile = blockIdx.x; tile * NP < P.n_pairs; tile += gridDim.x) {
         const int64_t pair0 = tile * NP;
         if (threadIdx.x == 0) flags[0] = 0;
+        for (int t = threadIdx.x; t < 2 * lay.all_words; t += blockDim.x) tds[t] = 0u;
         __syncthreads();
-        // stage x - 128 of both images (zeros past the last pair and past n)
-        for (int t = threadIdx.x; t < NC * 16 * K0; t += blockDim.x) {
-            const int col = t / K0, pix = t - col * K0;
-            const int pr = col % NP;
-            const int64_t pg = pair0 + pr;
-            int8_t v = 0;
-            if (pg < P.n_pairs && pix < n) v = (int8_t)((int)(col < NP ? P.x1 : P.x2)[pg * n + pix] - 128);
-            act[col * RS + pix] = v;
+        // stage x - 128 of both images (zeros past the last pair and past n):
+        // wave w takes rows w, w + waves, ...; lanes take four pixels each
+        for (int col = wave; col < NC * 16; col += kPairWaves) {
+            const int64_t pg = pair0 + col % NP;
+            const uint8_t *src = (col < NP ? P.x1 : P.x2) + pg * n;
+            const bool live = pg < P.n_pairs;
+            for (int p4 = lane * 4; p4 < K0; p4 += 256) {
+                uint32_t w = 0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int pix = p4 + e;
+                    const uint32_t v = (live && pix < n) ? (uint32_t)(uint8_t)((int)src[pix] - 128) : 0u;
+                    w |= v << (8 * e);
+                }
+                *reinterpret_cast<uint32_t *>(act + col * RS + p4) = w;
+            }
         }
         // x2 - x1: the changed pixels of each pair (one wave per pair)
         for (int pr = wave; pr < NP; pr += kPairWaves) {
@@ -227,16 +241,19 @@ __global__ void __launch_bounds__(64 * kPairWaves) cov_pair_kernel(CovPairParams
                         for (int t = 0; t < 4; ++t) {
                             const int r = mt * 16 + g * 4 + t;
                             if (r < nout) {
-                                const int64_t a = (int64_t)acc[i][c][t] + off, b = (int64_t)acc[i][c + NX][t] + off;
-                                const bool sa = a >= 0, sb = b >= 0;   // sign(0) = 1
-                                const bool sc = sa != sb;
-                                const int64_t aa = a < 0 ? -a : a, bb = b < 0 ? -b : b;
-                                const int64_t mx = aa > bb ? aa : bb, mn = aa > bb ? bb : aa;
-                                const bool vc =
-                                    !sc && mx > 0 && (int64_t)P.cp.ratio_den * mx >= (int64_t)P.cp.ratio_num * mn;
-                                const int64_t dd = a - b;
-                                const unsigned long long ad = (unsigned long long)(dd < 0 ? -dd : dd);
-                                dsum = sat_add(dsum, ad * ad);   // |a - b| < 2^32
+                                // potentials fit int32 (the loader's headroom check);
+                                // |a - b| < 2^32 is |a| + |b| across a sign change,
+                                // else max - min of the magnitudes
+                                const int a = acc[i][c][t] + off, b = acc[i][c + NX][t] + off;
+                                const bool sc = (a >= 0) != (b >= 0);   // sign(0) = 1
+                                const uint32_t aa = a < 0 ? 0u - (uint32_t)a : (uint32_t)a;
+                                const uint32_t bb = b < 0 ? 0u - (uint32_t)b : (uint32_t)b;
+                                const uint32_t mx = aa > bb ? aa : bb, mn = aa > bb ? bb : aa;
+                                const bool vc = !sc && mx > 0 &&
+                                                (uint64_t)(uint32_t)P.cp.ratio_den * mx >=
+                                                    (uint64_t)(uint32_t)P.cp.ratio_num * mn;
+                                const uint32_t ad = sc ? aa + bb : mx - mn;
+                                dsum = sat_add(dsum, (unsigned long long)ad * ad);
                                 sn |= (int)sc << t;
                                 vn |= (int)vc << t;
                             }
@@ -293,8 +310,9 @@ __global__ void __launch_bounds__(64 * kPairWaves) cov_pair_kernel(CovPairParams
                             if (vw) atomicOr(P.bits.rows_sv + row + t, vw);
                         }
                         if (pdc) {
-                            if (sw) atomicOr(P.bits.all_ds + lay.alloff[l - 1] + t, sw);
-                            if (vw) atomicOr(P.bits.all_dv + lay.alloff[l - 1] + t, vw);
+                            // every pair of the tile ORs the same words: gather in LDS
+                            if (sw) atomicOr(tds + lay.alloff[l - 1] + t, sw);
+                            if (vw) atomicOr(tdv + lay.alloff[l - 1] + t, vw);
                         }
                     }
                 }
@@ -316,6 +334,11 @@ __global__ void __launch_bounds__(64 * kPairWaves) cov_pair_kernel(CovPairParams
                 pfirst = first;
                 pdc = cnt == 0 && dsum >= (unsigned long long)P.cp.dist_sq_min;
             }
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < lay.all_words; t += blockDim.x) {
+            if (tds[t]) atomicOr(P.bits.all_ds + t, tds[t]);
+            if (tdv[t]) atomicOr(P.bits.all_dv + t, tdv[t]);
         }
         __syncthreads();
     }
@@ -343,6 +366,8 @@ static bool cov_pair_plan(const QNetDev &net, const FwdExtra &fx, int nx, CovPai
     o += (size_t)net.L * NP * kPairWaves * 8;
     P.off_diff = (int)o;
     o += (size_t)NP * kPairRank * 4 + NP * 4 + 16;
+    P.off_all = (int)o;
+    o += (size_t)2 * std::max(P.lay.all_words, 1) * 4;
     lds = o;
     return lds <= (size_t)160 * 1024;
 }
