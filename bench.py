@@ -401,6 +401,22 @@ def retrain_leg(ctx, ibmc, inputs):
                 training_rate_batch256=rates)
 
 
+def replay_all(ibmc, ctx, net, w, cex):
+    """Replays every counterexample record of the step (its point rebuilt from
+    (k, rank) and the delta set, a full forward pass on the device) and counts
+    the records whose replayed label equals the recorded one."""
+    t0 = time.perf_counter()
+    ok = 0
+    order = np.argsort(cex["prop"], kind="stable")
+    recs = cex[order]
+    bounds = np.searchsorted(recs["prop"], np.arange(len(w.images) + 1))
+    for i in range(len(w.images)):
+        sel = recs[bounds[i]:bounds[i + 1]]
+        if len(sel):
+            ok += int(np.count_nonzero(ibmc.ibmc_replay(ctx, net, w.images[i], w.deltas, sel) == sel["new_label"]))
+    return dict(records=int(len(cex)), replayed_ok=ok, seconds=round(time.perf_counter() - t0, 3))
+
+
 def per_image(ibmc, ctx, net, w, sums):
     pots, labels = ibmc.ibmc_forward(ctx, net, w.images)
     z = np.sort(pots[:, -w.net.dims[-1]:].astype(np.int64), axis=1)
@@ -502,6 +518,8 @@ def main():
         "counterexamples_per_step": n_cex, "unsafe_images": unsafe,
         # per image: counterexamples and the clean top-2 logit margin
         "per_image": per_image(ibmc, ctx, net, w, sums),
+        # every record of the last timed step replayed (after the timed region)
+        "replay": replay_all(ibmc, ctx, net, w, cex),
     }
     if not args.no_extras:
         log("[bench] glyph leg")
