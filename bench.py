@@ -391,8 +391,10 @@ def retrain_leg(ctx, ibmc, inputs):
         t0 = time.perf_counter()
         ibmc.ibmc_fit_mlp(ctx, mb, Xb, Yb, epochs=5, batch=256, lr=1e-3, seed=3)
         t = time.perf_counter() - t0
+        tf = train_flops(dims, 5 * len(Yb)) / t / 1e12
         rates["-".join(map(str, dims))] = dict(samples_per_s=round(5 * len(Yb) / t), seconds=round(t, 4),
-                                               tflops=round(train_flops(dims, 5 * len(Yb)) / t / 1e12, 4))
+                                               tflops=round(tf, 4),
+                                               frac_fp32_peak=round(tf / MI355X_FP32_PEAK_TFLOPS, 5))
     return dict(workload="35-16-10 float net, 400 labelled glyphs (10 classes), 12 properties, pixels to 0/255, "
                          "k = 1..2", counterexamples_before=int(sum(len(c) for c in before)),
                 counterexamples_after=int(sum(len(c) for c in after)), augmented_samples=len(aug_x),
