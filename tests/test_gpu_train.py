@@ -156,3 +156,30 @@ def test_train_refusals(ctx):
         with pytest.raises(ibmc.IbmcError) as e:
             fn()
         assert e.value.code == code
+
+
+def test_fit_wide_net_split_batches_matches_oracle(ctx, orc):
+    """A batch whose partial rows exceed one launch's budget (784-1024-1024-
+    1024-10, 2.9 M parameters: the gradient is accumulated over several
+    launches before the Adam step) against the oracle's FP64 Adam."""
+    from paper_1907_12933_amd import ibmc
+    g = I.rng(24)
+    dims = [784, 1024, 1024, 1024, 10]
+    net = I.random_fnet(g, dims)
+    X = g.integers(0, 255, size=(70, 784), endpoint=True).astype(np.uint8)
+    Y = g.integers(0, 9, size=70, endpoint=True).astype(np.int32)
+    order = np.stack([g.permutation(70)])
+    m1, losses = ibmc.ibmc_fit_mlp(ctx, ibmc.Mlp(ctx, net), X, Y, epochs=1, batch=64, lr=1e-3, order=order)
+    W, b, rl = orc.f64_fit(net, X, Y, order, batch=64, lr=1e-3)
+    got, ref = flat(*m1.params), flat(W, b)
+    # Adam moves a parameter by about lr whatever its gradient's size, so a
+    # gradient within the FP32 rounding of zero may step either way: the
+    # strict bound holds where the first batch's gradient is clear of it
+    _, g0 = orc.f64_loss_grad(net, X[order[0][:64]], Y[order[0][:64]])
+    clear = np.abs(g0) > 1e-3 * np.max(np.abs(g0))
+    d = np.abs(got - ref)
+    print(f"wide fit: theta max diff {d[clear].max():.3e} where the gradient is clear of zero "
+          f"({clear.mean():.4f} of the parameters), {d.max():.3e} overall; losses {losses} vs {rl}")
+    assert d[clear].max() <= 1e-4 * 2 * 1e-3
+    assert d.max() <= 2 * 2 * 1e-3
+    assert np.allclose(losses, rl, rtol=1e-5)
