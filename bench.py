@@ -437,7 +437,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the proposer, coverage and batch legs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "one GPU only: the enumeration runs on a single device; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
