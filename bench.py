@@ -337,6 +337,22 @@ def table_leg(ctx, ibmc, inputs):
     out["table_false_counterexamples"] = len(t_rec - e_rec - e_tie)
     out["table_missed_counterexamples"] = len(e_rec - t_rec - e_tie)
     out["workload"] = "glyph35 net as float sigmoid (W/64, b/16384), 10 glyphs, deltas -16..16, k = 1..2"
+    # a property where the table does change verdicts: a seeded 35-16-5
+    # float net (seed 25) on one glyph, the same domain
+    g2 = inputs.rng(25)
+    net2 = inputs.fnet_from_qnet(inputs.random_qnet(g2, [35, 16, 5], shift=7))
+    x2 = inputs.glyph_images(g2, 1, 7, 5)[0]
+    m2 = ibmc.Mlp(ctx, net2)
+    sets = {}
+    for name, tab in (("exp", False), ("table", True)):
+        _, cx, tx = ibmc.ibmc_check_property(ctx, m2, x2, g.deltas, 1, 2, cex_capacity=1 << 22,
+                                             near_tie_capacity=1 << 20, table_sigmoid=tab)
+        sets[name] = (set(zip(cx["k"].tolist(), cx["rank"].tolist())), set(zip(tx["k"].tolist(), tx["rank"].tolist())))
+    (e2, et2), (t2, _) = sets["exp"], sets["table"]
+    out["seeded_property"] = dict(workload="35-16-5 float net (seed 25), one glyph, deltas -16..16, k = 1..2",
+                                  exp_counterexamples=len(e2), table_counterexamples=len(t2),
+                                  table_false_counterexamples=len(t2 - e2 - et2),
+                                  table_missed_counterexamples=len(e2 - t2 - et2))
     return out
 
 

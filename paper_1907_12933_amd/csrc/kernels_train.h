@@ -9,7 +9,7 @@
 
 namespace ibmc {
 
-constexpr int kTrainThreads = 256;
+constexpr int kTrainThreads = 1024;
 constexpr int kTrainMaxTile = 16;          // samples per workgroup
 constexpr int kTrainLdsBytes = 64 * 1024;  // LDS of one workgroup
 
