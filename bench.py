@@ -281,6 +281,30 @@ def glyph_leg(ctx, ibmc, inputs):
                 counterexamples=int(sum(s["cex_total"] for s in sums)))
 
 
+def covsearch_leg(ctx, ibmc, inputs):
+    """Coverage-guided test generation (the covers of Sec. III-B as the
+    objective, Sec. IV-C): a seeded 30-40-30-6 integer net (shifts 5 and 4)
+    and a random 30-pixel image; every point of level 2 of the deltas
+    +-20/+-60/+-120 (15,660 candidate tests) scored for each criterion, and up
+    to 64 tests taken greedily."""
+    g = inputs.rng(33)
+    net = inputs.random_qnet(g, [30, 40, 30, 6], shift=[5, 4], wmax=40, bmax=300)
+    x = g.integers(0, 255, size=30, endpoint=True).astype(np.uint8)
+    D = np.array([-120, -60, -20, 20, 60, 120], np.int16)
+    m = ibmc.Mlp(ctx, net)
+    out = {}
+    for crit in ("SS", "DS", "SV", "DV"):
+        ibmc.ibmc_coverage_search(ctx, m, x, D, 2, crit, max_tests=64)
+        t0 = time.perf_counter()
+        tests, gains, cov = ibmc.ibmc_coverage_search(ctx, m, x, D, 2, crit, max_tests=64)
+        t = time.perf_counter() - t0
+        out[crit] = dict(seconds=round(t, 5), tests=len(tests), covered_pairs=cov["covered_pairs"],
+                         total_pairs=cov["total_pairs"], first_gain=int(gains[0]) if len(gains) else 0,
+                         candidates_per_s=round(435 * 36 / t))
+    out["workload"] = "30-40-30-6 net (seed 33), one random image, level k = 2 of 6 deltas (15,660 candidate tests)"
+    return out
+
+
 def ball_leg(ctx, ibmc, inputs):
     """The paper's own domain (Sec. III-C, Eq. (9)): every image within L2
     distance gamma * 255 of each of the ten 7x5 glyphs of the 35-16-5 net,
@@ -542,6 +566,8 @@ def main():
     if not args.no_extras:
         log("[bench] glyph leg")
         out["glyph35"] = glyph_leg(ctx, ibmc, inputs)
+        log("[bench] coverage-guided test generation leg")
+        out["coverage_search"] = covsearch_leg(ctx, ibmc, inputs)
         log("[bench] L2-ball leg")
         out["ball"] = ball_leg(ctx, ibmc, inputs)
         log("[bench] table sigmoid leg")
