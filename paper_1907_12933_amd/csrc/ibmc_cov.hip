@@ -266,9 +266,12 @@ extern "C" ibmc_status ibmc_coverage_search(ibmc_ctx *ctx, const ibmc_mlp *net, 
     HIP_OK(hipMemcpyAsync(dimg, image, (size_t)n, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(ddel, delta_set, (size_t)n_deltas * 2, hipMemcpyHostToDevice, s));
     const size_t mask_bytes = (size_t)nc * words * 8;
-    // [potentials | masks | labels | covered (kCovSearchMaxWords words) | best key], 256-byte aligned parts
+    // [potentials | masks | labels | covered (kCovSearchMaxWords words) | a batch of greedy steps' best
+    // keys | their labels], 256-byte aligned parts
+    constexpr int kSteps = 16;
     const size_t need = ((size_t)lay.U * 4 + 255) / 256 * 256 + (mask_bytes + 255) / 256 * 256 +
-                        ((size_t)nc * 4 + 255) / 256 * 256 + (size_t)(kCovSearchMaxWords + 1) * 8;
+                        ((size_t)nc * 4 + 255) / 256 * 256 + (size_t)(kCovSearchMaxWords + kSteps) * 8 +
+                        (size_t)kSteps * 4;
     IBMC_TRY(ctx->cov_pots.reserve(need));
     char *base = ctx->cov_pots.as<char>();
     int32_t *pot0 = reinterpret_cast<int32_t *>(base);
@@ -276,7 +279,8 @@ extern "C" ibmc_status ibmc_coverage_search(ibmc_ctx *ctx, const ibmc_mlp *net, 
     int32_t *labels = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(masks) + ((mask_bytes + 255) / 256) * 256);
     unsigned long long *covered =
         reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(labels) + (((size_t)nc * 4 + 255) / 256) * 256);
-    unsigned long long *key = covered + kCovSearchMaxWords;
+    unsigned long long *keys = covered + kCovSearchMaxWords;
+    int32_t *labs = reinterpret_cast<int32_t *>(keys + kSteps);
     HIP_OK(launch_fwd_pots_q8(net->qd, net->fx, dimg, 1, pot0, lay.U, nullptr, s));
     CovCandParams cpar{};
     cpar.net = net->qd;
@@ -293,26 +297,37 @@ extern "C" ibmc_status ibmc_coverage_search(ibmc_ctx *ctx, const ibmc_mlp *net, 
     cpar.masks = masks;
     cpar.labels = labels;
     HIP_OK(launch_cov_cand(cpar, s));
-    HIP_OK(launch_fill_u64(covered, kCovSearchMaxWords + 1, 0ull, s));
+    HIP_OK(launch_fill_u64(covered, kCovSearchMaxWords, 0ull, s));
     // greedy: the candidate adding the most uncovered pairs (lowest rank on
-    // ties), until none adds any or max_tests are taken
+    // ties), until none adds any or max_tests are taken.  Steps are queued
+    // kSteps at a time and their winners read back once per batch; a step
+    // after one without a winner finds none either (nothing was added).
     int32_t taken = 0;
+    bool done = false;
     std::vector<CexRec> picked;
     std::vector<int64_t> gain_v;
-    while (taken < max_tests) {
-        HIP_OK(launch_fill_u64(key, 1, 0ull, s));
-        HIP_OK(launch_cov_gain(masks, nc, words, covered, key, s));
-        HIP_OK(launch_cov_take(masks, words, key, covered, s));
-        unsigned long long hk = 0;
-        HIP_OK(hipMemcpyAsync(&hk, key, 8, hipMemcpyDeviceToHost, s));
+    unsigned long long hk[kSteps];
+    int32_t hl[kSteps];
+    while (taken < max_tests && !done) {
+        const int nb = std::min(kSteps, max_tests - taken);
+        HIP_OK(launch_fill_u64(keys, nb, 0ull, s));
+        for (int i = 0; i < nb; ++i) {
+            HIP_OK(launch_cov_gain(masks, nc, words, covered, keys + i, s));
+            HIP_OK(launch_cov_take(masks, words, keys + i, covered, labels, labs + i, s));
+        }
+        HIP_OK(hipMemcpyAsync(hk, keys, (size_t)nb * 8, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(hl, labs, (size_t)nb * 4, hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
-        if (!hk) break;
-        const int64_t c = (int64_t)(((1ull << 40) - 1ull) - (hk & ((1ull << 40) - 1ull)));
-        int32_t lab = 0;
-        HIP_OK(hipMemcpy(&lab, labels + c, 4, hipMemcpyDeviceToHost));
-        picked.push_back(CexRec{0, k, c, lab, 0});
-        gain_v.push_back((int64_t)(hk >> 40));
-        ++taken;
+        for (int i = 0; i < nb; ++i) {
+            if (!hk[i]) {
+                done = true;
+                break;
+            }
+            const int64_t c = (int64_t)(((1ull << 40) - 1ull) - (hk[i] & ((1ull << 40) - 1ull)));
+            picked.push_back(CexRec{0, k, c, hl[i], 0});
+            gain_v.push_back((int64_t)(hk[i] >> 40));
+            ++taken;
+        }
     }
     std::vector<unsigned long long> cov(words);
     HIP_OK(hipMemcpyAsync(cov.data(), covered, (size_t)words * 8, hipMemcpyDeviceToHost, s));

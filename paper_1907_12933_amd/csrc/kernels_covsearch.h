@@ -24,7 +24,8 @@ struct CovCandParams {
 hipError_t launch_cov_cand(const CovCandParams &P, hipStream_t s);
 hipError_t launch_cov_gain(const unsigned long long *masks, int64_t n_cand, int words,
                            const unsigned long long *covered, unsigned long long *best_key, hipStream_t s);
+// ORs the winner's bits into `covered` and writes its label (-1: no winner).
 hipError_t launch_cov_take(const unsigned long long *masks, int words, const unsigned long long *best_key,
-                           unsigned long long *covered, hipStream_t s);
+                           unsigned long long *covered, const int32_t *labels, int32_t *label_out, hipStream_t s);
 
 }  // namespace ibmc

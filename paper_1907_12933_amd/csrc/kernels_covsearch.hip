@@ -7,7 +7,8 @@
 // the neuron pairs (i, j) of adjacent layers that the pair (x, x') covers
 // under one criterion, as a bitset in the layout of ibmc_coverage's
 // covered_bits.  A greedy loop then picks, one test at a time, the candidate
-// covering the most pairs not yet covered.  Networks whose non-input layers
+// covering the most pairs not yet covered (the host queues the steps in
+// batches and reads their winners back once per batch).  Networks whose non-input layers
 // have at most 64 units (one lane per unit).
 #include "kernels_covsearch.h"
 #include "enum_common.h"
@@ -145,11 +146,15 @@ __global__ void __launch_bounds__(256) cov_gain_kernel(const unsigned long long 
 }
 
 __global__ void cov_take_kernel(const unsigned long long *masks, int words, const unsigned long long *best_key,
-                                unsigned long long *covered) {
+                                unsigned long long *covered, const int32_t *labels, int32_t *label_out) {
     const unsigned long long key = *best_key;
-    if (!key) return;
+    if (!key) {
+        if (threadIdx.x == 0) *label_out = -1;
+        return;
+    }
     const int64_t c = (int64_t)(((1ull << 40) - 1ull) - (key & ((1ull << 40) - 1ull)));
     for (int w = threadIdx.x; w < words; w += blockDim.x) covered[w] |= masks[c * words + w];
+    if (threadIdx.x == 0) *label_out = labels[c];
 }
 
 hipError_t launch_cov_cand(const CovCandParams &P, hipStream_t s) {
@@ -167,8 +172,8 @@ hipError_t launch_cov_gain(const unsigned long long *masks, int64_t n_cand, int 
 }
 
 hipError_t launch_cov_take(const unsigned long long *masks, int words, const unsigned long long *best_key,
-                           unsigned long long *covered, hipStream_t s) {
-    hipLaunchKernelGGL(cov_take_kernel, dim3(1), dim3(64), 0, s, masks, words, best_key, covered);
+                           unsigned long long *covered, const int32_t *labels, int32_t *label_out, hipStream_t s) {
+    hipLaunchKernelGGL(cov_take_kernel, dim3(1), dim3(64), 0, s, masks, words, best_key, covered, labels, label_out);
     return hipGetLastError();
 }
 
