@@ -231,7 +231,10 @@ __global__ void __launch_bounds__(64 * kPairWaves) cov_pair_kernel(CovPairParams
             const int nbo = P.nib_off[l];
 #pragma unroll
             for (int c = 0; c < NX; ++c) {
-                unsigned long long dsum = 0;
+                // the squared distance as a 64-bit sum plus a count of its
+                // carries (saturated once, after the layer)
+                unsigned long long dlo = 0;
+                uint32_t dhi = 0;
 #pragma unroll
                 for (int i = 0; i < kPairMaxMt; ++i) {
                     const int mt = wave + kPairWaves * i;
@@ -245,7 +248,7 @@ __global__ void __launch_bounds__(64 * kPairWaves) cov_pair_kernel(CovPairParams
                                 // |a - b| < 2^32 is |a| + |b| across a sign change,
                                 // else max - min of the magnitudes
                                 const int a = acc[i][c][t] + off, b = acc[i][c + NX][t] + off;
-                                const bool sc = (a >= 0) != (b >= 0);   // sign(0) = 1
+                                const bool sc = (a ^ b) < 0;   // the signs differ (sign(0) = 1)
                                 const uint32_t aa = a < 0 ? 0u - (uint32_t)a : (uint32_t)a;
                                 const uint32_t bb = b < 0 ? 0u - (uint32_t)b : (uint32_t)b;
                                 const uint32_t mx = aa > bb ? aa : bb, mn = aa > bb ? bb : aa;
@@ -253,7 +256,9 @@ __global__ void __launch_bounds__(64 * kPairWaves) cov_pair_kernel(CovPairParams
                                                 (uint64_t)(uint32_t)P.cp.ratio_den * mx >=
                                                     (uint64_t)(uint32_t)P.cp.ratio_num * mn;
                                 const uint32_t ad = sc ? aa + bb : mx - mn;
-                                dsum = sat_add(dsum, (unsigned long long)ad * ad);
+                                const unsigned long long nl = dlo + (unsigned long long)ad * ad;
+                                dhi += nl < dlo;
+                                dlo = nl;
                                 sn |= (int)sc << t;
                                 vn |= (int)vc << t;
                             }
@@ -261,6 +266,7 @@ __global__ void __launch_bounds__(64 * kPairWaves) cov_pair_kernel(CovPairParams
                         nib[(c * 16 + j16) * P.nib_stride + nbo + mt * 4 + g] = (uint8_t)(sn | (vn << 4));
                     }
                 }
+                unsigned long long dsum = dhi ? ~0ull : dlo;
                 dsum = sat_add(dsum, __shfl_xor(dsum, 16));
                 dsum = sat_add(dsum, __shfl_xor(dsum, 32));
                 if (g == 0) dist[((l - 1) * NP + c * 16 + j16) * kPairWaves + wave] = dsum;
