@@ -406,22 +406,35 @@ def retrain_leg(ctx, ibmc, inputs):
         out = [ibmc.ibmc_check_property(ctx, mm, X[i], D, 1, 2)[1] for i in range(12)]
         return out, time.perf_counter() - t
 
+    def augment(recs):
+        ax, ay = [], []
+        for i, cex in enumerate(recs):
+            for k, r in zip(cex["k"], cex["rank"]):
+                pix, dig = ibmc.ibmc_decode_point(35, 2, int(k), int(r))
+                xp = X[i].astype(np.int64).copy()
+                for p_, d_ in zip(pix, dig):
+                    xp[p_] = min(255, max(0, xp[p_] + int(D[d_])))
+                ax.append(xp.astype(np.uint8))
+                ay.append(Y[i])
+        return ax, ay
+
     before, t_chk = check(m0)
-    aug_x, aug_y = [], []
-    for i, cex in enumerate(before):
-        for k, r in zip(cex["k"], cex["rank"]):
-            pix, dig = ibmc.ibmc_decode_point(35, 2, int(k), int(r))
-            xp = X[i].astype(np.int64).copy()
-            for p_, d_ in zip(pix, dig):
-                xp[p_] = min(255, max(0, xp[p_] + int(D[d_])))
-            aug_x.append(xp.astype(np.uint8))
-            aug_y.append(Y[i])
+    aug_x, aug_y = augment(before)
     X2 = np.concatenate([X, np.stack(aug_x)]) if aug_x else X
     Y2 = np.concatenate([Y, np.array(aug_y, np.int32)])
     t0 = time.perf_counter()
     m1, l1 = ibmc.ibmc_fit_mlp(ctx, m0, X2, Y2, epochs=20, batch=32, lr=5e-3, seed=2)
     t_refit = time.perf_counter() - t0
     after, _ = check(m1)
+    # a second pass of the loop on the counterexamples that remain
+    ax2, ay2 = augment(after)
+    if ax2:
+        X3 = np.concatenate([X2, np.stack(ax2)])
+        Y3 = np.concatenate([Y2, np.array(ay2, np.int32)])
+        m2, _ = ibmc.ibmc_fit_mlp(ctx, m1, X3, Y3, epochs=20, batch=32, lr=5e-3, seed=3)
+        second, _ = check(m2)
+    else:
+        second = after
     # training rate
     _, Xb, Yb = inputs.labelled_glyphs(g, 10, 20000, p_flip=0.03, proto_flip=0.15)
     rates = {}
@@ -438,6 +451,7 @@ def retrain_leg(ctx, ibmc, inputs):
     return dict(workload="35-16-10 float net, 400 labelled glyphs (10 classes), 12 properties, pixels to 0/255, "
                          "k = 1..2", counterexamples_before=int(sum(len(c) for c in before)),
                 counterexamples_after=int(sum(len(c) for c in after)), augmented_samples=len(aug_x),
+                counterexamples_after_second_pass=int(sum(len(c) for c in second)),
                 loss_first_last=[round(float(l0[0]), 4), round(float(l0[-1]), 4)],
                 fit_seconds=round(t_fit, 4), refit_seconds=round(t_refit, 4), check_seconds=round(t_chk, 4),
                 training_rate_batch256=rates)
