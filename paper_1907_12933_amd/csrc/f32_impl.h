@@ -332,13 +332,15 @@ __device__ __forceinline__ void segment_prefix(const Cursor &c, int (&pp)[kMaxK]
 // fixed) the wave computes v_j before the last pixel once into its LDS slot;
 // per property it keeps the clean label in a register; a chunk then loads
 // only its own pixels, deltas and first-layer rows.
-template <int H1, int H2, int NCP>
+template <int H1, int H2, int NCP, bool TAB>
 __global__ void __launch_bounds__(256) enum_f32_lane_kernel(FEnumParams P) {
     constexpr int CH = kF32LaneChunk;
     __shared__ float a2s[kLaneWaves][H2 > 0 ? H2 : NCP][64];
     __shared__ __attribute__((aligned(16))) float bases[kLaneWaves][H1];
     __shared__ float tab[kLutIntervals + 1];
-    const bool use_tab = stage_table(P.lut, tab);
+    // TAB is a compile-time switch: a run-time choice inside the unrolled
+    // layer loops keeps both activations live and spills the 128-wide ones
+    const bool use_tab = TAB && stage_table(P.lut, tab);
     const int lane = __lane_id();
     float *a2w = &a2s[threadIdx.x >> 6][0][0];
     float *base = &bases[threadIdx.x >> 6][0];
@@ -416,11 +418,11 @@ __global__ void __launch_bounds__(256) enum_f32_lane_kernel(FEnumParams P) {
 
 // Listed points (or the clean images of listed properties), one per lane,
 // in the same sequence of operations.
-template <int H1, int H2, int NCP>
+template <int H1, int H2, int NCP, bool TAB>
 __global__ void __launch_bounds__(256) eval_f32_lane_kernel(F32EvalParams E) {
     __shared__ float a2s[kLaneWaves][H2 > 0 ? H2 : NCP][64];
     __shared__ float tab[kLutIntervals + 1];
-    const bool use_tab = stage_table(E.lut, tab);
+    const bool use_tab = TAB && stage_table(E.lut, tab);
     const int lane = __lane_id();
     float *a2w = &a2s[threadIdx.x >> 6][0][0];
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -471,16 +473,19 @@ __global__ void __launch_bounds__(256) eval_f32_lane_kernel(F32EvalParams E) {
 }
 
 // A compiled lane instance: L weight layers, padded widths, its kernels.
+// enum_fn[t] / eval_fn[t]: the exponential sigmoid (t = 0) or the table (t = 1).
 struct F32LaneVariant {
     int L, h1, h2, ncp;
-    const void *enum_fn;
-    const void *eval_fn;
+    const void *enum_fn[2];
+    const void *eval_fn[2];
 };
 
 #define IBMC_F32_LANE(H1, H2, NCP)                                                                 \
     F32LaneVariant { (H2) > 0 ? 3 : 2, H1, H2, NCP,                                                \
-                     reinterpret_cast<const void *>(&enum_f32_lane_kernel<H1, H2, NCP>),            \
-                     reinterpret_cast<const void *>(&eval_f32_lane_kernel<H1, H2, NCP>) }
+                     {reinterpret_cast<const void *>(&enum_f32_lane_kernel<H1, H2, NCP, false>),    \
+                      reinterpret_cast<const void *>(&enum_f32_lane_kernel<H1, H2, NCP, true>)},    \
+                     {reinterpret_cast<const void *>(&eval_f32_lane_kernel<H1, H2, NCP, false>),    \
+                      reinterpret_cast<const void *>(&eval_f32_lane_kernel<H1, H2, NCP, true>)} }
 
 // Instance tables (one per source file, to split compilation).
 const F32LaneVariant *f32_lane_variants_l2(int *n);

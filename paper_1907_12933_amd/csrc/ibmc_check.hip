@@ -378,7 +378,7 @@ static ibmc_status run_levels(ibmc_ctx *ctx, const ibmc_property *props, int32_t
             pl.grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * occ, std::max<int64_t>(1, pl.total / 2));
             pl.batch = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, pl.total / ((int64_t)pl.grid * 32)));
         } else {
-            const int g = f32_enum_grid(net->fd, ctx->n_cu);
+            const int g = f32_enum_grid(net->fd, ctx->n_cu, o->sigmoid == IBMC_SIGMOID_TABLE);
             if (g < 1) return fail(IBMC_E_UNIMPL, "no float enumeration kernel for network %s", shape_key(net).c_str());
             pl.grid = (int)std::min<int64_t>(g, std::max<int64_t>(1, pl.total));
         }

@@ -74,7 +74,7 @@ hipError_t launch_eval_f32(const F32EvalParams &E, hipStream_t s);
 hipError_t launch_enum_f32(int grid_waves, const FEnumParams &P, hipStream_t s);
 // Points per chunk and a grid size (waves) that fills the device.
 int enum_f32_chunk(const FNetDev &net);
-int f32_enum_grid(const FNetDev &net, int n_cu);
+int f32_enum_grid(const FNetDev &net, int n_cu, bool table);  // table: the table-sigmoid instance
 // Whether a compiled lane instance serves this padded shape.
 bool f32_lane_supported(int L, const int *HP);
 

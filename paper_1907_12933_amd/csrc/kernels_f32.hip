@@ -391,11 +391,12 @@ F32Layout f32_layout(int L, const int *dims) {
 
 int enum_f32_chunk(const FNetDev &net) { return net.kind == F32_LANE ? kF32LaneChunk : kF32WideChunk; }
 
-int f32_enum_grid(const FNetDev &net, int n_cu) {
+int f32_enum_grid(const FNetDev &net, int n_cu, bool table) {
     int occ = 0;
     if (net.kind == F32_LANE) {
         const F32LaneVariant *v = find_lane(net.L, net.HP);
-        if (!v || hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, v->enum_fn, 256, 0) != hipSuccess) return 0;
+        if (!v || hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, v->enum_fn[table ? 1 : 0], 256, 0) != hipSuccess)
+            return 0;
         return std::max(occ, 1) * n_cu * kLaneWaves;
     }
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, enum_f32_wide_kernel, 64, wide_lds_bytes(net)) !=
@@ -410,7 +411,7 @@ hipError_t launch_enum_f32(int grid_waves, const FEnumParams &P, hipStream_t s) 
         if (!v) return hipErrorInvalidValue;
         FEnumParams a = P;
         void *args[] = {&a};
-        return hipLaunchKernel(v->enum_fn, dim3((grid_waves + kLaneWaves - 1) / kLaneWaves), dim3(256), args, 0, s);
+        return hipLaunchKernel(v->enum_fn[P.lut ? 1 : 0], dim3((grid_waves + kLaneWaves - 1) / kLaneWaves), dim3(256), args, 0, s);
     }
     hipLaunchKernelGGL(enum_f32_wide_kernel, dim3(grid_waves), dim3(64), wide_lds_bytes(P.net), s, P);
     return hipGetLastError();
@@ -423,7 +424,7 @@ hipError_t launch_eval_f32(const F32EvalParams &E, hipStream_t s) {
         if (!v) return hipErrorInvalidValue;
         F32EvalParams a = E;
         void *args[] = {&a};
-        return hipLaunchKernel(v->eval_fn, dim3((unsigned)((E.n + 255) / 256)), dim3(256), args, 0, s);
+        return hipLaunchKernel(v->eval_fn[E.lut ? 1 : 0], dim3((unsigned)((E.n + 255) / 256)), dim3(256), args, 0, s);
     }
     hipLaunchKernelGGL(eval_f32_wide_kernel, dim3((unsigned)((E.n + 15) / 16)), dim3(64), wide_lds_bytes(E.net), s, E);
     return hipGetLastError();
