@@ -550,7 +550,6 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
 
     // output layer of at most 16 classes: one M-tile, its weight tiles read
     // when needed, its init held in registers
-    const v4i *wo = reinterpret_cast<const v4i *>(wls) + lane;
     v4i bo4 = v4i{0, 0, 0, 0};
     if constexpr (OUT16) {
         const int4 b = *reinterpret_cast<const int4 *>(bls + g * 4);
@@ -756,9 +755,16 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
         v4i acco[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acco[nt] = bo4;
+        // weights read from global memory: the bases go through opaque
+        // scalar copies here, inside the chunk loop; otherwise the compiler
+        // hoists one 64-bit address per unrolled load (offsets beyond the
+        // load's immediate field) out of the loop and spills them
+        const int8_t *w2b = w2s, *wlb = wls;
+        if constexpr (!WLDS) asm volatile("" : "+s"(w2b), "+s"(wlb));
+        const v4i *wo = reinterpret_cast<const v4i *>(wlb) + lane;
         v4i a2[NT][(L == 3 && !OUT16) ? KB2 : 1];
         if constexpr (L == 3) {
-            const v4i *wt2 = reinterpret_cast<const v4i *>(w2s) + lane;
+            const v4i *wt2 = reinterpret_cast<const v4i *>(w2b) + lane;
             const int4 *bias2 = reinterpret_cast<const int4 *>(b2s + g * 4);
             v4i blk[NT];  // the a2 block being filled (OUT16)
             // requantisation of the finished tile pm into B operands; with
@@ -964,7 +970,7 @@ __global__ void __launch_bounds__(256, 2) enum_q8_kernel(EnumParams P, const int
                 for (int nt = 0; nt < NT; ++nt) acc[nt] = v4i{bias.x, bias.y, bias.z, bias.w};
 #pragma unroll
                 for (int kb = 0; kb < KBL; ++kb) {
-                    const v4i A = *reinterpret_cast<const v4i *>(wls + ((int64_t)(mt * KBL + kb) * 64 + lane) * 16);
+                    const v4i A = *reinterpret_cast<const v4i *>(wlb + ((int64_t)(mt * KBL + kb) * 64 + lane) * 16);
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt) {
                         if constexpr (L == 3)
