@@ -75,3 +75,41 @@ def test_every_instance_matches_oracle(ctx, orc, dims, shift):
             assert np.array_equal(cex["new_label"], ref["cex_label"]), name
     finally:
         ibmc.ibmc_set_variant(ctx, m, None)
+
+
+# integer lane-per-point kernel: (first hidden, second hidden or 0, classes),
+# padding to each of its instances (16|32|64, 0|16|32|64), some ragged
+LANE_SHAPES = [(16, 0, 5), (30, 0, 10), (64, 0, 16), (16, 16, 5), (12, 30, 8), (16, 64, 10),
+               (32, 16, 6), (32, 32, 10), (26, 48, 16), (64, 16, 7), (40, 32, 10), (64, 64, 16)]
+
+
+@pytest.mark.parametrize("h1,h2,nc", LANE_SHAPES, ids=[f"lane-{a}-{b}-{c}" for a, b, c in LANE_SHAPES])
+def test_every_lane_instance_matches_oracle(ctx, orc, h1, h2, nc):
+    """The lane kernel forced on each of its instances: the label property
+    and the threshold literal (V halfway between the two largest clean
+    logits), records equal to the oracle's."""
+    from paper_1907_12933_amd import ibmc
+    dims = [30, h1] + ([h2] if h2 else []) + [nc]
+    g = I.rng(500 + 7 * h1 + 3 * h2 + nc)
+    net = I.random_qnet(g, dims, shift=[5] * (len(dims) - 2), wmax=40, bmax=300)
+    x = narrow_image(net, g)
+    D = np.array([-90, -40, 40, 90], np.int16)
+    m = ibmc.Mlp(ctx, net)
+    try:
+        ibmc.ibmc_set_variant(ctx, m, "lane")
+        assert ibmc.ibmc_chosen_variant(ctx, m) == "lane"
+        s, cex, _ = ibmc.ibmc_check_property(ctx, m, x, D, 1, 2)
+        ref = orc.q8_check(net, x, D, 1, 2)
+        pot, _ = orc.q8_forward(net, x)
+        z = np.sort(pot[-nc:])
+        V = int(z[-2] + (z[-1] - z[-2]) // 2)
+        sl, cexl, _ = ibmc.ibmc_check_property(ctx, m, x, D, 1, 2, literal_v=V)
+        refl = orc.q8_check_literal(net, x, D, V, 1, 2)
+    finally:
+        ibmc.ibmc_set_variant(ctx, m, None)
+    print(f"{dims}: {ref['cex_total']} counterexamples, {refl['cex_total']} literal violations", flush=True)
+    assert ref["cex_total"] > 0
+    for got, want in ((cex, ref), (cexl, refl)):
+        assert np.array_equal(got["k"], want["cex_k"]) and np.array_equal(got["rank"], want["cex_rank"])
+        assert np.array_equal(got["new_label"], want["cex_label"])
+    assert list(s["ties"]) == [int(v) for v in ref["ties"]]
