@@ -79,6 +79,10 @@ def test_forward_potentials_exact(ctx, orc):
     (2, [35, 16, 5], 7, 100, 8, 16, 1),
     (3, [64, 70, 33, 10], 5, 60, 8, 64, 50),
     (4, [30, 100, 90, 80, 6], 4, 30, 3, 90, 1),
+    # widths whose 16-row tiles split evenly over the eight waves: one, two
+    # and four tiles per wave (128, 256, 512 units)
+    (5, [40, 128, 256, 10], 6, 24, 6, 64, 50),
+    (6, [40, 512, 128, 10], 6, 24, 6, 64, 50),
 ])
 def test_random_nets_all_criteria(ctx, orc, seed, dims, shift, pairs, maxpix, maxshift, dmin):
     from paper_1907_12933_amd import ibmc
